@@ -1,0 +1,168 @@
+/*
+ * cse.h -- C ABI of libcse, an MI355X (gfx950) engine that runs many
+ * independent randomized common-subexpression-elimination (CSE) processes
+ * over the ternary linear forms of fast matrix-multiplication schemes, after
+ * A. I. Perminov, "Parallel Heuristic Exploration for Additive Complexity
+ * Reduction in Fast Matrix Multiplication" (arXiv 2512.13365).
+ *
+ * Terms.
+ *   system     n_e linear forms over n_x variables with coefficients in
+ *              {-1, 0, 1} (Sec. 3.2.1), given as an int8 row-major matrix,
+ *              rows = forms, columns = variables.  No row may be all zero.
+ *   scheme     the three systems of a scheme (Sec. 3.2): U (forms over the
+ *              entries of A), V (over the entries of B) and W^T (one form per
+ *              entry of C over the products).  Components 0, 1, 2.
+ *   process    one reduction process of Sec. 3.5.1: a strategy, alpha and
+ *              beta, applied to each component independently.
+ *   unit       one component reduced by one process.  Unit results are a
+ *              pure function of (system, run configuration, process index):
+ *              they do not depend on batching or on other jobs.
+ *   program    the substitutions of a unit in order, as int32 triples
+ *              (a, b, s): 1-based variable ids a < b, s = +1 or -1.  The t-th
+ *              triple (t = 0, 1, ...) defines fresh variable n_x + t + 1 as
+ *              x_a + s x_b (Sec. 3.2.1, 3.6).
+ *   cost       additions of a unit: n_f + naive(final forms) (Sec. 3.2.1).
+ *
+ * Conventions.  Every function returns a status (0 = CSE_OK, < 0 = error)
+ * and never aborts or throws across the ABI.  Input arrays are copied; the
+ * caller keeps ownership.  Output arrays are caller-allocated host memory.
+ * A context serves one host thread at a time (no internal locking).
+ * `stream` arguments are hipStream_t values passed as void* (NULL = the
+ * default stream).  Device work is asynchronous until cse_wait or any
+ * cse_get_* call, which block until the job is done.
+ */
+#ifndef CSE_H_
+#define CSE_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSE_OK         0
+#define CSE_EINVAL    (-1)  /* bad shape, entry outside {-1,0,1}, zero row, bad configuration */
+#define CSE_ENOMEM    (-2)  /* device memory or LDS footprint exceeds capacity */
+#define CSE_ERANGE    (-3)  /* caller buffer too small, or a size limit exceeded */
+#define CSE_EHIP      (-4)  /* HIP runtime error; see cse_last_error */
+#define CSE_EBUSY     (-5)  /* job not finished (cse_poll) */
+#define CSE_ENOENT    (-6)  /* unknown scheme or job id */
+#define CSE_ECANCELED (-7)  /* job was cancelled */
+
+/* Strategy ids, the index into cse_run_cfg.weights (Sec. 3.4.1-3.4.3,
+ * 3.5.1).  Greedy-Potential (gp) is reserved: its weight must be 0. */
+#define CSE_STRAT_G   0   /* greedy: highest frequency */
+#define CSE_STRAT_GA  1   /* greedy-alternative: uniform among maximal */
+#define CSE_STRAT_WR  2   /* weighted-random: probability ~ c - 1 */
+#define CSE_STRAT_GR  3   /* greedy-random: ga with prob gr_p, else wr */
+#define CSE_STRAT_GI  4   /* greedy-intersections (Sec. 3.4.2) */
+#define CSE_STRAT_MIX 5   /* per step one of gi/ga/gr/wr by mix_weights */
+#define CSE_STRAT_GP  6   /* reserved */
+
+/* Counting paths for the pair counts of the Analysis step (Algorithm 1).
+ * All paths give identical results. */
+#define CSE_COUNT_AUTO     0
+#define CSE_COUNT_POPCOUNT 1   /* wavefront popcount over column bitsets */
+#define CSE_COUNT_MFMA     2   /* int8 MFMA Gram product for the first count */
+
+typedef struct cse_ctx cse_ctx;
+
+/* Run configuration (Sec. 3.5).  Zero-initialise and set what is needed. */
+typedef struct {
+    uint64_t seed;             /* key of every random draw */
+    uint32_t n_proc;           /* processes; unit results depend on the index */
+    uint32_t weights[7];       /* integer strategy weights, by CSE_STRAT_* */
+    uint32_t mix_weights[4];   /* mix: gi, ga, gr, wr (paper: 8, 4, 2, 1) */
+    uint32_t proc0_greedy;     /* process 0 runs g (Sec. 3.5.1) */
+    uint32_t gr_p_q16;         /* greedy-random: P(ga) in 2^-16 units (<= 65536) */
+    uint32_t step_cap;         /* maximal program length; 0 = none */
+    uint32_t share_every;      /* steps per sharing round; 0 = no sharing */
+    uint32_t share_src_pm;     /* sources: first ceil(N pm/1000) by (cost, process) */
+    uint32_t share_dst_pm;     /* P(an active non-source unit is a target), per mille */
+    uint32_t share_max_rounds; /* at most this many sharing events (<= 1023) */
+    uint32_t iteration;        /* outer iteration (keys per-process draws) */
+    uint32_t count_path;       /* CSE_COUNT_* */
+    uint32_t reserved[3];      /* must be 0 */
+} cse_run_cfg;
+
+/* Library ABI version (this header: 1). */
+int32_t cse_version(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int32_t cse_ctx_create(int32_t device, cse_ctx** out);
+void cse_ctx_destroy(cse_ctx* ctx);
+/* Text of the last error on this context (static storage of the context). */
+const char* cse_last_error(const cse_ctx* ctx);
+
+/* Load one system (Sec. 3.2.1) as a one-component scheme.  A is rows x cols
+ * int8 row-major, entries in {-1, 0, 1}, no zero row; rows <= 512 and
+ * cols + floor((nnz - rows) / 2) < 32768.  Returns CSE_EINVAL otherwise. */
+int32_t cse_system_load(cse_ctx* ctx, const int8_t* A, int32_t rows, int32_t cols,
+                        int32_t* scheme_id);
+
+/* Load a scheme's three systems U (u_rows x u_cols), V and W^T (Sec. 3.2),
+ * with the same rules as cse_system_load for each. */
+int32_t cse_scheme_load(cse_ctx* ctx,
+                        const int8_t* U, int32_t u_rows, int32_t u_cols,
+                        const int8_t* V, int32_t v_rows, int32_t v_cols,
+                        const int8_t* Wt, int32_t w_rows, int32_t w_cols,
+                        int32_t* scheme_id);
+
+/* Shape of a loaded scheme: *n_comp components; info (4 per component):
+ * n_e, n_x, n_fmax (the fresh-variable bound floor((nnz - n_e) / 2)), and
+ * the naive count (Sec. 3.2.1). */
+int32_t cse_scheme_info(cse_ctx* ctx, int32_t scheme_id, int32_t* n_comp, int32_t info[12]);
+int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
+
+/* Launch n_proc processes on every component of a scheme (Algorithm 1 per
+ * unit, strategies of Sec. 3.4, sharing rounds of Sec. 3.5.2 when
+ * share_every > 0).  Asynchronous on `stream`; *job_id receives the job. */
+int32_t cse_launch(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream,
+                   int32_t* job_id);
+
+/* Launch n jobs (scheme_ids[i] with cfgs[i]) whose units share device
+ * launches.  Every unit result equals that of the separate cse_launch. */
+int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs,
+                         int32_t n, void* stream, int32_t* job_ids);
+
+/* *done = 1 when the job's device work has completed, else 0. */
+int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done);
+/* Block until the job is done. */
+int32_t cse_wait(cse_ctx* ctx, int32_t job_id);
+
+/* Per-unit results of component `comp` for processes 0..n-1 (n = n_proc);
+ * any pointer may be NULL.  cost: Sec. 3.2.1 cost; steps: program length;
+ * executed: selection steps run (replays of shared prefixes excluded);
+ * epoch: times the unit restarted from a shared prefix; k0: program length
+ * right after the last restart (0 if none); ops: algorithmic work tally;
+ * strat: the process strategy (CSE_STRAT_*); finish: device wall-clock ticks
+ * from job start until the unit finished. */
+int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n,
+                             int32_t* cost, int32_t* steps, int32_t* executed,
+                             int32_t* epoch, int32_t* k0, int64_t* ops, int32_t* strat,
+                             uint64_t* finish);
+
+/* Programs of all n units of component `comp`: triples is n x cap x 3
+ * int32; entries past a unit's length are zero.  cap must be >= n_fmax. */
+int32_t cse_get_programs(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n,
+                         int32_t* triples, int32_t cap);
+
+/* Program of one unit (proc = -1: the lowest-cost unit, ties to the lower
+ * process index).  triples holds cap x 3 int32; *n_fresh and *cost receive
+ * its length and cost; if cap < length, returns CSE_ERANGE and sets *needed. */
+int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc,
+                        int32_t* triples, int32_t cap, int32_t* n_fresh, int32_t* cost,
+                        int32_t* needed);
+
+/* Timing of a finished job: device ticks from job start to the last unit's
+ * finish, and the tick rate in Hz. */
+int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz);
+
+/* Free a job's device memory. */
+int32_t cse_job_release(cse_ctx* ctx, int32_t job_id);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSE_H_ */

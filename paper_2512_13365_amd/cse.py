@@ -1,0 +1,279 @@
+"""ctypes binding of libcse (include/cse.h): the same entry points, argument
+marshalling only.  Every step of the reduction runs in the library's HIP
+kernels; this module never computes a result itself and raises if the
+built library is missing.
+
+Typical use::
+
+    ctx = cse_ctx_create(0)
+    sid = cse_scheme_load(ctx, U, V, Wt)
+    job = cse_launch(ctx, sid, cse_run_cfg(n_proc=4096, weights={"gi": 1}), stream)
+    res = cse_get_unit_results(ctx, job, comp=0)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcse.so")
+
+STRATEGIES = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
+CSE_COUNT_AUTO, CSE_COUNT_POPCOUNT, CSE_COUNT_MFMA = 0, 1, 2
+
+STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4: "CSE_EHIP",
+          -5: "CSE_EBUSY", -6: "CSE_ENOENT", -7: "CSE_ECANCELED"}
+
+# Every symbol declared in include/cse.h.
+EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
+           "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_launch", "cse_launch_batch",
+           "cse_poll", "cse_wait", "cse_get_unit_results", "cse_get_programs", "cse_get_program",
+           "cse_job_timing", "cse_job_release")
+
+
+class CseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CseRunCfg(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64),
+        ("n_proc", ctypes.c_uint32),
+        ("weights", ctypes.c_uint32 * 7),
+        ("mix_weights", ctypes.c_uint32 * 4),
+        ("proc0_greedy", ctypes.c_uint32),
+        ("gr_p_q16", ctypes.c_uint32),
+        ("step_cap", ctypes.c_uint32),
+        ("share_every", ctypes.c_uint32),
+        ("share_src_pm", ctypes.c_uint32),
+        ("share_dst_pm", ctypes.c_uint32),
+        ("share_max_rounds", ctypes.c_uint32),
+        ("iteration", ctypes.c_uint32),
+        ("count_path", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcse.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcse.so not built at {path}: run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    i32, u32, vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
+    L.cse_version.restype = i32
+    L.cse_ctx_create.argtypes = [i32, P(vp)]
+    L.cse_ctx_create.restype = i32
+    L.cse_ctx_destroy.argtypes = [vp]
+    L.cse_ctx_destroy.restype = None
+    L.cse_last_error.argtypes = [vp]
+    L.cse_last_error.restype = ctypes.c_char_p
+    L.cse_system_load.argtypes = [vp, P(ctypes.c_int8), i32, i32, P(i32)]
+    L.cse_system_load.restype = i32
+    L.cse_scheme_load.argtypes = [vp, P(ctypes.c_int8), i32, i32, P(ctypes.c_int8), i32, i32,
+                                  P(ctypes.c_int8), i32, i32, P(i32)]
+    L.cse_scheme_load.restype = i32
+    L.cse_scheme_info.argtypes = [vp, i32, P(i32), P(i32)]
+    L.cse_scheme_info.restype = i32
+    L.cse_scheme_free.argtypes = [vp, i32]
+    L.cse_scheme_free.restype = i32
+    L.cse_launch.argtypes = [vp, i32, P(CseRunCfg), vp, P(i32)]
+    L.cse_launch.restype = i32
+    L.cse_launch_batch.argtypes = [vp, P(i32), P(CseRunCfg), i32, vp, P(i32)]
+    L.cse_launch_batch.restype = i32
+    L.cse_poll.argtypes = [vp, i32, P(i32)]
+    L.cse_poll.restype = i32
+    L.cse_wait.argtypes = [vp, i32]
+    L.cse_wait.restype = i32
+    L.cse_get_unit_results.argtypes = [vp, i32, i32, i32, P(i32), P(i32), P(i32), P(i32), P(i32),
+                                       P(ctypes.c_int64), P(i32), P(ctypes.c_uint64)]
+    L.cse_get_unit_results.restype = i32
+    L.cse_get_programs.argtypes = [vp, i32, i32, i32, P(i32), i32]
+    L.cse_get_programs.restype = i32
+    L.cse_get_program.argtypes = [vp, i32, i32, i32, P(i32), i32, P(i32), P(i32), P(i32)]
+    L.cse_get_program.restype = i32
+    L.cse_job_timing.argtypes = [vp, i32, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    L.cse_job_timing.restype = i32
+    L.cse_job_release.argtypes = [vp, i32]
+    L.cse_job_release.restype = i32
+    _lib = L
+    return L
+
+
+def _check(ctx, rc):
+    if rc != 0:
+        msg = load_library().cse_last_error(ctx).decode() if ctx else ""
+        raise CseError(rc, msg)
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _i8(A):
+    A = np.ascontiguousarray(A, dtype=np.int8)
+    if A.ndim != 2:
+        raise ValueError("system must be a 2-D matrix")
+    return A
+
+
+def cse_run_cfg(seed=0, n_proc=1, weights=None, mix_weights=(8, 4, 2, 1), proc0_greedy=False,
+                gr_p_q16=49152, step_cap=0, share_every=0, share_src_pm=0, share_dst_pm=0,
+                share_max_rounds=0, iteration=0, count_path=CSE_COUNT_AUTO) -> CseRunCfg:
+    """Build a cse_run_cfg; weights is {strategy name: integer weight}."""
+    cfg = CseRunCfg()
+    cfg.seed = seed
+    cfg.n_proc = n_proc
+    w = [0] * 7
+    for k, v in (weights or {"gi": 1}).items():
+        w[STRATEGIES.index(k)] = int(v)
+    cfg.weights = (ctypes.c_uint32 * 7)(*w)
+    cfg.mix_weights = (ctypes.c_uint32 * 4)(*[int(x) for x in mix_weights])
+    cfg.proc0_greedy = int(bool(proc0_greedy))
+    cfg.gr_p_q16 = gr_p_q16
+    cfg.step_cap = step_cap
+    cfg.share_every = share_every
+    cfg.share_src_pm = share_src_pm
+    cfg.share_dst_pm = share_dst_pm
+    cfg.share_max_rounds = share_max_rounds
+    cfg.iteration = iteration
+    cfg.count_path = count_path
+    return cfg
+
+
+def cse_version() -> int:
+    return int(load_library().cse_version())
+
+
+def cse_ctx_create(device: int = 0):
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(None, L.cse_ctx_create(device, ctypes.byref(h)))
+    return h
+
+
+def cse_ctx_destroy(ctx):
+    load_library().cse_ctx_destroy(ctx)
+
+
+def cse_last_error(ctx) -> str:
+    return load_library().cse_last_error(ctx).decode()
+
+
+def cse_system_load(ctx, A) -> int:
+    A = _i8(A)
+    sid = ctypes.c_int32()
+    _check(ctx, load_library().cse_system_load(ctx, _p(A, ctypes.c_int8), A.shape[0], A.shape[1],
+                                               ctypes.byref(sid)))
+    return sid.value
+
+
+def cse_scheme_load(ctx, U, V, Wt) -> int:
+    U, V, Wt = _i8(U), _i8(V), _i8(Wt)
+    sid = ctypes.c_int32()
+    _check(ctx, load_library().cse_scheme_load(
+        ctx, _p(U, ctypes.c_int8), U.shape[0], U.shape[1], _p(V, ctypes.c_int8), V.shape[0], V.shape[1],
+        _p(Wt, ctypes.c_int8), Wt.shape[0], Wt.shape[1], ctypes.byref(sid)))
+    return sid.value
+
+
+def cse_scheme_info(ctx, scheme_id):
+    """[(n_e, n_x, n_fmax, naive) per component]"""
+    n = ctypes.c_int32()
+    info = (ctypes.c_int32 * 12)()
+    _check(ctx, load_library().cse_scheme_info(ctx, scheme_id, ctypes.byref(n), info))
+    return [tuple(info[4 * c:4 * c + 4]) for c in range(n.value)]
+
+
+def cse_scheme_free(ctx, scheme_id):
+    _check(ctx, load_library().cse_scheme_free(ctx, scheme_id))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def cse_launch(ctx, scheme_id, cfg: CseRunCfg, stream=None) -> int:
+    job = ctypes.c_int32()
+    _check(ctx, load_library().cse_launch(ctx, scheme_id, ctypes.byref(cfg), _stream_ptr(stream),
+                                          ctypes.byref(job)))
+    return job.value
+
+
+def cse_launch_batch(ctx, scheme_ids, cfgs, stream=None):
+    n = len(scheme_ids)
+    ids = np.ascontiguousarray(scheme_ids, dtype=np.int32)
+    arr = (CseRunCfg * n)(*cfgs)
+    jobs = np.zeros(n, np.int32)
+    _check(ctx, load_library().cse_launch_batch(ctx, _p(ids, ctypes.c_int32), arr, n, _stream_ptr(stream),
+                                                _p(jobs, ctypes.c_int32)))
+    return [int(j) for j in jobs]
+
+
+def cse_poll(ctx, job_id) -> bool:
+    done = ctypes.c_int32()
+    _check(ctx, load_library().cse_poll(ctx, job_id, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def cse_wait(ctx, job_id):
+    _check(ctx, load_library().cse_wait(ctx, job_id))
+
+
+def cse_get_unit_results(ctx, job_id, comp, n_proc):
+    out = {k: np.zeros(n_proc, np.int32) for k in ("cost", "steps", "executed", "epoch", "k0", "strat")}
+    out["ops"] = np.zeros(n_proc, np.int64)
+    out["finish"] = np.zeros(n_proc, np.uint64)
+    i32 = ctypes.c_int32
+    _check(ctx, load_library().cse_get_unit_results(
+        ctx, job_id, comp, n_proc, _p(out["cost"], i32), _p(out["steps"], i32), _p(out["executed"], i32),
+        _p(out["epoch"], i32), _p(out["k0"], i32), _p(out["ops"], ctypes.c_int64), _p(out["strat"], i32),
+        _p(out["finish"], ctypes.c_uint64)))
+    return out
+
+
+def cse_get_programs(ctx, job_id, comp, n_proc, cap):
+    tri = np.zeros((n_proc, max(1, cap), 3), np.int32)
+    _check(ctx, load_library().cse_get_programs(ctx, job_id, comp, n_proc, _p(tri, ctypes.c_int32),
+                                                max(1, cap)))
+    return tri
+
+
+def cse_get_program(ctx, job_id, comp, proc=-1, cap=None):
+    L = load_library()
+    nf, cost, need = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    if cap is None:
+        rc = L.cse_get_program(ctx, job_id, comp, proc, None, 0, ctypes.byref(nf), ctypes.byref(cost),
+                               ctypes.byref(need))
+        if rc not in (0, -3):
+            _check(ctx, rc)
+        cap = need.value
+    tri = np.zeros((max(1, cap), 3), np.int32)
+    _check(ctx, L.cse_get_program(ctx, job_id, comp, proc, _p(tri, ctypes.c_int32), cap, ctypes.byref(nf),
+                                  ctypes.byref(cost), ctypes.byref(need)))
+    return tri[:nf.value], cost.value
+
+
+def cse_job_timing(ctx, job_id):
+    """(ticks from job start to the last unit's finish, tick rate in Hz)"""
+    t, hz = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, load_library().cse_job_timing(ctx, job_id, ctypes.byref(t), ctypes.byref(hz)))
+    return t.value, hz.value
+
+
+def cse_job_release(ctx, job_id):
+    _check(ctx, load_library().cse_job_release(ctx, job_id))

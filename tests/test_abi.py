@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every symbol include/cse.h declares
+(no GPU needed), and the binding refuses to run without it."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cse.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cse_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    assert "cse_launch" in names and "cse_get_program" in names and "cse_ctx_create" in names
+    from paper_2512_13365_amd import cse
+    assert sorted(cse.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2512_13365_amd import cse
+    if not os.path.exists(cse.LIB_PATH):
+        pytest.skip("libcse.so not built")
+    lib = ctypes.CDLL(cse.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.cse_version() == 1
+
+
+def test_cfg_struct_layout_matches_header(tmp_path):
+    """The binding's cse_run_cfg has the C compiler's size and offsets."""
+    import subprocess
+
+    from paper_2512_13365_amd import cse
+    fields = [f[0] for f in cse.CseRunCfg._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cse.h"\nint main(void){\n'
+                   '  printf("%zu\\n", sizeof(cse_run_cfg));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(cse_run_cfg, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cse.CseRunCfg) == 104
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cse.CseRunCfg, f).offset == off, f
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2512_13365_amd import cse
+    saved = cse._lib
+    cse._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            cse.load_library(str(tmp_path / "missing.so"))
+    finally:
+        cse._lib = saved

@@ -1,0 +1,169 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every unit is compared element by element: cost, program length, selection
+steps, restarts, the algorithmic work tally, the strategy, and the full
+program.  Integer work, so the bar is bit-exact.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from cse_helpers import check_program, read_golden
+from paper_2512_13365_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+ALL_W = {"g": 1, "ga": 2, "wr": 2, "gr": 2, "gi": 4, "mix": 2}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_13365_amd import cse
+    cse.load_library()
+    ctx = cse.cse_ctx_create(0)
+    yield cse, ctx, torch
+    cse.cse_ctx_destroy(ctx)
+
+
+def run_gpu(gpu, systems, kw):
+    cse, ctx, torch = gpu
+    if len(systems) == 3:
+        sid = cse.cse_scheme_load(ctx, *systems)
+    else:
+        sid = cse.cse_system_load(ctx, systems[0])
+    info = cse.cse_scheme_info(ctx, sid)
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    cse.cse_wait(ctx, job)
+    out = []
+    for c in range(len(systems)):
+        r = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+        r["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+        out.append(r)
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    return out
+
+
+def compare(oracle, systems, kw, label, procs=None):
+    ocfg = oracle.make_cfg(**kw)
+    res = []
+    for c, A in enumerate(systems):
+        ref = oracle.run_pool(A, ocfg, comp=c, procs=procs, n_threads=THREADS)
+        res.append(ref)
+    return res
+
+
+def assert_same(got, ref, label):
+    for k in ("cost", "steps", "executed", "epoch", "k0", "ops", "strat"):
+        g, r = np.asarray(got[k]), np.asarray(ref[k])
+        bad = np.flatnonzero(g != r)
+        assert bad.size == 0, f"{label}: {k} differs at units {bad[:8]} gpu={g[bad[:8]]} oracle={r[bad[:8]]}"
+    assert got["prog"].shape == ref["prog"].shape
+    bad = np.flatnonzero((got["prog"] != ref["prog"]).any(axis=(1, 2)))
+    assert bad.size == 0, f"{label}: programs differ at units {bad[:8]}"
+
+
+def check_workload(gpu, oracle, systems, kw, label):
+    say(f"[gpu] {label}: shapes {[A.shape for A in systems]} n_proc {kw['n_proc']}")
+    got = run_gpu(gpu, systems, kw)
+    ref = compare(oracle, systems, kw, label)
+    for c in range(len(systems)):
+        assert_same(got[c], ref[c], f"{label} comp {c}")
+    return got, ref
+
+
+def test_tiny_2x2x2_every_unit(gpu, oracle):
+    wl = workloads.tiny_2x2x2()
+    check_workload(gpu, oracle, wl.schemes[0].systems, wl.runs[0].as_kwargs(), "tiny-2x2x2")
+
+
+def test_plain_4x4x4_every_unit(gpu, oracle):
+    """The benchmarked workload at full size: 4096 processes x 3 components."""
+    wl = workloads.plain_4x4x4()
+    got, ref = check_workload(gpu, oracle, wl.schemes[0].systems, wl.runs[0].as_kwargs(), "plain-4x4x4")
+    sc = wl.schemes[0]
+    for c, A in enumerate(sc.systems):
+        best = int(np.argmin(got[c]["cost"]))
+        check_program(A, got[c]["prog"][best, :got[c]["steps"][best]], int(got[c]["cost"][best]))
+
+
+@pytest.mark.parametrize("rows,cols,p,hi", [
+    (2, 6, 0.6, None), (9, 5, 0.5, None), (63, 20, 0.25, 8), (64, 20, 0.25, 8), (65, 24, 0.25, 8),
+    (127, 16, 0.3, 8), (130, 30, 0.2, 10), (200, 40, 0.12, 12), (512, 10, 0.4, 6), (20, 120, 0.1, 30)])
+def test_ragged_shapes_all_strategies(gpu, oracle, rows, cols, p, hi):
+    """Row counts across 1..8 bitset words with ragged tails, every strategy."""
+    A = workloads.random_system(rows * 1000 + cols, rows, cols, p, 1, hi)
+    kw = dict(seed=rows + cols, n_proc=96, weights=dict(ALL_W), proc0_greedy=True)
+    check_workload(gpu, oracle, [A], kw, f"system {rows}x{cols}")
+
+
+def test_step_cap_and_seeds(gpu, oracle):
+    A = workloads.random_system(77, 49, 16, 0.3, 1, 8)
+    for seed, cap in ((0, 1), (1, 5), (2 ** 40 + 3, 17)):
+        kw = dict(seed=seed, n_proc=128, weights=dict(ALL_W), step_cap=cap)
+        check_workload(gpu, oracle, [A], kw, f"cap {cap} seed {seed}")
+
+
+def test_degenerate_systems(gpu, oracle):
+    """No repeated pair (Strassen, Sec. 2.2), one row, identical rows."""
+    g = read_golden("strassen_2x2x2.txt")
+    S = [np.array([[int(x) for x in r] for r in g[k]], np.int8) for k in ("U", "V", "Wt")]
+    got, _ = check_workload(gpu, oracle, S, dict(seed=1, n_proc=64, weights=dict(ALL_W)), "strassen")
+    assert sum(int(r["cost"][0]) for r in got) == 18 and all((r["steps"] == 0).all() for r in got)
+    one = np.array([[1, -1, 1, 1, -1, 0, 1]], np.int8)
+    check_workload(gpu, oracle, [one], dict(seed=2, n_proc=8, weights=dict(ALL_W)), "one row")
+    row = np.array([1, -1, 1, 1, -1, 1, 1, -1, 1, 1], np.int8)
+    same = np.stack([row, -row, row, row, -row, row])
+    got, _ = check_workload(gpu, oracle, [same], dict(seed=3, n_proc=64, weights=dict(ALL_W)), "equal rows")
+    assert (got[0]["cost"] == 9).all()
+
+
+def test_sharing_rounds_small_pool(gpu, oracle):
+    """Sharing (Sec. 3.5.2) on the 6x6x6 shape with a 256-process pool."""
+    wl = workloads.plain_6x6x6(n_proc=256)
+    got, _ = check_workload(gpu, oracle, wl.schemes[0].systems, wl.runs[0].as_kwargs(), "share-6x6x6-256")
+    assert max(int(r["epoch"].max()) for r in got) > 0
+
+
+def test_sharing_dense_targets(gpu, oracle):
+    A = workloads.random_system(91, 60, 18, 0.3, 1, 8)
+    kw = dict(seed=5, n_proc=200, weights=dict(ALL_W), proc0_greedy=True, share_every=3,
+              share_src_pm=50, share_dst_pm=400, share_max_rounds=6)
+    got, _ = check_workload(gpu, oracle, [A], kw, "share-dense")
+    assert got[0]["epoch"].max() > 1
+
+
+def test_invalid_inputs_rejected(gpu):
+    cse, ctx, torch = gpu
+    bad = [np.array([[1, 0], [0, 0]], np.int8), np.array([[1, 2]], np.int8), np.zeros((0, 3), np.int8),
+           np.ones((513, 2), np.int8)]
+    for A in bad:
+        with pytest.raises(cse.CseError) as e:
+            cse.cse_system_load(ctx, A)
+        assert e.value.status == -1
+    sid = cse.cse_system_load(ctx, np.array([[1, 1], [1, 1]], np.int8))
+    with pytest.raises(cse.CseError):
+        cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=4, weights={"gp": 1}))
+    with pytest.raises(cse.CseError):
+        cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=0))
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_launch(ctx, 9999, cse.cse_run_cfg(n_proc=4))
+    assert e.value.status == -6
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=4))
+    with pytest.raises(cse.CseError):
+        cse.cse_get_unit_results(ctx, job, 1, 4)
+    tri, cost = cse.cse_get_program(ctx, job, 0, -1)
+    assert cost == 1 and tri.tolist() == [[1, 2, 1]]
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
