@@ -112,6 +112,7 @@ int32_t cse_scheme_load(cse_ctx* ctx,
  * n_e, n_x, n_fmax (the fresh-variable bound floor((nnz - n_e) / 2)), and
  * the naive count (Sec. 3.2.1). */
 int32_t cse_scheme_info(cse_ctx* ctx, int32_t scheme_id, int32_t* n_comp, int32_t info[12]);
+/* Free a scheme; CSE_EBUSY while a job of it has not been released. */
 int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
 
 /* Launch n_proc processes on every component of a scheme (Algorithm 1 per
@@ -120,10 +121,21 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
 int32_t cse_launch(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream,
                    int32_t* job_id);
 
-/* Launch n jobs (scheme_ids[i] with cfgs[i]) whose units share device
- * launches.  Every unit result equals that of the separate cse_launch. */
+/* Launch n jobs (scheme_ids[i] with cfgs[i]) as one batch: the units of
+ * all their components share device launches (one launch per row-word
+ * count), and sharing rounds, if any, advance all jobs together.  Every unit
+ * result equals that of the separate cse_launch of its job.  Unit finish
+ * times count from the batch start. */
 int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs,
                          int32_t n, void* stream, int32_t* job_ids);
+
+/* Run a job again on its own device buffers, optionally with a new
+ * configuration (NULL = the same one; n_proc and whether it shares must not
+ * change).  A job launched in a batch reruns the whole batch, and then cfg
+ * must be NULL.  Results of the earlier run are overwritten.  No device
+ * memory is allocated, so the launches can be timed on `stream` without
+ * allocation in between; on the same stream the call does not block. */
+int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void* stream);
 
 /* *done = 1 when the job's device work has completed, else 0. */
 int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done);
@@ -158,7 +170,7 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
  * finish, and the tick rate in Hz. */
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz);
 
-/* Free a job's device memory. */
+/* Free a job's device memory (the other jobs of its batch keep theirs). */
 int32_t cse_job_release(cse_ctx* ctx, int32_t job_id);
 
 #ifdef __cplusplus

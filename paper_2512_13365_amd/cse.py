@@ -29,7 +29,7 @@ STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4:
 # Every symbol declared in include/cse.h.
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
            "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_launch", "cse_launch_batch",
-           "cse_poll", "cse_wait", "cse_get_unit_results", "cse_get_programs", "cse_get_program",
+           "cse_relaunch", "cse_poll", "cse_wait", "cse_get_unit_results", "cse_get_programs", "cse_get_program",
            "cse_job_timing", "cse_job_release")
 
 
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     L.cse_launch.restype = i32
     L.cse_launch_batch.argtypes = [vp, P(i32), P(CseRunCfg), i32, vp, P(i32)]
     L.cse_launch_batch.restype = i32
+    L.cse_relaunch.argtypes = [vp, i32, P(CseRunCfg), vp]
+    L.cse_relaunch.restype = i32
     L.cse_poll.argtypes = [vp, i32, P(i32)]
     L.cse_poll.restype = i32
     L.cse_wait.argtypes = [vp, i32]
@@ -222,6 +224,11 @@ def cse_launch_batch(ctx, scheme_ids, cfgs, stream=None):
     _check(ctx, load_library().cse_launch_batch(ctx, _p(ids, ctypes.c_int32), arr, n, _stream_ptr(stream),
                                                 _p(jobs, ctypes.c_int32)))
     return [int(j) for j in jobs]
+
+
+def cse_relaunch(ctx, job_id, cfg: CseRunCfg | None = None, stream=None):
+    _check(ctx, load_library().cse_relaunch(ctx, job_id, ctypes.byref(cfg) if cfg is not None else None,
+                                            _stream_ptr(stream)))
 
 
 def cse_poll(ctx, job_id) -> bool:

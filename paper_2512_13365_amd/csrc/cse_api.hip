@@ -1,10 +1,14 @@
 // cse_api.hip -- host runtime of libcse: the C ABI declared in include/cse.h.
 //
-// A context owns loaded schemes (input systems as column bitsets in HBM) and
-// jobs (per-unit state and programs in HBM).  A job launches, per component,
-// one workgroup per process; with sharing rounds (Sec. 3.5.2) the host
-// alternates step launches of at most share_every steps with the sharing
-// kernels until no unit of the job is active.
+// A context owns loaded schemes (input systems as column bitsets in HBM),
+// jobs (per-unit state and programs of one scheme run) and batches (the
+// jobs launched together).  Every batch is executed by launch groups: one
+// step-kernel launch per row-word count W covering the units of all its
+// jobs' components, described by a segment table in device memory.  With
+// sharing (Sec. 3.5.2) the host runs rounds: every group advances its units
+// by at most share_every steps, each component pool ranks its units and
+// copies prefixes, and the host reads the number of active units per pool
+// until none is left.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,11 +25,12 @@
 
 namespace {
 
-constexpr int kMaxRows = 512;   // W <= 8 row words
-constexpr int kMaxVars = 32767; // 15-bit variable ids
+constexpr int kMaxRows = 512;          // W <= 8 row words
+constexpr int kMaxVars = 32767;        // 15-bit variable ids
+constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB of LDS per unit
 
 struct DevComp {
-    int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0;
+    int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0;
     long long occ0 = 0;
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
@@ -38,19 +43,46 @@ struct SchemeRec {
 
 struct CompJob {
     csek::UnitState st{};
-    void* block = nullptr;     // one allocation for all per-unit arrays
+    void* block = nullptr;  // one allocation for all per-unit arrays
 };
 
 struct JobRec {
     int scheme = -1;
     cse_run_cfg cfg{};
-    hipStream_t stream = nullptr;
     int n_comp = 0;
     CompJob cj[3];
-    unsigned long long* d_t0 = nullptr;
-    int* d_err = nullptr;
+    int batch = -1;
+};
+
+struct LaunchGroup {
+    int W = 0;
+    uint32_t n_grid = 0;
+    size_t lds = 0;
+    int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
+};
+
+struct Pool {  // the units of one component of one job
+    int job = 0, comp = 0;
+    uint32_t n = 0, n_src = 0;
+    bool shares = false;
+    size_t scratch_off = 0;  // bytes into the batch's sharing scratch
+};
+
+struct BatchRec {
+    std::vector<int> jobs;
+    std::vector<csek::Segment> segs;  // host copy of the segment table
+    csek::Segment* d_segs = nullptr;
+    std::vector<LaunchGroup> groups;
+    std::vector<Pool> pools;
+    bool sharing = false;
+    hipStream_t stream = nullptr;
     hipEvent_t ev_done = nullptr;
-    bool finished = false;
+    bool finished = true;
+    int* d_err = nullptr;
+    unsigned long long* d_t0 = nullptr;
+    int32_t* d_share = nullptr;   // sharing scratch of all pools
+    int32_t* d_counts = nullptr;  // active units per pool
+    int32_t* h_counts = nullptr;  // pinned copy
 };
 
 }  // namespace
@@ -60,8 +92,8 @@ struct cse_ctx {
     std::string err;
     std::map<int, SchemeRec> schemes;
     std::map<int, JobRec> jobs;
-    int next_scheme = 1;
-    int next_job = 1;
+    std::map<int, BatchRec> batches;
+    int next_scheme = 1, next_job = 1, next_batch = 1;
     size_t lds_max = 65536;
     uint64_t tick_hz = 100000000ull;
 };
@@ -80,15 +112,14 @@ int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(ctx, expr)                                                                      \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
+#define HIP_TRY(ctx, expr)                                                                          \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
         if (e_ != hipSuccess) return fail((ctx), CSE_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 size_t lds_bytes(const DevComp& c) {
-    const size_t n_vmax = (size_t)c.n_x + c.n_fmax;
-    return 2 * n_vmax * c.W * 8 + (size_t)c.m_cap * 8 + n_vmax * 4 + 16;
+    return csek::lds_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words).bytes;
 }
 
 int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
@@ -111,8 +142,8 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.n_e = rows;
     c.n_x = cols;
     // Each substitution removes c >= 2 nonzeros and no row empties, so at
-    // most floor((nnz - n_e) / 2) fresh variables; candidates each use at
-    // least two of the (never growing) pair occurrences.
+    // most floor((nnz - n_e) / 2) fresh variables; every candidate uses at
+    // least two of the pair occurrences, whose number never grows.
     c.n_fmax = (int)((nnz - rows) / 2);
     if ((long long)cols + c.n_fmax > kMaxVars)
         return fail(ctx, CSE_EINVAL, "variables %lld exceed %d", (long long)cols + c.n_fmax, kMaxVars);
@@ -120,6 +151,10 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.occ0 = occ;
     c.m_cap = (int)std::max<long long>(1, occ / 2);
     c.naive0 = (int)naive;
+    const int n_vmax = cols + c.n_fmax;
+    c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
+    const long long full_masks = (long long)n_vmax * ((c.m_cap + 63) / 64);
+    c.m_words = (int)std::min<long long>(full_masks, kMaskBudgetWords);
     std::vector<uint64_t> P((size_t)cols * c.W, 0), N((size_t)cols * c.W, 0);
     for (int i = 0; i < rows; ++i)
         for (int j = 0; j < cols; ++j) {
@@ -142,6 +177,8 @@ void free_component(DevComp& c) {
     c.d_P = c.d_N = nullptr;
 }
 
+bool shares(const cse_run_cfg& c) { return c.share_every > 0 && c.share_src_pm > 0 && c.share_max_rounds > 0; }
+
 int validate_cfg(cse_ctx* ctx, const cse_run_cfg* cfg) {
     if (!cfg) return fail(ctx, CSE_EINVAL, "null configuration");
     if (cfg->n_proc < 1 || cfg->n_proc > (1u << 24)) return fail(ctx, CSE_EINVAL, "n_proc %u out of range", cfg->n_proc);
@@ -155,13 +192,14 @@ int validate_cfg(cse_ctx* ctx, const cse_run_cfg* cfg) {
         return fail(ctx, CSE_EINVAL, "mix weights must sum to 1..2^32-1");
     if (cfg->gr_p_q16 > 65536) return fail(ctx, CSE_EINVAL, "gr_p_q16 > 65536");
     if (cfg->share_max_rounds > 1023) return fail(ctx, CSE_EINVAL, "share_max_rounds > 1023");
+    if (cfg->share_every > 65535) return fail(ctx, CSE_EINVAL, "share_every > 65535");
     if (cfg->share_src_pm > 1000 || cfg->share_dst_pm > 1000) return fail(ctx, CSE_EINVAL, "per mille > 1000");
     if (cfg->count_path > CSE_COUNT_MFMA) return fail(ctx, CSE_EINVAL, "unknown count path");
     if (cfg->reserved[0] || cfg->reserved[1] || cfg->reserved[2]) return fail(ctx, CSE_EINVAL, "reserved fields must be 0");
     return CSE_OK;
 }
 
-csek::RunArgs run_args(const cse_run_cfg& cfg, int budget) {
+csek::RunArgs run_args(const cse_run_cfg& cfg) {
     csek::RunArgs R{};
     R.seed = cfg.seed;
     for (int i = 0; i < 7; ++i) R.weights[i] = cfg.weights[i];
@@ -170,7 +208,7 @@ csek::RunArgs run_args(const cse_run_cfg& cfg, int budget) {
     R.gr_p_q16 = cfg.gr_p_q16;
     R.step_cap = cfg.step_cap;
     R.iteration = cfg.iteration;
-    R.budget = budget;
+    R.budget = shares(cfg) ? (int)cfg.share_every : -1;
     R.n_units = cfg.n_proc;
     return R;
 }
@@ -186,39 +224,12 @@ csek::CompArgs comp_args(const DevComp& c, int comp) {
     C.naive0 = c.naive0;
     C.comp = (uint32_t)comp;
     C.prog_stride = std::max(1, c.n_fmax);
+    C.newc_cap = c.newc_cap;
+    C.m_words = c.m_words;
     return C;
 }
 
-template <int W>
-int launch_step_w(cse_ctx* ctx, const DevComp& c, const csek::CompArgs& C, const csek::RunArgs& R,
-                  const csek::UnitState& S, int* d_err, hipStream_t s) {
-    const size_t lds = lds_bytes(c);
-    if (lds > ctx->lds_max) return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", lds, ctx->lds_max);
-    if (lds > 65536) HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(csek::step_kernel<W>, dim3(R.n_units), dim3(csek::kWave), lds, s, C, R, S, d_err);
-    HIP_TRY(ctx, hipGetLastError());
-    return CSE_OK;
-}
-
-int launch_step(cse_ctx* ctx, const DevComp& c, int comp, const cse_run_cfg& cfg, int budget,
-                const csek::UnitState& S, int* d_err, hipStream_t s) {
-    const csek::CompArgs C = comp_args(c, comp);
-    const csek::RunArgs R = run_args(cfg, budget);
-    switch (c.W) {
-    case 1: return launch_step_w<1>(ctx, c, C, R, S, d_err, s);
-    case 2: return launch_step_w<2>(ctx, c, C, R, S, d_err, s);
-    case 3: return launch_step_w<3>(ctx, c, C, R, S, d_err, s);
-    case 4: return launch_step_w<4>(ctx, c, C, R, S, d_err, s);
-    case 5: return launch_step_w<5>(ctx, c, C, R, S, d_err, s);
-    case 6: return launch_step_w<6>(ctx, c, C, R, S, d_err, s);
-    case 7: return launch_step_w<7>(ctx, c, C, R, S, d_err, s);
-    case 8: return launch_step_w<8>(ctx, c, C, R, S, d_err, s);
-    default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", c.W);
-    }
-}
-
-int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, unsigned long long* d_t0, CompJob* cj) {
+int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
     const size_t i32 = (size_t)n * 4;
     const size_t u64 = (size_t)n * 8;
@@ -238,103 +249,230 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, unsigned long lon
     S.k0 = (int32_t*)take(i32);
     S.active = (int32_t*)take(i32);
     S.strat = (int32_t*)take(i32);
-    S.t0 = d_t0;
     return CSE_OK;
 }
 
-JobRec* find_job(cse_ctx* ctx, int id) {
-    auto it = ctx->jobs.find(id);
-    return it == ctx->jobs.end() ? nullptr : &it->second;
+void free_batch_device(BatchRec& B) {
+    if (B.d_segs) (void)hipFree(B.d_segs);
+    if (B.d_err) (void)hipFree(B.d_err);
+    if (B.d_t0) (void)hipFree(B.d_t0);
+    if (B.d_share) (void)hipFree(B.d_share);
+    if (B.d_counts) (void)hipFree(B.d_counts);
+    if (B.h_counts) (void)hipHostFree(B.h_counts);
+    if (B.ev_done) (void)hipEventDestroy(B.ev_done);
+    B.d_segs = nullptr;
+    B.d_err = nullptr;
+    B.d_t0 = nullptr;
+    B.d_share = nullptr;
+    B.d_counts = nullptr;
+    B.h_counts = nullptr;
+    B.ev_done = nullptr;
 }
 
-int check_err(cse_ctx* ctx, JobRec& J) {
+void free_job_device(JobRec& J) {
+    for (int c = 0; c < J.n_comp; ++c) {
+        if (J.cj[c].block) (void)hipFree(J.cj[c].block);
+        J.cj[c].block = nullptr;
+    }
+}
+
+// Segment table and launch groups of a batch: the components of all its
+// jobs, grouped by row-word count W (the kernel is specialised on W).
+void build_segments(cse_ctx* ctx, BatchRec& B) {
+    B.segs.clear();
+    B.groups.clear();
+    for (int W = 1; W <= 8; ++W) {
+        LaunchGroup G;
+        G.W = W;
+        G.seg_begin = (int)B.segs.size();
+        uint32_t unit = 0;
+        for (int jid : B.jobs) {
+            JobRec& J = ctx->jobs[jid];
+            const SchemeRec& sc = ctx->schemes[J.scheme];
+            for (int c = 0; c < J.n_comp; ++c) {
+                const DevComp& dc = sc.comp[c];
+                if (dc.W != W) continue;
+                csek::Segment s{};
+                s.C = comp_args(dc, c);
+                s.R = run_args(J.cfg);
+                s.S = J.cj[c].st;
+                s.S.t0 = B.d_t0;
+                s.unit_begin = unit;
+                unit += J.cfg.n_proc;
+                G.lds = std::max(G.lds, lds_bytes(dc));
+                B.segs.push_back(s);
+            }
+        }
+        G.n_segs = (int)B.segs.size() - G.seg_begin;
+        G.n_grid = unit;
+        if (G.n_segs) B.groups.push_back(G);
+    }
+}
+
+template <int W>
+int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+    if (G.lds > ctx->lds_max)
+        return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
+    if (G.lds > 65536)
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds));
+    hipLaunchKernelGGL(csek::step_kernel<W>, dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+                       d_segs + G.seg_begin, G.n_segs, G.n_grid, d_err);
+    HIP_TRY(ctx, hipGetLastError());
+    return CSE_OK;
+}
+
+int launch_group(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+    switch (G.W) {
+    case 1: return launch_group_w<1>(ctx, G, d_segs, d_err, s);
+    case 2: return launch_group_w<2>(ctx, G, d_segs, d_err, s);
+    case 3: return launch_group_w<3>(ctx, G, d_segs, d_err, s);
+    case 4: return launch_group_w<4>(ctx, G, d_segs, d_err, s);
+    case 5: return launch_group_w<5>(ctx, G, d_segs, d_err, s);
+    case 6: return launch_group_w<6>(ctx, G, d_segs, d_err, s);
+    case 7: return launch_group_w<7>(ctx, G, d_segs, d_err, s);
+    case 8: return launch_group_w<8>(ctx, G, d_segs, d_err, s);
+    default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
+    }
+}
+
+int check_err(cse_ctx* ctx, BatchRec& B) {
     int herr = 0;
-    HIP_TRY(ctx, hipMemcpy(&herr, J.d_err, sizeof herr, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&herr, B.d_err, sizeof herr, hipMemcpyDeviceToHost));
     if (herr) return fail(ctx, CSE_EHIP, "device consistency check failed (flags 0x%x)", herr);
     return CSE_OK;
 }
 
-int wait_job(cse_ctx* ctx, JobRec& J) {
-    if (!J.finished) {
-        HIP_TRY(ctx, hipEventSynchronize(J.ev_done));
-        J.finished = true;
-        return check_err(ctx, J);
+int wait_batch(cse_ctx* ctx, BatchRec& B) {
+    if (!B.finished) {
+        HIP_TRY(ctx, hipEventSynchronize(B.ev_done));
+        B.finished = true;
+        return check_err(ctx, B);
     }
     return CSE_OK;
 }
 
-// Sharing rounds (Sec. 3.5.2): every component advances by at most
-// share_every steps per round, then each component pool runs one sharing
-// event; the host reads the number of still-active units after each round
-// and stops when none is left.  After share_max_rounds events the remaining
-// units run to completion without sharing.
-int run_sharing_rounds(cse_ctx* ctx, JobRec& J, const SchemeRec& sc) {
-    const cse_run_cfg& cfg = J.cfg;
-    const uint32_t n = cfg.n_proc;
-    uint32_t n_src = (uint32_t)(((unsigned long long)n * cfg.share_src_pm + 999) / 1000);
-    n_src = std::max(1u, std::min(n_src, n));
-    int32_t* h_active = nullptr;
-    int32_t* d_scratch = nullptr;
-    const size_t per = csek::share_scratch_bytes(n);
-    HIP_TRY(ctx, hipHostMalloc((void**)&h_active, 64 * sizeof(int32_t), hipHostMallocDefault));
-    if (hipMalloc((void**)&d_scratch, per * J.n_comp) != hipSuccess) {
-        (void)hipHostFree(h_active);
-        return fail(ctx, CSE_ENOMEM, "sharing scratch of %zu B", per * J.n_comp);
-    }
-    bool live[3] = {true, true, true};
-    int rc = CSE_OK;
-    const dim3 blk(256), grd((n + 255) / 256);
-    for (uint32_t r = 0; rc == CSE_OK; ++r) {
-        const bool last = r >= cfg.share_max_rounds;
-        for (int c = 0; c < J.n_comp && rc == CSE_OK; ++c)
-            if (live[c]) rc = launch_step(ctx, sc.comp[c], c, cfg, last ? -1 : (int)cfg.share_every,
-                                          J.cj[c].st, J.d_err, J.stream);
-        if (rc || last) break;
-        bool any = false;
-        for (int c = 0; c < J.n_comp; ++c) {
-            if (!live[c]) continue;
-            csek::ShareScratch ss = csek::share_scratch(
-                (int32_t*)((char*)d_scratch + per * c), n);
-            hipLaunchKernelGGL(csek::share_clear_kernel, dim3(1), dim3(64), 0, J.stream, ss);
-            hipLaunchKernelGGL(csek::share_rank_kernel, grd, blk, 0, J.stream, J.cj[c].st, n, n_src, ss);
-            hipLaunchKernelGGL(csek::share_target_kernel, grd, blk, 0, J.stream, J.cj[c].st, n, n_src,
-                               sc.comp[c].n_fmax, (uint32_t)c, cfg.seed, cfg.share_dst_pm, r, ss);
-            if (hipGetLastError() != hipSuccess) { rc = fail(ctx, CSE_EHIP, "sharing launch failed"); break; }
-            if (hipMemcpyAsync(h_active + c, ss.counter, sizeof(int32_t), hipMemcpyDeviceToHost, J.stream)
-                != hipSuccess) { rc = fail(ctx, CSE_EHIP, "active count copy failed"); break; }
-            any = true;
-        }
-        if (rc || !any) break;
-        if (hipStreamSynchronize(J.stream) != hipSuccess) { rc = fail(ctx, CSE_EHIP, "round sync failed"); break; }
-        bool more = false;
-        for (int c = 0; c < J.n_comp; ++c) {
-            if (live[c] && h_active[c] == 0) live[c] = false;
-            more |= live[c];
-        }
-        if (!more) break;
-    }
-    (void)hipStreamSynchronize(J.stream);
-    (void)hipFree(d_scratch);
-    (void)hipHostFree(h_active);
-    return rc;
+BatchRec* batch_of(cse_ctx* ctx, int job_id, JobRec** job = nullptr) {
+    auto it = ctx->jobs.find(job_id);
+    if (it == ctx->jobs.end()) return nullptr;
+    if (job) *job = &it->second;
+    auto bt = ctx->batches.find(it->second.batch);
+    return bt == ctx->batches.end() ? nullptr : &bt->second;
 }
 
-// Enqueue every launch of one job on its stream.
-int run_job(cse_ctx* ctx, JobRec& J, const SchemeRec& sc) {
-    const cse_run_cfg& cfg = J.cfg;
-    const uint32_t n = cfg.n_proc;
-    for (int c = 0; c < J.n_comp; ++c) {
-        hipLaunchKernelGGL(csek::init_units_kernel, dim3((n + 255) / 256), dim3(256), 0, J.stream,
-                           J.cj[c].st, n, c == 0 ? 1 : 0);
+// Sharing rounds (Sec. 3.5.2): every group advances its active units by at
+// most share_every steps; each sharing pool below its round limit ranks its
+// units and copies prefixes into targets; the host then reads the number of
+// still-active units per pool and stops when none is left.  Pools past
+// share_max_rounds keep stepping without sharing, which is the same as
+// running to completion.
+int run_rounds(cse_ctx* ctx, BatchRec& B) {
+    const int n_pools = (int)B.pools.size();
+    for (uint32_t r = 0;; ++r) {
+        for (const LaunchGroup& G : B.groups) {
+            int rc = launch_group(ctx, G, B.d_segs, B.d_err, B.stream);
+            if (rc) return rc;
+        }
+        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), dim3(256), 0, B.stream,
+                           B.d_counts, n_pools, 0);
+        for (int p = 0; p < n_pools; ++p) {
+            const Pool& P = B.pools[p];
+            JobRec& J = ctx->jobs[P.job];
+            const csek::UnitState& S = J.cj[P.comp].st;
+            const dim3 blk(256), grd((P.n + 255) / 256);
+            hipLaunchKernelGGL(csek::count_active_kernel, grd, blk, 0, B.stream, S, P.n, B.d_counts + p);
+            if (!P.shares || r >= J.cfg.share_max_rounds) continue;
+            const csek::ShareScratch ss =
+                csek::share_scratch((int32_t*)((char*)B.d_share + P.scratch_off), P.n);
+            hipLaunchKernelGGL(csek::share_rank_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src, ss);
+            hipLaunchKernelGGL(csek::share_target_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src,
+                               ctx->schemes[J.scheme].comp[P.comp].n_fmax, (uint32_t)P.comp, J.cfg.seed,
+                               J.cfg.share_dst_pm, r, ss);
+        }
         HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost,
+                                    B.stream));
+        HIP_TRY(ctx, hipStreamSynchronize(B.stream));
+        bool any = false;
+        for (int p = 0; p < n_pools; ++p) any |= B.h_counts[p] != 0;
+        if (!any) break;
     }
-    const bool sharing = cfg.share_every > 0 && cfg.share_src_pm > 0 && cfg.share_max_rounds > 0;
-    if (sharing) return run_sharing_rounds(ctx, J, sc);
-    for (int c = 0; c < J.n_comp; ++c) {
-        int rc = launch_step(ctx, sc.comp[c], c, cfg, -1, J.cj[c].st, J.d_err, J.stream);
+    return CSE_OK;
+}
+
+// Enqueue every launch of a batch on its stream.
+int run_batch(cse_ctx* ctx, BatchRec& B) {
+    bool first = true;
+    for (int jid : B.jobs) {
+        JobRec& J = ctx->jobs[jid];
+        for (int c = 0; c < J.n_comp; ++c) {
+            csek::UnitState S = J.cj[c].st;
+            S.t0 = B.d_t0;
+            hipLaunchKernelGGL(csek::init_units_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0, B.stream,
+                               S, J.cfg.n_proc, first ? 1 : 0, B.d_err);
+            first = false;
+        }
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (B.sharing) return run_rounds(ctx, B);
+    for (const LaunchGroup& G : B.groups) {
+        int rc = launch_group(ctx, G, B.d_segs, B.d_err, B.stream);
         if (rc) return rc;
     }
     return CSE_OK;
+}
+
+// Device buffers of a batch that do not depend on results: the segment
+// table, the start stamp and error word, and the sharing scratch.
+int setup_batch(cse_ctx* ctx, BatchRec& B) {
+    HIP_TRY(ctx, hipMalloc((void**)&B.d_t0, 64));
+    HIP_TRY(ctx, hipMalloc((void**)&B.d_err, 64));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_done, hipEventDisableTiming));
+    build_segments(ctx, B);
+    for (const LaunchGroup& G : B.groups)
+        if (G.lds > ctx->lds_max)
+            return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
+    HIP_TRY(ctx, hipMalloc((void**)&B.d_segs, sizeof(csek::Segment) * std::max<size_t>(1, B.segs.size())));
+    HIP_TRY(ctx, hipMemcpy(B.d_segs, B.segs.data(), sizeof(csek::Segment) * B.segs.size(), hipMemcpyHostToDevice));
+    size_t off = 0;
+    for (int jid : B.jobs) {
+        JobRec& J = ctx->jobs[jid];
+        B.sharing |= shares(J.cfg);
+        for (int c = 0; c < J.n_comp; ++c) {
+            Pool P;
+            P.job = jid;
+            P.comp = c;
+            P.n = J.cfg.n_proc;
+            P.shares = shares(J.cfg);
+            uint32_t n_src = (uint32_t)(((unsigned long long)P.n * J.cfg.share_src_pm + 999) / 1000);
+            P.n_src = std::max(1u, std::min(n_src, P.n));
+            P.scratch_off = off;
+            if (P.shares) off += csek::share_scratch_bytes(P.n);
+            B.pools.push_back(P);
+        }
+    }
+    if (B.sharing) {
+        HIP_TRY(ctx, hipMalloc((void**)&B.d_share, std::max<size_t>(off, 256)));
+        HIP_TRY(ctx, hipMalloc((void**)&B.d_counts, sizeof(int32_t) * B.pools.size()));
+        HIP_TRY(ctx, hipHostMalloc((void**)&B.h_counts, sizeof(int32_t) * B.pools.size(), hipHostMallocDefault));
+    }
+    return CSE_OK;
+}
+
+void drop_batch(cse_ctx* ctx, int bid) {
+    auto it = ctx->batches.find(bid);
+    if (it == ctx->batches.end()) return;
+    BatchRec& B = it->second;
+    if (!B.finished && B.ev_done) (void)hipEventSynchronize(B.ev_done);
+    for (int jid : B.jobs) {
+        auto jt = ctx->jobs.find(jid);
+        if (jt != ctx->jobs.end()) {
+            free_job_device(jt->second);
+            ctx->jobs.erase(jt);
+        }
+    }
+    free_batch_device(B);
+    ctx->batches.erase(it);
 }
 
 }  // namespace
@@ -353,9 +491,8 @@ int32_t cse_ctx_create(int32_t device, cse_ctx** out) {
     if (!ctx) return CSE_ENOMEM;
     ctx->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
         ctx->lds_max = std::max<size_t>(prop.sharedMemPerBlock, 65536);
-    }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         ctx->tick_hz = (uint64_t)khz * 1000ull;
@@ -366,14 +503,9 @@ int32_t cse_ctx_create(int32_t device, cse_ctx** out) {
 void cse_ctx_destroy(cse_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    for (auto& kv : ctx->jobs) {
-        JobRec& J = kv.second;
-        if (!J.finished) (void)hipEventSynchronize(J.ev_done);
-        for (int c = 0; c < J.n_comp; ++c) (void)hipFree(J.cj[c].block);
-        (void)hipFree(J.d_t0);
-        (void)hipFree(J.d_err);
-        (void)hipEventDestroy(J.ev_done);
-    }
+    std::vector<int> bids;
+    for (auto& kv : ctx->batches) bids.push_back(kv.first);
+    for (int b : bids) drop_batch(ctx, b);
     for (auto& kv : ctx->schemes)
         for (int c = 0; c < kv.second.n_comp; ++c) free_component(kv.second.comp[c]);
     delete ctx;
@@ -437,7 +569,8 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id) {
     auto it = ctx->schemes.find(scheme_id);
     if (it == ctx->schemes.end()) return fail(ctx, CSE_ENOENT, "unknown scheme %d", scheme_id);
     for (auto& kv : ctx->jobs)
-        if (kv.second.scheme == scheme_id && !kv.second.finished) (void)wait_job(ctx, kv.second);
+        if (kv.second.scheme == scheme_id)
+            return fail(ctx, CSE_EBUSY, "scheme %d still has job %d; release it first", scheme_id, kv.first);
     for (int c = 0; c < it->second.n_comp; ++c) free_component(it->second.comp[c]);
     ctx->schemes.erase(it);
     return CSE_OK;
@@ -456,60 +589,108 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
         int rc = validate_cfg(ctx, &cfgs[i]);
         if (rc) return rc;
     }
-    for (int i = 0; i < n; ++i) {
+    const int bid = ctx->next_batch++;
+    BatchRec& B = ctx->batches[bid];
+    B.stream = (hipStream_t)stream;
+    int rc = CSE_OK;
+    for (int i = 0; i < n && rc == CSE_OK; ++i) {
         const SchemeRec& sc = ctx->schemes[scheme_ids[i]];
-        JobRec J;
+        const int jid = ctx->next_job++;
+        JobRec& J = ctx->jobs[jid];
         J.scheme = scheme_ids[i];
         J.cfg = cfgs[i];
-        J.stream = (hipStream_t)stream;
         J.n_comp = sc.n_comp;
-        HIP_TRY(ctx, hipMalloc((void**)&J.d_t0, 64));
-        HIP_TRY(ctx, hipMalloc((void**)&J.d_err, 64));
-        HIP_TRY(ctx, hipMemsetAsync(J.d_err, 0, 64, J.stream));
-        for (int c = 0; c < sc.n_comp; ++c) {
-            int rc = alloc_comp_job(ctx, sc.comp[c], J.cfg.n_proc, J.d_t0, &J.cj[c]);
-            if (rc) return rc;
-        }
-        HIP_TRY(ctx, hipEventCreateWithFlags(&J.ev_done, hipEventDisableTiming));
-        int rc = run_job(ctx, J, sc);
-        if (rc) return rc;
-        HIP_TRY(ctx, hipEventRecord(J.ev_done, J.stream));
-        const int id = ctx->next_job++;
-        ctx->jobs[id] = J;
-        job_ids[i] = id;
+        J.batch = bid;
+        B.jobs.push_back(jid);
+        for (int c = 0; c < sc.n_comp && rc == CSE_OK; ++c) rc = alloc_comp_job(ctx, sc.comp[c], J.cfg.n_proc, &J.cj[c]);
     }
+    if (rc == CSE_OK) rc = setup_batch(ctx, B);
+    if (rc == CSE_OK) {
+        B.finished = false;
+        rc = run_batch(ctx, B);
+    }
+    if (rc == CSE_OK) {
+        hipError_t e = hipEventRecord(B.ev_done, B.stream);
+        if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+    if (rc != CSE_OK) {
+        std::string keep = ctx->err;
+        (void)hipStreamSynchronize(B.stream);
+        B.finished = true;
+        drop_batch(ctx, bid);
+        ctx->err = keep;
+        return rc;
+    }
+    for (int i = 0; i < n; ++i) job_ids[i] = B.jobs[i];
+    return CSE_OK;
+}
+
+int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void* stream) {
+    if (!ctx) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // On the batch's own stream the earlier run is ordered before the new
+    // one; elsewhere, and whenever the host drives rounds, wait for it.
+    int rc = CSE_OK;
+    if ((hipStream_t)stream != B->stream || B->sharing) rc = wait_batch(ctx, *B);
+    if (rc) return rc;
+    if (cfg) {
+        rc = validate_cfg(ctx, cfg);
+        if (rc) return rc;
+        if (B->jobs.size() != 1) return fail(ctx, CSE_EINVAL, "a batched job is relaunched with its batch's configurations");
+        if (cfg->n_proc != J->cfg.n_proc) return fail(ctx, CSE_EINVAL, "n_proc cannot change on relaunch");
+        if (shares(*cfg) != shares(J->cfg)) return fail(ctx, CSE_EINVAL, "relaunch cannot switch sharing on or off");
+        rc = wait_batch(ctx, *B);
+        if (rc) return rc;
+        J->cfg = *cfg;
+        for (csek::Segment& s : B->segs) s.R = run_args(J->cfg);
+        HIP_TRY(ctx, hipMemcpy(B->d_segs, B->segs.data(), sizeof(csek::Segment) * B->segs.size(),
+                               hipMemcpyHostToDevice));
+        for (Pool& P : B->pools) {
+            uint32_t n_src = (uint32_t)(((unsigned long long)P.n * J->cfg.share_src_pm + 999) / 1000);
+            P.n_src = std::max(1u, std::min(n_src, P.n));
+        }
+    }
+    B->stream = (hipStream_t)stream;
+    B->finished = false;
+    rc = run_batch(ctx, *B);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipEventRecord(B->ev_done, B->stream));
     return CSE_OK;
 }
 
 int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done) {
     if (!ctx || !done) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    if (J->finished) { *done = 1; return CSE_OK; }
-    hipError_t e = hipEventQuery(J->ev_done);
+    BatchRec* B = batch_of(ctx, job_id);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (B->finished) { *done = 1; return CSE_OK; }
+    hipError_t e = hipEventQuery(B->ev_done);
     if (e == hipErrorNotReady) { *done = 0; return CSE_OK; }
     if (e != hipSuccess) return fail(ctx, CSE_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
-    J->finished = true;
+    B->finished = true;
     *done = 1;
-    return check_err(ctx, *J);
+    return check_err(ctx, *B);
 }
 
 int32_t cse_wait(cse_ctx* ctx, int32_t job_id) {
     if (!ctx) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    return wait_job(ctx, *J);
+    BatchRec* B = batch_of(ctx, job_id);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    return wait_batch(ctx, *B);
 }
 
 int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n, int32_t* cost,
                              int32_t* steps, int32_t* executed, int32_t* epoch, int32_t* k0, int64_t* ops,
                              int32_t* strat, uint64_t* finish) {
     if (!ctx) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
     if (n != (int32_t)J->cfg.n_proc) return fail(ctx, CSE_ERANGE, "n must equal n_proc (%u)", J->cfg.n_proc);
-    int rc = wait_job(ctx, *J);
+    int rc = wait_batch(ctx, *B);
     if (rc) return rc;
     const csek::UnitState& S = J->cj[comp].st;
     const size_t b4 = (size_t)n * 4, b8 = (size_t)n * 8;
@@ -526,13 +707,14 @@ int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t
 
 int32_t cse_get_programs(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n, int32_t* triples, int32_t cap) {
     if (!ctx || !triples) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
     if (n != (int32_t)J->cfg.n_proc) return fail(ctx, CSE_ERANGE, "n must equal n_proc (%u)", J->cfg.n_proc);
     const DevComp& dc = ctx->schemes[J->scheme].comp[comp];
     if (cap < dc.n_fmax) return fail(ctx, CSE_ERANGE, "cap %d < n_fmax %d", cap, dc.n_fmax);
-    int rc = wait_job(ctx, *J);
+    int rc = wait_batch(ctx, *B);
     if (rc) return rc;
     const int nf = std::max(1, dc.n_fmax);
     std::vector<uint32_t> keys((size_t)n * nf);
@@ -555,12 +737,13 @@ int32_t cse_get_programs(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n, 
 int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc, int32_t* triples, int32_t cap,
                         int32_t* n_fresh, int32_t* cost, int32_t* needed) {
     if (!ctx) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
     const int n = (int)J->cfg.n_proc;
     if (proc < -1 || proc >= n) return fail(ctx, CSE_EINVAL, "process %d out of range", proc);
-    int rc = wait_job(ctx, *J);
+    int rc = wait_batch(ctx, *B);
     if (rc) return rc;
     std::vector<int32_t> costs(n), len(n);
     HIP_TRY(ctx, hipMemcpy(costs.data(), J->cj[comp].st.cost, (size_t)n * 4, hipMemcpyDeviceToHost));
@@ -589,9 +772,10 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
 
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz) {
     if (!ctx) return CSE_EINVAL;
-    JobRec* J = find_job(ctx, job_id);
-    if (!J) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    int rc = wait_job(ctx, *J);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    int rc = wait_batch(ctx, *B);
     if (rc) return rc;
     uint64_t last = 0;
     const int n = (int)J->cfg.n_proc;
@@ -607,15 +791,25 @@ int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* 
 
 int32_t cse_job_release(cse_ctx* ctx, int32_t job_id) {
     if (!ctx) return CSE_EINVAL;
-    auto it = ctx->jobs.find(job_id);
-    if (it == ctx->jobs.end()) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    JobRec& J = it->second;
-    if (!J.finished) (void)hipEventSynchronize(J.ev_done);
-    for (int c = 0; c < J.n_comp; ++c) (void)hipFree(J.cj[c].block);
-    (void)hipFree(J.d_t0);
-    (void)hipFree(J.d_err);
-    (void)hipEventDestroy(J.ev_done);
-    ctx->jobs.erase(it);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    const int bid = J->batch;
+    if (!B->finished) (void)wait_batch(ctx, *B);
+    B->jobs.erase(std::remove(B->jobs.begin(), B->jobs.end(), job_id), B->jobs.end());
+    B->pools.erase(std::remove_if(B->pools.begin(), B->pools.end(), [&](const Pool& p) { return p.job == job_id; }),
+                   B->pools.end());
+    free_job_device(*J);
+    ctx->jobs.erase(job_id);
+    if (B->jobs.empty()) {
+        drop_batch(ctx, bid);
+        return CSE_OK;
+    }
+    // The remaining jobs of a batch keep their results; relaunching them
+    // uses a table rebuilt without the released job.
+    build_segments(ctx, *B);
+    HIP_TRY(ctx, hipMemcpy(B->d_segs, B->segs.data(), sizeof(csek::Segment) * B->segs.size(),
+                           hipMemcpyHostToDevice));
     return CSE_OK;
 }
 

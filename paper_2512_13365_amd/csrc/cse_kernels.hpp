@@ -2,14 +2,20 @@
 // (Perminov, arXiv 2512.13365, Algorithm 1 and Sec. 3.4-3.5).
 //
 // Execution model: one 64-lane wavefront (one workgroup) per unit, i.e. one
-// component reduced by one process.  The unit's state lives in LDS:
+// component reduced by one process.  A launch covers a table of segments;
+// a segment is a contiguous range of units that share one system and one run
+// configuration, so one launch can hold the three components of a scheme or
+// the components of many schemes.  The unit's state lives in LDS:
 //   colP[v][w], colN[v][w]  pos / neg bitsets of variable v over the rows,
 //                           W 64-bit words per column (rows <= 64 W);
-//   live[]                  ids of the variables with a nonzero column,
-//                           ascending (fresh ids are always the largest);
+//   live[], vpos[]          ids of the variables with a nonzero column,
+//                           ascending (fresh ids are always the largest), and
+//                           the position of each live variable in that list;
 //   cand[]                  the pairs occurring at least twice, in canonical
 //                           order, one 64-bit entry each: key | c << 32 with
-//                           key = a << 16 | b << 1 | (s < 0).
+//                           key = a << 16 | b << 1 | (s < 0);
+//   newc[], M[]             scratch for the pairs of a fresh variable and for
+//                           the per-variable candidate masks of gi.
 // The pair count of (a, b, +) is popc(Pa & Pb) + popc(Na & Nb) and of
 // (a, b, -) popc(Pa & Nb) + popc(Na & Pb), summed over the row words.
 // Every random draw is a Philox4x32-10 block of a counter that names the
@@ -19,11 +25,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Wavefront reductions and scans of the ROCm device library (DPP based).
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ __attribute__((const)) long long __ockl_wfred_add_i64(long long);
+extern "C" __device__ __attribute__((const)) long long __ockl_wfred_max_i64(long long);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
 namespace csek {
 
 constexpr int kWave = 64;
 enum { S_G = 0, S_GA = 1, S_WR = 2, S_GR = 3, S_GI = 4, S_MIX = 5, S_GP = 6, N_STRAT = 7 };
 enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4 };
+
+// Device consistency flags (host reports them as an error).
+enum { ERR_CAND_OVERFLOW = 1, ERR_BAD_PICK = 2, ERR_COUNT_MISMATCH = 4, ERR_NEW_OVERFLOW = 8 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC 2011).  Ten rounds; each multiplies words
@@ -60,7 +75,8 @@ __device__ __forceinline__ uint32_t scale_u32(uint32_t u, uint32_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront helpers (64 lanes, one wave per workgroup).
+// Wavefront helpers (64 lanes, one wave per workgroup).  Reductions and scans
+// use the device library's DPP sequences; call them in uniform control flow.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -69,49 +85,23 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
-
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ long long wave_sum64(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+__device__ __forceinline__ int wave_sum(int v) { return __ockl_wfred_add_i32(v); }
+__device__ __forceinline__ long long wave_sum64(long long v) { return __ockl_wfred_add_i64(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ long long wave_max64(long long v) { return __ockl_wfred_max_i64(v); }
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o);
-        v = w > v ? w : v;
-    }
-    return v;
+    return __ockl_wfred_max_u64(v);
 }
 // Inclusive prefix sum across the wave.
-__device__ __forceinline__ uint32_t wave_scan(uint32_t v) {
-    const int l = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t w = __shfl_up(v, o);
-        if (l >= o) v += w;
-    }
-    return v;
-}
+__device__ __forceinline__ int wave_scan(int v) { return __ockl_wfscan_add_i32(v, true); }
 
 __device__ __forceinline__ uint32_t pair_key(int a, int b, int neg) {
     return ((uint32_t)a << 16) | ((uint32_t)b << 1) | (uint32_t)neg;
 }
 __device__ __forceinline__ int key_a(uint32_t k) { return (int)(k >> 16); }
 __device__ __forceinline__ int key_b(uint32_t k) { return (int)((k >> 1) & 0x7FFFu); }
+__device__ __forceinline__ int entry_c(uint64_t e) { return (int)((e >> 32) & 0x3FFu); }
 
 // ---------------------------------------------------------------------------
 // Kernel arguments.
@@ -123,6 +113,9 @@ struct CompArgs {
     int32_t naive0;
     uint32_t comp;
     int32_t prog_stride;  // max(1, n_fmax): program entries per unit
+    int32_t newc_cap;     // capacity of the fresh-variable pair list
+    int32_t m_words;      // capacity of the gi masks (64-bit words)
+    int32_t pad;
 };
 
 struct RunArgs {
@@ -148,6 +141,33 @@ struct UnitState {         // per process arrays of one component
     const unsigned long long* t0;
 };
 
+// A contiguous range of grid units sharing one system and one configuration.
+struct Segment {
+    CompArgs C;
+    RunArgs R;
+    UnitState S;
+    uint32_t unit_begin;   // first grid unit of the segment
+    uint32_t pad;
+};
+
+// LDS layout of a unit (the host sizes the launch with the same formula).
+struct LdsLayout {
+    size_t colP, colN, cand, newc, M, live, vpos, bytes;
+};
+__host__ __device__ inline LdsLayout lds_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words) {
+    LdsLayout L;
+    size_t o = 0;
+    L.colP = o; o += (size_t)n_vmax * W * 8;
+    L.colN = o; o += (size_t)n_vmax * W * 8;
+    L.cand = o; o += (size_t)m_cap * 8;
+    L.newc = o; o += (size_t)newc_cap * 8;
+    L.M = o;    o += (size_t)m_words * 8;
+    L.live = o; o += (size_t)n_vmax * 4;
+    L.vpos = o; o += (size_t)n_vmax * 4;
+    L.bytes = (o + 15) & ~size_t(15);
+    return L;
+}
+
 __device__ __forceinline__ int weighted_pick(const uint32_t* w, int n, uint32_t u) {
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += w[i];
@@ -158,6 +178,20 @@ __device__ __forceinline__ int weighted_pick(const uint32_t* w, int n, uint32_t 
         if (run > x) return i;
     }
     return -1;
+}
+
+// Pair counts of two columns: .x = c(+), .y = c(-).
+template <int W>
+__device__ __forceinline__ int2 pair_counts(const uint64_t* colP, const uint64_t* colN, int va, int vb) {
+    int cp = 0, cm = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint64_t Pa = colP[va * W + w], Na = colN[va * W + w];
+        const uint64_t Pb = colP[vb * W + w], Nb = colN[vb * W + w];
+        cp += popc64(Pa & Pb) + popc64(Na & Nb);
+        cm += popc64(Pa & Nb) + popc64(Na & Pb);
+    }
+    return make_int2(cp, cm);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,8 +229,9 @@ __device__ __forceinline__ int substitute(uint64_t* colP, uint64_t* colN, uint32
 }
 
 // Remove the variables that died and append the fresh one (the largest id),
-// keeping the list ascending.  Returns the new length.
-__device__ __forceinline__ int update_live(uint32_t* live, int n_live, int a, int b, int dead, int k) {
+// keeping the list ascending and vpos in step.  Returns the new length.
+__device__ __forceinline__ int update_live(uint32_t* live, int32_t* vpos, int n_live, int a, int b, int dead,
+                                           int k) {
     const int l = lane_id();
     int n = n_live;
     if (dead) {
@@ -207,61 +242,163 @@ __device__ __forceinline__ int update_live(uint32_t* live, int n_live, int a, in
             const bool keep = i < n_live && !((dead & 1) && (int)x == a) && !((dead & 2) && (int)x == b);
             const uint64_t m = ballot(keep);
             __syncthreads();
-            if (keep) live[out + lanes_below(m)] = x;
+            if (keep) {
+                const int p = out + lanes_below(m);
+                live[p] = x;
+                vpos[x - 1] = p;
+            }
             out += popc64(m);
             __syncthreads();
         }
         n = out;
     }
-    if (l == 0) live[n] = (uint32_t)k;
+    if (l == 0) {
+        live[n] = (uint32_t)k;
+        vpos[k - 1] = n;
+    }
     __syncthreads();
     return n + 1;
 }
 
-// Analysis (Algorithm 1): count every canonical pair of live variables from
-// the bitsets and keep those with c >= 2, in canonical order.  Pairs are
+// Full Analysis (Algorithm 1): count every canonical pair of live variables
+// from the bitsets and keep those with c >= 2, in canonical order.  Pairs are
 // enumerated by (first, second) position in the ascending live list, which
-// is the canonical (a, b) order; within a pair '+' precedes '-'.
+// is the canonical (a, b) order; within a pair '+' precedes '-'.  Used once
+// per launch; later steps update the list incrementally.
 template <int W>
-__device__ __forceinline__ int analyse_full(const uint64_t* colP, const uint64_t* colN, const uint32_t* live,
-                                            int n_live, uint64_t* cand, int m_cap, int* overflow) {
+__device__ int analyse_full(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                            uint64_t* cand, int m_cap, int* err_flags) {
     const int l = lane_id();
     int m = 0;
     for (int i = 0; i + 1 < n_live; ++i) {
         const int a = (int)live[i];
-        uint64_t Pa[W], Na[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) { Pa[w] = colP[(a - 1) * W + w]; Na[w] = colN[(a - 1) * W + w]; }
         for (int jb = i + 1; jb < n_live; jb += kWave) {
             const int j = jb + l;
             const bool valid = j < n_live;
-            const int b = valid ? (int)live[j] : 1;
-            int cp = 0, cm = 0;
-            if (valid) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const uint64_t Pb = colP[(b - 1) * W + w], Nb = colN[(b - 1) * W + w];
-                    cp += popc64(Pa[w] & Pb) + popc64(Na[w] & Nb);
-                    cm += popc64(Pa[w] & Nb) + popc64(Na[w] & Pb);
-                }
-            }
-            const bool hp = valid && cp >= 2, hm = valid && cm >= 2;
+            const int b = valid ? (int)live[j] : a;
+            const int2 c = valid ? pair_counts<W>(colP, colN, a - 1, b - 1) : make_int2(0, 0);
+            const bool hp = c.x >= 2, hm = c.y >= 2;
             const uint64_t bp = ballot(hp), bm = ballot(hm);
             const int pos = m + lanes_below(bp) + lanes_below(bm);
             if (hp) {
-                if (pos < m_cap) cand[pos] = pair_key(a, b, 0) | ((uint64_t)cp << 32);
-                else *overflow = 1;
+                if (pos < m_cap) cand[pos] = pair_key(a, b, 0) | ((uint64_t)c.x << 32);
+                else *err_flags |= ERR_CAND_OVERFLOW;
             }
             if (hm) {
                 const int q = pos + (hp ? 1 : 0);
-                if (q < m_cap) cand[q] = pair_key(a, b, 1) | ((uint64_t)cm << 32);
-                else *overflow = 1;
+                if (q < m_cap) cand[q] = pair_key(a, b, 1) | ((uint64_t)c.y << 32);
+                else *err_flags |= ERR_CAND_OVERFLOW;
             }
             m += popc64(bp) + popc64(bm);
         }
     }
     __syncthreads();
     return m < m_cap ? m : m_cap;
+}
+
+// Incremental Analysis after substituting (a, b) -> k.  Only pairs touching a,
+// b or k change: counts touching a or b can only fall (they are recounted
+// and dropped below 2); pairs with k are new.  Pairs (x, k) sort after every
+// old pair whose first variable is <= x (k is the largest id), so the new
+// list is an ordered merge of the filtered old list and the new pairs.
+template <int W>
+__device__ int update_candidates(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                                 uint64_t* cand, int m, uint64_t* newc, int newc_cap, int m_cap, int a, int b,
+                                 int k, int* err_flags) {
+    const int l = lane_id();
+    // 1. Recount the pairs touching a or b; compact in place.
+    int mf = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int i = base + l;
+        const bool valid = i < m;
+        uint64_t e = valid ? cand[i] : 0ull;
+        const uint32_t key = (uint32_t)e;
+        const int qa = key_a(key), qb = key_b(key);
+        const bool touch = valid && (qa == a || qa == b || qb == a || qb == b);
+        int c = entry_c(e);
+        if (touch) {
+            const int2 cc = pair_counts<W>(colP, colN, qa - 1, qb - 1);
+            c = (key & 1u) ? cc.y : cc.x;
+            e = (uint64_t)key | ((uint64_t)c << 32);
+        }
+        const bool keep = valid && c >= 2;
+        const uint64_t bk = ballot(keep);
+        __syncthreads();
+        if (keep) cand[mf + lanes_below(bk)] = e;
+        mf += popc64(bk);
+    }
+    __syncthreads();
+    // 2. Pairs of the fresh variable k (the last live entry) with every other.
+    int n_new = 0;
+    for (int base = 0; base < n_live - 1; base += kWave) {
+        const int i = base + l;
+        const bool valid = i < n_live - 1;
+        const int x = valid ? (int)live[i] : k;
+        const int2 c = valid ? pair_counts<W>(colP, colN, x - 1, k - 1) : make_int2(0, 0);
+        const bool hp = c.x >= 2, hm = c.y >= 2;
+        const uint64_t bp = ballot(hp), bm = ballot(hm);
+        const int pos = n_new + lanes_below(bp) + lanes_below(bm);
+        if (hp) {
+            if (pos < newc_cap) newc[pos] = pair_key(x, k, 0) | ((uint64_t)c.x << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        if (hm) {
+            const int q = pos + (hp ? 1 : 0);
+            if (q < newc_cap) newc[q] = pair_key(x, k, 1) | ((uint64_t)c.y << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        n_new += popc64(bp) + popc64(bm);
+    }
+    if (n_new > newc_cap) n_new = newc_cap;
+    if (mf + n_new > m_cap) { *err_flags |= ERR_CAND_OVERFLOW; n_new = m_cap - mf; }
+    __syncthreads();
+    if (n_new == 0) return mf;
+    // 3a. Destination of each new pair: its index plus the number of old
+    // pairs whose first variable is <= x (binary search).  Kept in bits 42+.
+    for (int base = 0; base < n_new; base += kWave) {
+        const int e = base + l;
+        if (e < n_new) {
+            const uint64_t v = newc[e];
+            const int x = key_a((uint32_t)v);
+            int lo = 0, hi = mf;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)cand[mid]) <= x) lo = mid + 1; else hi = mid;
+            }
+            newc[e] = v | ((uint64_t)(e + lo) << 42);
+        }
+    }
+    __syncthreads();
+    // 3b. Move old pairs up by the number of new pairs with a smaller first
+    // variable, last chunk first (destinations are increasing in the index).
+    for (int base = ((mf - 1) / kWave) * kWave; base >= 0; base -= kWave) {
+        const int i = base + l;
+        const bool valid = i < mf;
+        const uint64_t v = valid ? cand[i] : 0ull;
+        int shift = 0;
+        if (valid) {
+            const int qa = key_a((uint32_t)v);
+            int lo = 0, hi = n_new;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)newc[mid]) < qa) lo = mid + 1; else hi = mid;
+            }
+            shift = lo;
+        }
+        __syncthreads();
+        if (valid) cand[i + shift] = v;
+        __syncthreads();
+    }
+    // 3c. Place the new pairs.
+    for (int base = 0; base < n_new; base += kWave) {
+        const int e = base + l;
+        if (e < n_new) {
+            const uint64_t v = newc[e];
+            cand[(int)(v >> 42)] = v & ((1ull << 42) - 1);
+        }
+    }
+    __syncthreads();
+    return mf + n_new;
 }
 
 // Greedy (Sec. 3.4.1): highest c, first in canonical order.
@@ -271,7 +408,8 @@ __device__ __forceinline__ int select_g(const uint64_t* cand, int m) {
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
         if (q < m) {
-            const unsigned long long key = ((cand[q] >> 32) << 32) | (0xFFFFFFFFull - (unsigned)q);
+            const unsigned long long key = ((unsigned long long)entry_c(cand[q]) << 32) |
+                                           (0xFFFFFFFFull - (unsigned)q);
             best = key > best ? key : best;
         }
     }
@@ -286,18 +424,18 @@ __device__ __forceinline__ int select_ga(const uint64_t* cand, int m, uint32_t u
     int cmax = 0;
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
-        if (q < m) { const int c = (int)(cand[q] >> 32); cmax = c > cmax ? c : cmax; }
+        if (q < m) { const int c = entry_c(cand[q]); cmax = c > cmax ? c : cmax; }
     }
     cmax = wave_max(cmax);
     int ties = 0;
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
-        ties += popc64(ballot(q < m && (int)(cand[q] >> 32) == cmax));
+        ties += popc64(ballot(q < m && entry_c(cand[q]) == cmax));
     }
     uint32_t want = scale_u32(u, (uint32_t)ties);
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
-        const bool tie = q < m && (int)(cand[q] >> 32) == cmax;
+        const bool tie = q < m && entry_c(cand[q]) == cmax;
         const uint64_t bt = ballot(tie);
         const uint32_t cnt = (uint32_t)popc64(bt);
         if (want < cnt) {
@@ -309,27 +447,40 @@ __device__ __forceinline__ int select_ga(const uint64_t* cand, int m, uint32_t u
     return -1;
 }
 
-// Weighted-Random (Sec. 3.4.1): probability proportional to c - 1; the first
-// candidate whose running sum of c - 1 exceeds floor(u T / 2^32).
-__device__ __forceinline__ int select_wr(const uint64_t* cand, int m, uint32_t u) {
+// Sum of c - 1 over the candidates.
+__device__ __forceinline__ int total_profit(const uint64_t* cand, int m) {
     const int l = lane_id();
     int tot = 0;
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
-        tot += q < m ? (int)(cand[q] >> 32) - 1 : 0;
+        tot += q < m ? entry_c(cand[q]) - 1 : 0;
     }
-    tot = wave_sum(tot);
+    return wave_sum(tot);
+}
+
+// Weighted-Random (Sec. 3.4.1): probability proportional to c - 1; the first
+// candidate whose running sum of c - 1 exceeds floor(u T / 2^32).
+__device__ __forceinline__ int select_wr(const uint64_t* cand, int m, uint32_t u) {
+    const int l = lane_id();
+    const int tot = total_profit(cand, m);
     const uint32_t x = scale_u32(u, (uint32_t)tot);
     uint32_t run = 0;
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
-        const uint32_t w = q < m ? (uint32_t)(cand[q] >> 32) - 1u : 0u;
-        const uint32_t incl = wave_scan(w);
+        const int w = q < m ? entry_c(cand[q]) - 1 : 0;
+        const uint32_t incl = (uint32_t)wave_scan(w);
         const uint64_t hit = ballot(q < m && run + incl > x);
         if (hit) return base + ctz64(hit);
-        run += __shfl(incl, kWave - 1);
+        run += (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
     }
     return -1;
+}
+
+// Greedy-Intersections argmax over per-lane (score, index) with ties to the
+// lower index.
+__device__ __forceinline__ int gi_argmax(long long best_h, int best_p) {
+    const long long hmax = wave_max64(best_h);
+    return wave_min(best_h == hmax ? best_p : 0x7FFFFFFF);
 }
 
 // Greedy-Intersections (Sec. 3.4.2).  Lane p scores candidate p:
@@ -337,11 +488,10 @@ __device__ __forceinline__ int select_wr(const uint64_t* cand, int m, uint32_t u
 // with D_p the profit of the disjoint candidates and X_p that of the
 // intersecting candidates whose coin is 1.  The j-th intersecting candidate
 // of p in canonical order uses bit j mod 128 of Philox block
-// (proc, COIN|comp|epoch|step, key(p), j div 128).  Every q is visited in
-// canonical order (the O(m^2) form).  Ties go to the lower index.
-__device__ __forceinline__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_t bq,
-                                               uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw,
-                                               long long* n_int, long long* n_blk) {
+// (proc, COIN|comp|epoch|step, key(p), j div 128).  This form visits every q
+// (the O(m^2) scan); it serves when the masks of the sparse form do not fit.
+__device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
+                               uint32_t proc, uint32_t dw, long long* n_int, long long* n_blk) {
     const int l = lane_id();
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
@@ -358,7 +508,7 @@ __device__ __forceinline__ int select_gi_dense(const uint64_t* cand, int m, uint
             const uint64_t eq = cand[q];
             const uint32_t kq = (uint32_t)eq;
             const int qa = key_a(kq), qb = key_b(kq);
-            const int wq = (int)(eq >> 32) - 1;
+            const int wq = entry_c(eq) - 1;
             const bool inter = (qa == ap) | (qa == bp) | (qb == ap) | (qb == bp);
             if (!inter) {
                 D += wq;
@@ -371,22 +521,89 @@ __device__ __forceinline__ int select_gi_dense(const uint64_t* cand, int m, uint
             }
         }
         if (valid) {
-            const long long wp = (long long)(ep >> 32) - 1;
+            const long long wp = (long long)entry_c(ep) - 1;
             const long long h = (wp << 32) + (long long)aq * (((long long)D << 16) + (long long)bq * X);
             if (h > best_h) { best_h = h; best_p = p; }
             my_int += j;
             my_blk += (j + 127) >> 7;
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long oh = __shfl_xor(best_h, o);
-        const int op = __shfl_xor(best_p, o);
-        if (oh > best_h || (oh == best_h && op < best_p)) { best_h = oh; best_p = op; }
+    *n_int = wave_sum64(my_int);
+    *n_blk = wave_sum64(my_blk);
+    return gi_argmax(best_h, best_p);
+}
+
+// Greedy-Intersections, sparse form: M[v][w] marks (bit i of word w) the
+// candidates 64w + i that contain the live variable at position v.  Lane p
+// walks the set bits of M[a] | M[b] (minus p itself) in increasing index,
+// i.e. exactly the intersecting candidates in canonical order, so the coin
+// order is the same as the dense form's.  D_p = T - (c_p - 1) - I_p with I_p
+// the profit of all intersecting candidates.
+__device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M,
+                                uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw,
+                                long long* n_int, long long* n_blk) {
+    const int l = lane_id();
+    const int nw = (m + kWave - 1) / kWave;
+    for (int i = l; i < n_live * nw; i += kWave) M[i] = 0ull;
+    __syncthreads();
+    for (int base = 0; base < m; base += kWave) {
+        const int q = base + l;
+        if (q < m) {
+            const uint32_t key = (uint32_t)cand[q];
+            const int w = base / kWave;
+            const unsigned long long bit = 1ull << l;
+            atomicOr((unsigned long long*)&M[vpos[key_a(key) - 1] * nw + w], bit);
+            atomicOr((unsigned long long*)&M[vpos[key_b(key) - 1] * nw + w], bit);
+        }
+    }
+    __syncthreads();
+    const int T = total_profit(cand, m);
+    long long best_h = -1;
+    int best_p = 0x7FFFFFFF;
+    long long my_int = 0, my_blk = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int p = base + l;
+        const bool valid = p < m;
+        const uint64_t ep = valid ? cand[p] : 0ull;
+        const uint32_t kp = (uint32_t)ep;
+        U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
+        uint64_t cw = (uint64_t)blk.x | ((uint64_t)blk.y << 32);
+        int I = 0, X = 0, j = 0;
+        if (valid) {
+            const uint64_t* Ma = M + vpos[key_a(kp) - 1] * nw;
+            const uint64_t* Mb = M + vpos[key_b(kp) - 1] * nw;
+            for (int w = 0; w < nw; ++w) {
+                uint64_t u = Ma[w] | Mb[w];
+                if (w == base / kWave) u &= ~(1ull << l);
+                while (u) {
+                    const int q = (w << 6) + ctz64(u);
+                    u &= u - 1;
+                    const int wq = entry_c(cand[q]) - 1;
+                    I += wq;
+                    X += (cw & 1ull) ? wq : 0;
+                    cw >>= 1;
+                    ++j;
+                    if ((j & 63) == 0) {
+                        if ((j & 127) == 0) {
+                            blk = philox10(proc, dw, kp, (uint32_t)(j >> 7), k0, k1);
+                            cw = (uint64_t)blk.x | ((uint64_t)blk.y << 32);
+                        } else {
+                            cw = (uint64_t)blk.z | ((uint64_t)blk.w << 32);
+                        }
+                    }
+                }
+            }
+            const long long wp = (long long)entry_c(ep) - 1;
+            const long long D = (long long)T - wp - I;
+            const long long h = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
+            if (h > best_h) { best_h = h; best_p = p; }
+            my_int += j;
+            my_blk += (j + 127) >> 7;
+        }
     }
     *n_int = wave_sum64(my_int);
     *n_blk = wave_sum64(my_blk);
-    return best_p;
+    return gi_argmax(best_h, best_p);
 }
 
 // Algorithmic work of a step in 32-bit integer lane operations (the same
@@ -401,24 +618,46 @@ __device__ __forceinline__ unsigned long long step_ops(int strat, int m, long lo
     return (unsigned long long)(98 + sel + 10 * w + 24 * w * (long long)(n_live - 1));
 }
 
+__device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uint32_t g) {
+    int lo = 0, hi = n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].unit_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // The step kernel: one workgroup (one wave) per unit.  Restores the unit by
-// replaying its program from the input system, then runs up to `budget`
-// selection steps (Analysis -> Selection -> Substitution) or until no pair
-// occurs twice / the program reaches step_cap.
+// replaying its program from the input system, counts all pairs once, then
+// runs up to `budget` selection steps (Selection -> Substitution ->
+// incremental Analysis) or until no pair occurs twice / the program reaches
+// step_cap.  Grid unit g maps to segment s and process g - unit_begin.
 // ---------------------------------------------------------------------------
 template <int W>
-__global__ __launch_bounds__(kWave) void step_kernel(CompArgs C, RunArgs R, UnitState S, int* err) {
+__global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
+                                                     uint32_t n_grid, int* err) {
     extern __shared__ uint64_t smem[];
     const int l = lane_id();
-    const uint32_t proc = blockIdx.x;
+    const uint32_t g = blockIdx.x;
+    if (g >= n_grid) return;
+    const Segment& sg = segs[find_segment(segs, n_segs, g)];
+    const CompArgs& C = sg.C;
+    const RunArgs& R = sg.R;
+    const UnitState& S = sg.S;
+    const uint32_t proc = g - sg.unit_begin;
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    uint64_t* colP = smem;
-    uint64_t* colN = colP + (size_t)n_vmax * W;
-    uint64_t* cand = colN + (size_t)n_vmax * W;
-    uint32_t* live = (uint32_t*)(cand + C.m_cap);
+    const LdsLayout LL = lds_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words);
+    char* base = (char*)smem;
+    uint64_t* colP = (uint64_t*)(base + LL.colP);
+    uint64_t* colN = (uint64_t*)(base + LL.colN);
+    uint64_t* cand = (uint64_t*)(base + LL.cand);
+    uint64_t* newc = (uint64_t*)(base + LL.newc);
+    uint64_t* M = (uint64_t*)(base + LL.M);
+    uint32_t* live = (uint32_t*)(base + LL.live);
+    int32_t* vpos = (int32_t*)(base + LL.vpos);
 
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
 
@@ -455,24 +694,28 @@ __global__ __launch_bounds__(kWave) void step_kernel(CompArgs C, RunArgs R, Unit
     int n_live = 0;
     {
         const int n_v = C.n_x + t;
-        for (int base = 0; base < n_v; base += kWave) {
-            const int v = base + l;
+        for (int b0 = 0; b0 < n_v; b0 += kWave) {
+            const int v = b0 + l;
             bool nz = false;
             if (v < n_v) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) nz |= (colP[v * W + w] | colN[v * W + w]) != 0;
             }
             const uint64_t mk = ballot(nz);
-            if (nz) live[n_live + lanes_below(mk)] = (uint32_t)(v + 1);
+            if (nz) {
+                const int p = n_live + lanes_below(mk);
+                live[p] = (uint32_t)(v + 1);
+                vpos[v] = p;
+            }
             n_live += popc64(mk);
         }
         __syncthreads();
     }
 
+    int err_flags = 0;
+    int m = analyse_full<W>(colP, colN, live, n_live, cand, C.m_cap, &err_flags);
     int active = 1;
-    int overflow = 0;
     for (int done = 0;; ++done) {
-        const int m = analyse_full<W>(colP, colN, live, n_live, cand, C.m_cap, &overflow);
         if (m == 0 || (R.step_cap && (uint32_t)t >= R.step_cap) || t >= C.n_fmax) { active = 0; break; }
         if (R.budget >= 0 && done >= R.budget) break;
 
@@ -486,28 +729,41 @@ __global__ __launch_bounds__(kWave) void step_kernel(CompArgs C, RunArgs R, Unit
 
         long long n_int = 0, n_blk = 0;
         int pick;
-        if (s == S_G) pick = select_g(cand, m);
-        else if (s == S_GA) pick = select_ga(cand, m, su.z);
-        else if (s == S_WR) pick = select_wr(cand, m, su.z);
-        else pick = select_gi_dense(cand, m, alpha_q, beta_q, k0, k1, proc,
-                                    domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t), &n_int, &n_blk);
-        if (pick < 0 || pick >= m) { if (l == 0) atomicOr(err, 2); active = 0; break; }
+        if (s == S_G) {
+            pick = select_g(cand, m);
+        } else if (s == S_GA) {
+            pick = select_ga(cand, m, su.z);
+        } else if (s == S_WR) {
+            pick = select_wr(cand, m, su.z);
+        } else {
+            const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
+            if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
+                pick = select_gi_sparse(cand, m, vpos, n_live, M, alpha_q, beta_q, k0, k1, proc, dw, &n_int,
+                                        &n_blk);
+            else
+                pick = select_gi_dense(cand, m, alpha_q, beta_q, k0, k1, proc, dw, &n_int, &n_blk);
+        }
+        if (pick < 0 || pick >= m) { err_flags |= ERR_BAD_PICK; active = 0; break; }
 
         const uint64_t e = cand[pick];
         const uint32_t key = (uint32_t)e;
-        const int csel = (int)(e >> 32);
+        const int csel = entry_c(e);
         __syncthreads();
         int dead;
-        const int c = substitute<W>(colP, colN, key, C.n_x + t, &dead);
-        if (c != csel && l == 0) atomicOr(err, 4);
-        n_live = update_live(live, n_live, key_a(key), key_b(key), dead, C.n_x + t + 1);
+        const int k = C.n_x + t + 1;
+        const int c = substitute<W>(colP, colN, key, k - 1, &dead);
+        if (c != csel) err_flags |= ERR_COUNT_MISMATCH;
+        n_live = update_live(live, vpos, n_live, key_a(key), key_b(key), dead, k);
         if (l == 0) prog[t] = key;
         ++t;
         cost -= c - 1;
         ++executed;
         ops += step_ops(s, m, n_int, n_blk, C.n_e, n_live);
+        m = update_candidates<W>(colP, colN, live, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
+                                 key_b(key), k, &err_flags);
     }
-    if (overflow && l == 0) atomicOr(err, 1);
+    const unsigned any_err = __ockl_wfred_or_u32((unsigned)err_flags);
+    if (any_err && l == 0) atomicOr(err, (int)any_err);
 
     if (l == 0) {
         S.t[proc] = t;
@@ -521,9 +777,12 @@ __global__ __launch_bounds__(kWave) void step_kernel(CompArgs C, RunArgs R, Unit
 }
 
 // Job start stamp and per-unit state initialisation.
-__global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp) {
+__global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp, int* err) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (stamp && i == 0) *(unsigned long long*)S.t0 = wall_clock64();
+    if (stamp && i == 0) {
+        *(unsigned long long*)S.t0 = wall_clock64();
+        *err = 0;
+    }
     if (i >= n_units) return;
     S.t[i] = 0;
     S.cost[i] = 0;

@@ -20,25 +20,33 @@ namespace csek {
 struct ShareScratch {
     int32_t* is_src;    // n
     int32_t* src_list;  // n_src, in rank order
-    int32_t* counter;   // [0] active units
 };
 
-inline size_t share_scratch_bytes(uint32_t n) { return ((size_t)n * 2 + 64) * 4; }
+// Scratch of one pool: 2 n int32, rounded to 256 bytes.
+inline size_t share_scratch_bytes(uint32_t n) { return (((size_t)n * 8) + 255) & ~size_t(255); }
 
 inline ShareScratch share_scratch(int32_t* base, uint32_t n) {
     ShareScratch s;
-    s.counter = base;
-    s.is_src = base + 64;
-    s.src_list = base + 64 + n;
+    s.is_src = base;
+    s.src_list = base + n;
     return s;
 }
 
-__global__ void share_clear_kernel(ShareScratch s) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) s.counter[0] = 0;
+__global__ void fill_i32_kernel(int32_t* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Number of active units of a pool, added to *out.
+__global__ void count_active_kernel(UnitState S, uint32_t n, int32_t* out) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool a = u < n && S.active[u] != 0;
+    const int c = __popcll(__ballot(a));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
 // Rank every unit by (cost, process); mark the first n_src and list them in
-// rank order; count the active units.
+// rank order.
 __global__ void share_rank_kernel(UnitState S, uint32_t n, uint32_t n_src, ShareScratch sc) {
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
@@ -51,7 +59,6 @@ __global__ void share_rank_kernel(UnitState S, uint32_t n, uint32_t n_src, Share
     const bool src = below < n_src;
     sc.is_src[u] = src ? 1 : 0;
     if (src) sc.src_list[below] = (int32_t)u;
-    if (S.active[u]) atomicAdd(sc.counter, 1);
 }
 
 // Targets copy a prefix of their source's program; the step kernel replays

@@ -167,3 +167,67 @@ def test_invalid_inputs_rejected(gpu):
     assert cost == 1 and tri.tolist() == [[1, 2, 1]]
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
+
+
+def test_dense_gi_fallback_large_candidate_set(gpu, oracle):
+    """Many candidates (m ~ 2000): the gi masks exceed their LDS budget and
+    the O(m^2) form runs; both forms use the same coin order."""
+    A = workloads.random_system(2024, 100, 60, 0.25, 1, 20)
+    kw = dict(seed=11, n_proc=16, weights={"gi": 3, "mix": 1, "wr": 1}, step_cap=30)
+    check_workload(gpu, oracle, [A], kw, "dense-gi 100x60")
+
+
+def test_relaunch_new_seed(gpu, oracle):
+    cse, ctx, torch = gpu
+    wl = workloads.plain_4x4x4(n_proc=512)
+    sc, rs = wl.schemes[0], wl.runs[0]
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    kw = rs.as_kwargs()
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    for seed in (7, 8):
+        kw["seed"] = seed
+        say(f"[gpu] relaunch seed {seed}")
+        cse.cse_relaunch(ctx, job, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+        cse.cse_wait(ctx, job)
+        ocfg = oracle.make_cfg(**kw)
+        for c, A in enumerate(sc.systems):
+            got = cse.cse_get_unit_results(ctx, job, c, rs.n_proc)
+            got["prog"] = cse.cse_get_programs(ctx, job, c, rs.n_proc, cse.cse_scheme_info(ctx, sid)[c][2])
+            ref = oracle.run_pool(A, ocfg, comp=c, n_threads=THREADS)
+            assert_same(got, ref, f"relaunch seed {seed} comp {c}")
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+
+
+def test_batch_equals_separate_jobs(gpu, oracle):
+    """One batched launch over uneven schemes (row words 1 and 2, with and
+    without sharing) gives every unit the result of its own job."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(44)
+    shapes = [(2, 3, 4), (4, 4, 3), (3, 2, 2), (5, 5, 4), (2, 2, 2), (3, 4, 4), (4, 4, 4)]
+    ranks = [workloads.scheme_rank(*s) for s in shapes]
+    pools = workloads.pools_by_rank(ranks, 420)
+    runs = []
+    for i, ((n, m, p), r) in enumerate(zip(shapes, ranks)):
+        U, V, Wt = workloads.scheme_systems(rng, n, m, p, r, 0.2)
+        sc = workloads.Scheme(f"{n}x{m}x{p}:{r}", U, V, Wt)
+        kw = dict(seed=i, n_proc=pools[i], weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+        if i % 2 == 0:
+            kw.update(share_every=8, share_src_pm=50, share_dst_pm=200, share_max_rounds=20)
+        runs.append((sc, kw))
+    sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc, _ in runs]
+    say(f"[gpu] batch of {len(runs)}: {[sc.name for sc, _ in runs]}")
+    jobs = cse.cse_launch_batch(ctx, sids, [cse.cse_run_cfg(**kw) for _, kw in runs],
+                                torch.cuda.current_stream())
+    for (sc, kw), sid, job in zip(runs, sids, jobs):
+        ocfg = oracle.make_cfg(**kw)
+        info = cse.cse_scheme_info(ctx, sid)
+        for c, A in enumerate(sc.systems):
+            got = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+            got["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+            ref = oracle.run_pool(A, ocfg, comp=c, n_threads=THREADS)
+            assert_same(got, ref, f"batch {sc.name} comp {c}")
+    for job in jobs:
+        cse.cse_job_release(ctx, job)
+    for sid in sids:
+        cse.cse_scheme_free(ctx, sid)
