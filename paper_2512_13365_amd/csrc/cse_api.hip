@@ -27,10 +27,14 @@ namespace {
 
 constexpr int kMaxRows = 512;          // W <= 8 row words
 constexpr int kMaxVars = 32767;        // 15-bit variable ids
-constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB of LDS per unit
+constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit
+// Units whose state exceeds this many bytes of LDS keep the bulk of it in
+// HBM (one slot per unit) and only the variable lists in LDS.
+constexpr size_t kLdsUnitBudget = 64 * 1024;
 
 struct DevComp {
     int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0;
+    bool gs = false;     // bulk state in HBM
     long long occ0 = 0;
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
@@ -56,6 +60,7 @@ struct JobRec {
 
 struct LaunchGroup {
     int W = 0;
+    bool gs = false;
     uint32_t n_grid = 0;
     size_t lds = 0;
     int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
@@ -118,8 +123,11 @@ int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail((ctx), CSE_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+size_t bulk_bytes(const DevComp& c) {
+    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words).bytes;
+}
 size_t lds_bytes(const DevComp& c) {
-    return csek::lds_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words).bytes;
+    return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
 }
 
 int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
@@ -155,6 +163,7 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
     const long long full_masks = (long long)n_vmax * ((c.m_cap + 63) / 64);
     c.m_words = (int)std::min<long long>(full_masks, kMaskBudgetWords);
+    c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
     std::vector<uint64_t> P((size_t)cols * c.W, 0), N((size_t)cols * c.W, 0);
     for (int i = 0; i < rows; ++i)
         for (int j = 0; j < cols; ++j) {
@@ -233,12 +242,15 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
     const size_t i32 = (size_t)n * 4;
     const size_t u64 = (size_t)n * 8;
-    const size_t total = prog + 7 * i32 + 2 * u64 + 64 * 10;
+    const size_t gs = c.gs ? (size_t)n * bulk_bytes(c) : 0;
+    const size_t total = gs + prog + 7 * i32 + 2 * u64 + 64 * 11;
     char* base = nullptr;
     HIP_TRY(ctx, hipMalloc((void**)&base, total));
     cj->block = base;
     auto take = [&](size_t bytes) { char* p = base; base += (bytes + 63) & ~size_t(63); return p; };
     csek::UnitState& S = cj->st;
+    S.gs_base = c.gs ? take(gs) : nullptr;
+    S.gs_stride = c.gs ? bulk_bytes(c) : 0;
     S.ops = (unsigned long long*)take(u64);
     S.finish = (unsigned long long*)take(u64);
     S.prog = (uint32_t*)take(prog);
@@ -281,9 +293,12 @@ void free_job_device(JobRec& J) {
 void build_segments(cse_ctx* ctx, BatchRec& B) {
     B.segs.clear();
     B.groups.clear();
-    for (int W = 1; W <= 8; ++W) {
+    for (int cls = 0; cls < 16; ++cls) {
+        const int W = 1 + (cls >> 1);
+        const bool gs = cls & 1;
         LaunchGroup G;
         G.W = W;
+        G.gs = gs;
         G.seg_begin = (int)B.segs.size();
         uint32_t unit = 0;
         for (int jid : B.jobs) {
@@ -291,7 +306,7 @@ void build_segments(cse_ctx* ctx, BatchRec& B) {
             const SchemeRec& sc = ctx->schemes[J.scheme];
             for (int c = 0; c < J.n_comp; ++c) {
                 const DevComp& dc = sc.comp[c];
-                if (dc.W != W) continue;
+                if (dc.W != W || dc.gs != gs) continue;
                 csek::Segment s{};
                 s.C = comp_args(dc, c);
                 s.R = run_args(J.cfg);
@@ -309,31 +324,36 @@ void build_segments(cse_ctx* ctx, BatchRec& B) {
     }
 }
 
-template <int W>
+template <int W, bool GS>
 int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
     if (G.lds > 65536)
-        HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W>,
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds));
-    hipLaunchKernelGGL(csek::step_kernel<W>, dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+    hipLaunchKernelGGL((csek::step_kernel<W, GS>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
                        d_segs + G.seg_begin, G.n_segs, G.n_grid, d_err);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;
 }
 
-int launch_group(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+template <bool GS>
+int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
     switch (G.W) {
-    case 1: return launch_group_w<1>(ctx, G, d_segs, d_err, s);
-    case 2: return launch_group_w<2>(ctx, G, d_segs, d_err, s);
-    case 3: return launch_group_w<3>(ctx, G, d_segs, d_err, s);
-    case 4: return launch_group_w<4>(ctx, G, d_segs, d_err, s);
-    case 5: return launch_group_w<5>(ctx, G, d_segs, d_err, s);
-    case 6: return launch_group_w<6>(ctx, G, d_segs, d_err, s);
-    case 7: return launch_group_w<7>(ctx, G, d_segs, d_err, s);
-    case 8: return launch_group_w<8>(ctx, G, d_segs, d_err, s);
+    case 1: return launch_group_w<1, GS>(ctx, G, d_segs, d_err, s);
+    case 2: return launch_group_w<2, GS>(ctx, G, d_segs, d_err, s);
+    case 3: return launch_group_w<3, GS>(ctx, G, d_segs, d_err, s);
+    case 4: return launch_group_w<4, GS>(ctx, G, d_segs, d_err, s);
+    case 5: return launch_group_w<5, GS>(ctx, G, d_segs, d_err, s);
+    case 6: return launch_group_w<6, GS>(ctx, G, d_segs, d_err, s);
+    case 7: return launch_group_w<7, GS>(ctx, G, d_segs, d_err, s);
+    case 8: return launch_group_w<8, GS>(ctx, G, d_segs, d_err, s);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
     }
+}
+
+int launch_group(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+    return G.gs ? launch_group_gs<true>(ctx, G, d_segs, d_err, s) : launch_group_gs<false>(ctx, G, d_segs, d_err, s);
 }
 
 int check_err(cse_ctx* ctx, BatchRec& B) {

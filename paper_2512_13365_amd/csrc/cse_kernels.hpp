@@ -139,6 +139,8 @@ struct UnitState {         // per process arrays of one component
     unsigned long long* ops;
     unsigned long long* finish;
     const unsigned long long* t0;
+    char* gs_base;         // HBM-resident unit state (large systems), else null
+    unsigned long long gs_stride;  // bytes of HBM state per unit
 };
 
 // A contiguous range of grid units sharing one system and one configuration.
@@ -150,23 +152,25 @@ struct Segment {
     uint32_t pad;
 };
 
-// LDS layout of a unit (the host sizes the launch with the same formula).
-struct LdsLayout {
-    size_t colP, colN, cand, newc, M, live, vpos, bytes;
+// Layout of a unit's state (the host sizes launches with the same formulas).
+// The bulk (bitsets, candidates, scratch) lives in LDS, or for systems too
+// large for LDS in a per-unit HBM slot; live/vpos always live in LDS.
+struct BulkLayout {
+    size_t colP, colN, cand, newc, M, bytes;
 };
-__host__ __device__ inline LdsLayout lds_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words) {
-    LdsLayout L;
+__host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words) {
+    BulkLayout L;
     size_t o = 0;
     L.colP = o; o += (size_t)n_vmax * W * 8;
     L.colN = o; o += (size_t)n_vmax * W * 8;
     L.cand = o; o += (size_t)m_cap * 8;
     L.newc = o; o += (size_t)newc_cap * 8;
     L.M = o;    o += (size_t)m_words * 8;
-    L.live = o; o += (size_t)n_vmax * 4;
-    L.vpos = o; o += (size_t)n_vmax * 4;
-    L.bytes = (o + 15) & ~size_t(15);
+    L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
+// live and vpos: n_vmax int32 each.
+__host__ __device__ inline size_t list_bytes(int n_vmax) { return ((size_t)n_vmax * 8 + 15) & ~size_t(15); }
 
 __device__ __forceinline__ int weighted_pick(const uint32_t* w, int n, uint32_t u) {
     uint64_t total = 0;
@@ -634,7 +638,7 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // incremental Analysis) or until no pair occurs twice / the program reaches
 // step_cap.  Grid unit g maps to segment s and process g - unit_begin.
 // ---------------------------------------------------------------------------
-template <int W>
+template <int W, bool GS>
 __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
                                                      uint32_t n_grid, int* err) {
     extern __shared__ uint64_t smem[];
@@ -649,15 +653,16 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    const LdsLayout LL = lds_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words);
-    char* base = (char*)smem;
-    uint64_t* colP = (uint64_t*)(base + LL.colP);
-    uint64_t* colN = (uint64_t*)(base + LL.colN);
-    uint64_t* cand = (uint64_t*)(base + LL.cand);
-    uint64_t* newc = (uint64_t*)(base + LL.newc);
-    uint64_t* M = (uint64_t*)(base + LL.M);
-    uint32_t* live = (uint32_t*)(base + LL.live);
-    int32_t* vpos = (int32_t*)(base + LL.vpos);
+    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words);
+    char* bulk = GS ? S.gs_base + (size_t)proc * S.gs_stride : (char*)smem;
+    char* lists = GS ? (char*)smem : (char*)smem + BL.bytes;
+    uint64_t* colP = (uint64_t*)(bulk + BL.colP);
+    uint64_t* colN = (uint64_t*)(bulk + BL.colN);
+    uint64_t* cand = (uint64_t*)(bulk + BL.cand);
+    uint64_t* newc = (uint64_t*)(bulk + BL.newc);
+    uint64_t* M = (uint64_t*)(bulk + BL.M);
+    uint32_t* live = (uint32_t*)lists;
+    int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
 
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
 

@@ -231,3 +231,12 @@ def test_batch_equals_separate_jobs(gpu, oracle):
         cse.cse_job_release(ctx, job)
     for sid in sids:
         cse.cse_scheme_free(ctx, sid)
+
+
+@pytest.mark.parametrize("rows,cols,p,cap", [(42, 197, 0.2, 40), (331, 64, 0.12, 25)])
+def test_hbm_state_large_systems(gpu, oracle, rows, cols, p, cap):
+    """Systems whose state exceeds the LDS budget keep it in HBM slots
+    (shapes of the 7x7x4-r197 W^T and the 8x8x8-r331 U components)."""
+    A = workloads.random_system(rows + 7 * cols, rows, cols, p)
+    kw = dict(seed=3, n_proc=12, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True, step_cap=cap)
+    check_workload(gpu, oracle, [A], kw, f"hbm-state {rows}x{cols}")
