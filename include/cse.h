@@ -65,7 +65,13 @@ extern "C" {
 #define CSE_COUNT_POPCOUNT 1   /* wavefront popcount over column bitsets */
 #define CSE_COUNT_MFMA     2   /* int8 MFMA Gram product for the first count */
 
+/* States of a job submitted to a server. */
+#define CSE_JOB_QUEUED  0   /* waiting for admission */
+#define CSE_JOB_RUNNING 1   /* admitted; advances one round per tick */
+#define CSE_JOB_DONE    2   /* every unit finished; results readable */
+
 typedef struct cse_ctx cse_ctx;
+typedef struct cse_server cse_server;
 
 /* Run configuration (Sec. 3.5).  Zero-initialise and set what is needed. */
 typedef struct {
@@ -170,8 +176,37 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
  * finish, and the tick rate in Hz. */
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz);
 
-/* Free a job's device memory (the other jobs of its batch keep theirs). */
+/* Free a job's device memory (the other jobs of its batch keep theirs).
+ * Server jobs are released with cse_server_release. */
 int32_t cse_job_release(cse_ctx* ctx, int32_t job_id);
+
+/* ---- Serving: continuous batching of reduction jobs -------------------
+ * A server admits submitted jobs first come, first served while the device
+ * state of the admitted, unreleased jobs fits max_state_bytes, and advances
+ * every admitted job by one round per tick: one launch per row-word class
+ * covers the units of all admitted jobs, so a job admitted between ticks
+ * joins the next launch.  A round is at most share_every selection steps
+ * per unit for a job that shares (then its sharing event), else at most
+ * round_steps.  Every job's results equal those of its own cse_launch. */
+
+/* Create a server on ctx issuing its work on `stream`; round_steps >= 1. */
+int32_t cse_server_create(cse_ctx* ctx, uint64_t max_state_bytes, uint32_t round_steps, void* stream,
+                          cse_server** out);
+/* Queue a job (not yet admitted).  CSE_ENOMEM if it alone exceeds the
+ * server's budget. */
+int32_t cse_server_submit(cse_server* s, int32_t scheme_id, const cse_run_cfg* cfg, int32_t* job_id);
+/* Admit what fits, run one round of every admitted job, retire finished
+ * jobs; blocks until the round's device work is done.  Reports how many
+ * jobs are running and queued afterwards. */
+int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued);
+/* State (CSE_JOB_*) and host steady-clock times in ns of submission,
+ * admission and completion (0 until reached). */
+int32_t cse_server_job_info(cse_server* s, int32_t job_id, int32_t* state, uint64_t times_ns[3]);
+/* Free a done job's device memory and return it to the admission budget.
+ * Results are read with cse_get_* while the job is done and unreleased. */
+int32_t cse_server_release(cse_server* s, int32_t job_id);
+/* Destroy the server and every job it owns. */
+void cse_server_destroy(cse_server* s);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,9 @@ STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4:
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
            "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_launch", "cse_launch_batch",
            "cse_relaunch", "cse_poll", "cse_wait", "cse_get_unit_results", "cse_get_programs", "cse_get_program",
-           "cse_job_timing", "cse_job_release")
+           "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
+           "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy")
+CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE = 0, 1, 2
 
 
 class CseError(RuntimeError):
@@ -108,6 +110,18 @@ def load_library(path: str = LIB_PATH):
     L.cse_job_timing.restype = i32
     L.cse_job_release.argtypes = [vp, i32]
     L.cse_job_release.restype = i32
+    L.cse_server_create.argtypes = [vp, ctypes.c_uint64, u32, vp, P(vp)]
+    L.cse_server_create.restype = i32
+    L.cse_server_submit.argtypes = [vp, i32, P(CseRunCfg), P(i32)]
+    L.cse_server_submit.restype = i32
+    L.cse_server_tick.argtypes = [vp, P(i32), P(i32)]
+    L.cse_server_tick.restype = i32
+    L.cse_server_job_info.argtypes = [vp, i32, P(i32), P(ctypes.c_uint64)]
+    L.cse_server_job_info.restype = i32
+    L.cse_server_release.argtypes = [vp, i32]
+    L.cse_server_release.restype = i32
+    L.cse_server_destroy.argtypes = [vp]
+    L.cse_server_destroy.restype = None
     _lib = L
     return L
 
@@ -284,3 +298,49 @@ def cse_job_timing(ctx, job_id):
 
 def cse_job_release(ctx, job_id):
     _check(ctx, load_library().cse_job_release(ctx, job_id))
+
+
+# Servers report errors through the context they were created on.
+class CseServer:
+    """Handle of a server; keeps the context for error messages."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+
+def cse_server_create(ctx, max_state_bytes, round_steps=32, stream=None) -> CseServer:
+    h = ctypes.c_void_p()
+    _check(ctx, load_library().cse_server_create(ctx, max_state_bytes, round_steps, _stream_ptr(stream),
+                                                 ctypes.byref(h)))
+    return CseServer(ctx, h)
+
+
+def cse_server_submit(server: CseServer, scheme_id, cfg: CseRunCfg) -> int:
+    job = ctypes.c_int32()
+    _check(server.ctx, load_library().cse_server_submit(server.handle, scheme_id, ctypes.byref(cfg),
+                                                        ctypes.byref(job)))
+    return job.value
+
+
+def cse_server_tick(server: CseServer):
+    """Returns (running, queued)."""
+    r, q = ctypes.c_int32(), ctypes.c_int32()
+    _check(server.ctx, load_library().cse_server_tick(server.handle, ctypes.byref(r), ctypes.byref(q)))
+    return r.value, q.value
+
+
+def cse_server_job_info(server: CseServer, job_id):
+    """Returns (state, (t_submit_ns, t_admit_ns, t_done_ns))."""
+    st = ctypes.c_int32()
+    t = (ctypes.c_uint64 * 3)()
+    _check(server.ctx, load_library().cse_server_job_info(server.handle, job_id, ctypes.byref(st), t))
+    return st.value, tuple(int(x) for x in t)
+
+
+def cse_server_release(server: CseServer, job_id):
+    _check(server.ctx, load_library().cse_server_release(server.handle, job_id))
+
+
+def cse_server_destroy(server: CseServer):
+    load_library().cse_server_destroy(server.handle)

@@ -2,19 +2,24 @@
 //
 // A context owns loaded schemes (input systems as column bitsets in HBM),
 // jobs (per-unit state and programs of one scheme run) and batches (the
-// jobs launched together).  Every batch is executed by launch groups: one
-// step-kernel launch per row-word count W covering the units of all its
-// jobs' components, described by a segment table in device memory.  With
-// sharing (Sec. 3.5.2) the host runs rounds: every group advances its units
-// by at most share_every steps, each component pool ranks its units and
-// copies prefixes, and the host reads the number of active units per pool
-// until none is left.
+// jobs that share launches).  A batch is executed by launch groups: one
+// step-kernel launch per (row-word count W, state placement) covering the
+// units of all its jobs' components, described by a segment table in device
+// memory.  With sharing (Sec. 3.5.2) the host runs rounds: every group
+// advances its units by at most share_every steps, each component pool
+// counts its active units, ranks them and copies prefixes, and the host
+// reads the counts.  A server is a batch whose job set changes between
+// rounds: jobs are admitted as device memory frees up and join the next
+// round's launches (continuous batching); every job keeps its own round
+// counter, so its results are those of running alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -32,9 +37,14 @@ constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit
 // HBM (one slot per unit) and only the variable lists in LDS.
 constexpr size_t kLdsUnitBudget = 64 * 1024;
 
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 struct DevComp {
     int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0;
-    bool gs = false;     // bulk state in HBM
+    bool gs = false;  // bulk state in HBM
     long long occ0 = 0;
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
@@ -48,6 +58,7 @@ struct SchemeRec {
 struct CompJob {
     csek::UnitState st{};
     void* block = nullptr;  // one allocation for all per-unit arrays
+    size_t bytes = 0;
 };
 
 struct JobRec {
@@ -56,6 +67,16 @@ struct JobRec {
     int n_comp = 0;
     CompJob cj[3];
     int batch = -1;
+    unsigned long long* d_t0 = nullptr;  // device clock at the start of the latest run
+    int32_t* d_share = nullptr;          // sharing scratch of its pools
+    int budget = -1;                     // selection steps per launch (< 0: to completion)
+    uint32_t round = 0;                  // rounds completed in the latest run
+    bool done = false;                   // every unit finished (round-driven runs)
+    bool allocated = false;
+    bool server = false;                 // owned by a server
+    int state = CSE_JOB_DONE;            // CSE_JOB_* (server jobs)
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    size_t bytes = 0;                    // device footprint
 };
 
 struct LaunchGroup {
@@ -70,24 +91,25 @@ struct Pool {  // the units of one component of one job
     int job = 0, comp = 0;
     uint32_t n = 0, n_src = 0;
     bool shares = false;
-    size_t scratch_off = 0;  // bytes into the batch's sharing scratch
+    int32_t* scratch = nullptr;
 };
 
 struct BatchRec {
-    std::vector<int> jobs;
+    std::vector<int> jobs;            // jobs launched by this batch (unfinished ones for a server)
     std::vector<csek::Segment> segs;  // host copy of the segment table
     csek::Segment* d_segs = nullptr;
+    size_t segs_cap = 0;
     std::vector<LaunchGroup> groups;
     std::vector<Pool> pools;
-    bool sharing = false;
+    bool rounds = false;  // host-driven rounds (sharing or server)
     hipStream_t stream = nullptr;
     hipEvent_t ev_done = nullptr;
     bool finished = true;
     int* d_err = nullptr;
-    unsigned long long* d_t0 = nullptr;
-    int32_t* d_share = nullptr;   // sharing scratch of all pools
     int32_t* d_counts = nullptr;  // active units per pool
     int32_t* h_counts = nullptr;  // pinned copy
+    size_t counts_cap = 0;
+    bool is_server = false;
 };
 
 }  // namespace
@@ -101,6 +123,15 @@ struct cse_ctx {
     int next_scheme = 1, next_job = 1, next_batch = 1;
     size_t lds_max = 65536;
     uint64_t tick_hz = 100000000ull;
+};
+
+struct cse_server {
+    cse_ctx* ctx = nullptr;
+    int batch = -1;
+    uint64_t max_bytes = 0, used_bytes = 0;
+    uint32_t round_steps = 32;
+    std::deque<int> queue;
+    bool dirty = true;  // job set changed since the segment table was built
 };
 
 namespace {
@@ -208,7 +239,8 @@ int validate_cfg(cse_ctx* ctx, const cse_run_cfg* cfg) {
     return CSE_OK;
 }
 
-csek::RunArgs run_args(const cse_run_cfg& cfg) {
+csek::RunArgs run_args(const JobRec& J) {
+    const cse_run_cfg& cfg = J.cfg;
     csek::RunArgs R{};
     R.seed = cfg.seed;
     for (int i = 0; i < 7; ++i) R.weights[i] = cfg.weights[i];
@@ -217,7 +249,7 @@ csek::RunArgs run_args(const cse_run_cfg& cfg) {
     R.gr_p_q16 = cfg.gr_p_q16;
     R.step_cap = cfg.step_cap;
     R.iteration = cfg.iteration;
-    R.budget = shares(cfg) ? (int)cfg.share_every : -1;
+    R.budget = J.budget;
     R.n_units = cfg.n_proc;
     return R;
 }
@@ -238,15 +270,32 @@ csek::CompArgs comp_args(const DevComp& c, int comp) {
     return C;
 }
 
+size_t comp_job_bytes(const DevComp& c, uint32_t n) {
+    const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
+    const size_t gs = c.gs ? (size_t)n * bulk_bytes(c) : 0;
+    return gs + prog + 7 * (size_t)n * 4 + 2 * (size_t)n * 8 + 64 * 11;
+}
+
+size_t job_bytes(cse_ctx* ctx, int scheme, const cse_run_cfg& cfg) {
+    const SchemeRec& sc = ctx->schemes[scheme];
+    size_t b = 128;
+    for (int c = 0; c < sc.n_comp; ++c) {
+        b += comp_job_bytes(sc.comp[c], cfg.n_proc);
+        if (shares(cfg)) b += csek::share_scratch_bytes(cfg.n_proc);
+    }
+    return b;
+}
+
 int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
     const size_t i32 = (size_t)n * 4;
     const size_t u64 = (size_t)n * 8;
     const size_t gs = c.gs ? (size_t)n * bulk_bytes(c) : 0;
-    const size_t total = gs + prog + 7 * i32 + 2 * u64 + 64 * 11;
+    const size_t total = comp_job_bytes(c, n);
     char* base = nullptr;
     HIP_TRY(ctx, hipMalloc((void**)&base, total));
     cj->block = base;
+    cj->bytes = total;
     auto take = [&](size_t bytes) { char* p = base; base += (bytes + 63) & ~size_t(63); return p; };
     csek::UnitState& S = cj->st;
     S.gs_base = c.gs ? take(gs) : nullptr;
@@ -264,35 +313,58 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     return CSE_OK;
 }
 
-void free_batch_device(BatchRec& B) {
-    if (B.d_segs) (void)hipFree(B.d_segs);
-    if (B.d_err) (void)hipFree(B.d_err);
-    if (B.d_t0) (void)hipFree(B.d_t0);
-    if (B.d_share) (void)hipFree(B.d_share);
-    if (B.d_counts) (void)hipFree(B.d_counts);
-    if (B.h_counts) (void)hipHostFree(B.h_counts);
-    if (B.ev_done) (void)hipEventDestroy(B.ev_done);
-    B.d_segs = nullptr;
-    B.d_err = nullptr;
-    B.d_t0 = nullptr;
-    B.d_share = nullptr;
-    B.d_counts = nullptr;
-    B.h_counts = nullptr;
-    B.ev_done = nullptr;
-}
-
 void free_job_device(JobRec& J) {
     for (int c = 0; c < J.n_comp; ++c) {
         if (J.cj[c].block) (void)hipFree(J.cj[c].block);
         J.cj[c].block = nullptr;
     }
+    if (J.d_t0) (void)hipFree(J.d_t0);
+    if (J.d_share) (void)hipFree(J.d_share);
+    J.d_t0 = nullptr;
+    J.d_share = nullptr;
+    J.allocated = false;
 }
 
-// Segment table and launch groups of a batch: the components of all its
-// jobs, grouped by row-word count W (the kernel is specialised on W).
-void build_segments(cse_ctx* ctx, BatchRec& B) {
+// Device memory of one job: unit arrays per component, start stamp,
+// sharing scratch.
+int alloc_job(cse_ctx* ctx, JobRec& J) {
+    const SchemeRec& sc = ctx->schemes[J.scheme];
+    J.n_comp = sc.n_comp;
+    J.allocated = true;
+    for (int c = 0; c < sc.n_comp; ++c) {
+        int rc = alloc_comp_job(ctx, sc.comp[c], J.cfg.n_proc, &J.cj[c]);
+        if (rc) return rc;
+        J.cj[c].st.t0 = nullptr;
+    }
+    HIP_TRY(ctx, hipMalloc((void**)&J.d_t0, 64));
+    for (int c = 0; c < sc.n_comp; ++c) J.cj[c].st.t0 = J.d_t0;
+    if (shares(J.cfg))
+        HIP_TRY(ctx, hipMalloc((void**)&J.d_share, csek::share_scratch_bytes(J.cfg.n_proc) * sc.n_comp));
+    J.bytes = job_bytes(ctx, J.scheme, J.cfg);
+    return CSE_OK;
+}
+
+void free_batch_device(BatchRec& B) {
+    if (B.d_segs) (void)hipFree(B.d_segs);
+    if (B.d_err) (void)hipFree(B.d_err);
+    if (B.d_counts) (void)hipFree(B.d_counts);
+    if (B.h_counts) (void)hipHostFree(B.h_counts);
+    if (B.ev_done) (void)hipEventDestroy(B.ev_done);
+    B.d_segs = nullptr;
+    B.d_err = nullptr;
+    B.d_counts = nullptr;
+    B.h_counts = nullptr;
+    B.ev_done = nullptr;
+    B.segs_cap = B.counts_cap = 0;
+}
+
+// Segment table, launch groups and pools of the batch's unfinished jobs:
+// components grouped by row-word count W and state placement (the kernel is
+// specialised on both), then uploaded on the batch's stream.
+int build_segments(cse_ctx* ctx, BatchRec& B) {
     B.segs.clear();
     B.groups.clear();
+    B.pools.clear();
     for (int cls = 0; cls < 16; ++cls) {
         const int W = 1 + (cls >> 1);
         const bool gs = cls & 1;
@@ -303,15 +375,15 @@ void build_segments(cse_ctx* ctx, BatchRec& B) {
         uint32_t unit = 0;
         for (int jid : B.jobs) {
             JobRec& J = ctx->jobs[jid];
+            if (J.done) continue;
             const SchemeRec& sc = ctx->schemes[J.scheme];
             for (int c = 0; c < J.n_comp; ++c) {
                 const DevComp& dc = sc.comp[c];
                 if (dc.W != W || dc.gs != gs) continue;
                 csek::Segment s{};
                 s.C = comp_args(dc, c);
-                s.R = run_args(J.cfg);
+                s.R = run_args(J);
                 s.S = J.cj[c].st;
-                s.S.t0 = B.d_t0;
                 s.unit_begin = unit;
                 unit += J.cfg.n_proc;
                 G.lds = std::max(G.lds, lds_bytes(dc));
@@ -322,6 +394,43 @@ void build_segments(cse_ctx* ctx, BatchRec& B) {
         G.n_grid = unit;
         if (G.n_segs) B.groups.push_back(G);
     }
+    for (int jid : B.jobs) {
+        JobRec& J = ctx->jobs[jid];
+        if (J.done) continue;
+        for (int c = 0; c < J.n_comp; ++c) {
+            Pool P;
+            P.job = jid;
+            P.comp = c;
+            P.n = J.cfg.n_proc;
+            P.shares = shares(J.cfg);
+            uint32_t n_src = (uint32_t)(((unsigned long long)P.n * J.cfg.share_src_pm + 999) / 1000);
+            P.n_src = std::max(1u, std::min(n_src, P.n));
+            P.scratch = P.shares ? (int32_t*)((char*)J.d_share + csek::share_scratch_bytes(P.n) * c) : nullptr;
+            B.pools.push_back(P);
+        }
+    }
+    for (const LaunchGroup& G : B.groups)
+        if (G.lds > ctx->lds_max)
+            return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
+    if (B.segs.size() > B.segs_cap) {
+        if (B.d_segs) HIP_TRY(ctx, hipFree(B.d_segs));
+        B.d_segs = nullptr;
+        B.segs_cap = std::max<size_t>(B.segs.size(), 2 * B.segs_cap);
+        HIP_TRY(ctx, hipMalloc((void**)&B.d_segs, sizeof(csek::Segment) * B.segs_cap));
+    }
+    if (B.rounds && B.pools.size() > B.counts_cap) {
+        if (B.d_counts) HIP_TRY(ctx, hipFree(B.d_counts));
+        if (B.h_counts) HIP_TRY(ctx, hipHostFree(B.h_counts));
+        B.d_counts = nullptr;
+        B.h_counts = nullptr;
+        B.counts_cap = std::max<size_t>(B.pools.size(), 2 * B.counts_cap);
+        HIP_TRY(ctx, hipMalloc((void**)&B.d_counts, sizeof(int32_t) * B.counts_cap));
+        HIP_TRY(ctx, hipHostMalloc((void**)&B.h_counts, sizeof(int32_t) * B.counts_cap, hipHostMallocDefault));
+    }
+    if (!B.segs.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(B.d_segs, B.segs.data(), sizeof(csek::Segment) * B.segs.size(),
+                                    hipMemcpyHostToDevice, B.stream));
+    return CSE_OK;
 }
 
 template <int W, bool GS>
@@ -352,8 +461,13 @@ int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_s
     }
 }
 
-int launch_group(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
-    return G.gs ? launch_group_gs<true>(ctx, G, d_segs, d_err, s) : launch_group_gs<false>(ctx, G, d_segs, d_err, s);
+int launch_groups(cse_ctx* ctx, BatchRec& B) {
+    for (const LaunchGroup& G : B.groups) {
+        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_err, B.stream)
+                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_err, B.stream);
+        if (rc) return rc;
+    }
+    return CSE_OK;
 }
 
 int check_err(cse_ctx* ctx, BatchRec& B) {
@@ -380,103 +494,75 @@ BatchRec* batch_of(cse_ctx* ctx, int job_id, JobRec** job = nullptr) {
     return bt == ctx->batches.end() ? nullptr : &bt->second;
 }
 
-// Sharing rounds (Sec. 3.5.2): every group advances its active units by at
-// most share_every steps; each sharing pool below its round limit ranks its
-// units and copies prefixes into targets; the host then reads the number of
-// still-active units per pool and stops when none is left.  Pools past
-// share_max_rounds keep stepping without sharing, which is the same as
-// running to completion.
-int run_rounds(cse_ctx* ctx, BatchRec& B) {
-    const int n_pools = (int)B.pools.size();
-    for (uint32_t r = 0;; ++r) {
-        for (const LaunchGroup& G : B.groups) {
-            int rc = launch_group(ctx, G, B.d_segs, B.d_err, B.stream);
-            if (rc) return rc;
-        }
-        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), dim3(256), 0, B.stream,
-                           B.d_counts, n_pools, 0);
-        for (int p = 0; p < n_pools; ++p) {
-            const Pool& P = B.pools[p];
-            JobRec& J = ctx->jobs[P.job];
-            const csek::UnitState& S = J.cj[P.comp].st;
-            const dim3 blk(256), grd((P.n + 255) / 256);
-            hipLaunchKernelGGL(csek::count_active_kernel, grd, blk, 0, B.stream, S, P.n, B.d_counts + p);
-            if (!P.shares || r >= J.cfg.share_max_rounds) continue;
-            const csek::ShareScratch ss =
-                csek::share_scratch((int32_t*)((char*)B.d_share + P.scratch_off), P.n);
-            hipLaunchKernelGGL(csek::share_rank_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src, ss);
-            hipLaunchKernelGGL(csek::share_target_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src,
-                               ctx->schemes[J.scheme].comp[P.comp].n_fmax, (uint32_t)P.comp, J.cfg.seed,
-                               J.cfg.share_dst_pm, r, ss);
-        }
-        HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost,
-                                    B.stream));
-        HIP_TRY(ctx, hipStreamSynchronize(B.stream));
-        bool any = false;
-        for (int p = 0; p < n_pools; ++p) any |= B.h_counts[p] != 0;
-        if (!any) break;
-    }
+// Reset the unit arrays of a job and stamp its start on the stream.
+int init_job(cse_ctx* ctx, JobRec& J, hipStream_t s) {
+    for (int c = 0; c < J.n_comp; ++c)
+        hipLaunchKernelGGL(csek::init_units_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0, s,
+                           J.cj[c].st, J.cfg.n_proc, c == 0 ? 1 : 0);
+    HIP_TRY(ctx, hipGetLastError());
+    J.round = 0;
+    J.done = false;
     return CSE_OK;
 }
 
-// Enqueue every launch of a batch on its stream.
-int run_batch(cse_ctx* ctx, BatchRec& B) {
-    bool first = true;
-    for (int jid : B.jobs) {
-        JobRec& J = ctx->jobs[jid];
-        for (int c = 0; c < J.n_comp; ++c) {
-            csek::UnitState S = J.cj[c].st;
-            S.t0 = B.d_t0;
-            hipLaunchKernelGGL(csek::init_units_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0, B.stream,
-                               S, J.cfg.n_proc, first ? 1 : 0, B.d_err);
-            first = false;
-        }
+// One round for every unfinished job of the batch (Sec. 3.5.2): one launch
+// per group advances each active unit by at most its job's budget; then every
+// pool counts its active units and, if its job shares and is below
+// share_max_rounds, ranks its units and copies prefixes into targets.  The
+// host waits for the counts; a job with no active unit left is done.
+int round_once(cse_ctx* ctx, BatchRec& B) {
+    int rc = launch_groups(ctx, B);
+    if (rc) return rc;
+    const int n_pools = (int)B.pools.size();
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), dim3(256), 0, B.stream, B.d_counts,
+                       n_pools, 0);
+    for (int p = 0; p < n_pools; ++p) {
+        const Pool& P = B.pools[p];
+        JobRec& J = ctx->jobs[P.job];
+        const csek::UnitState& S = J.cj[P.comp].st;
+        const dim3 blk(256), grd((P.n + 255) / 256);
+        hipLaunchKernelGGL(csek::count_active_kernel, grd, blk, 0, B.stream, S, P.n, B.d_counts + p);
+        if (!P.shares || J.round >= J.cfg.share_max_rounds) continue;
+        const csek::ShareScratch ss = csek::share_scratch(P.scratch, P.n);
+        hipLaunchKernelGGL(csek::share_rank_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src, ss);
+        hipLaunchKernelGGL(csek::share_target_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src,
+                           ctx->schemes[J.scheme].comp[P.comp].n_fmax, (uint32_t)P.comp, J.cfg.seed,
+                           J.cfg.share_dst_pm, J.round, ss);
     }
     HIP_TRY(ctx, hipGetLastError());
-    if (B.sharing) return run_rounds(ctx, B);
-    for (const LaunchGroup& G : B.groups) {
-        int rc = launch_group(ctx, G, B.d_segs, B.d_err, B.stream);
-        if (rc) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(ctx, hipStreamSynchronize(B.stream));
+    std::map<int, long long> active;
+    for (int p = 0; p < n_pools; ++p) active[B.pools[p].job] += B.h_counts[p];
+    for (auto& kv : active) {
+        JobRec& J = ctx->jobs[kv.first];
+        J.round++;
+        if (kv.second == 0) J.done = true;
     }
     return CSE_OK;
 }
 
-// Device buffers of a batch that do not depend on results: the segment
-// table, the start stamp and error word, and the sharing scratch.
-int setup_batch(cse_ctx* ctx, BatchRec& B) {
-    HIP_TRY(ctx, hipMalloc((void**)&B.d_t0, 64));
-    HIP_TRY(ctx, hipMalloc((void**)&B.d_err, 64));
-    HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_done, hipEventDisableTiming));
-    build_segments(ctx, B);
-    for (const LaunchGroup& G : B.groups)
-        if (G.lds > ctx->lds_max)
-            return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    HIP_TRY(ctx, hipMalloc((void**)&B.d_segs, sizeof(csek::Segment) * std::max<size_t>(1, B.segs.size())));
-    HIP_TRY(ctx, hipMemcpy(B.d_segs, B.segs.data(), sizeof(csek::Segment) * B.segs.size(), hipMemcpyHostToDevice));
-    size_t off = 0;
+// Enqueue a batch's run on its stream.  Without sharing one launch per group
+// runs every unit to completion asynchronously; with sharing the host runs
+// rounds until no job has an active unit.
+int run_batch(cse_ctx* ctx, BatchRec& B) {
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B.stream, B.d_err, 1, 0);
     for (int jid : B.jobs) {
         JobRec& J = ctx->jobs[jid];
-        B.sharing |= shares(J.cfg);
-        for (int c = 0; c < J.n_comp; ++c) {
-            Pool P;
-            P.job = jid;
-            P.comp = c;
-            P.n = J.cfg.n_proc;
-            P.shares = shares(J.cfg);
-            uint32_t n_src = (uint32_t)(((unsigned long long)P.n * J.cfg.share_src_pm + 999) / 1000);
-            P.n_src = std::max(1u, std::min(n_src, P.n));
-            P.scratch_off = off;
-            if (P.shares) off += csek::share_scratch_bytes(P.n);
-            B.pools.push_back(P);
-        }
+        J.budget = shares(J.cfg) ? (int)J.cfg.share_every : -1;
+        int rc = init_job(ctx, J, B.stream);
+        if (rc) return rc;
     }
-    if (B.sharing) {
-        HIP_TRY(ctx, hipMalloc((void**)&B.d_share, std::max<size_t>(off, 256)));
-        HIP_TRY(ctx, hipMalloc((void**)&B.d_counts, sizeof(int32_t) * B.pools.size()));
-        HIP_TRY(ctx, hipHostMalloc((void**)&B.h_counts, sizeof(int32_t) * B.pools.size(), hipHostMallocDefault));
+    int rc = build_segments(ctx, B);
+    if (rc) return rc;
+    if (!B.rounds) return launch_groups(ctx, B);
+    for (;;) {
+        rc = round_once(ctx, B);
+        if (rc) return rc;
+        bool any = false;
+        for (int jid : B.jobs) any |= !ctx->jobs[jid].done;
+        if (!any) return CSE_OK;
     }
-    return CSE_OK;
 }
 
 void drop_batch(cse_ctx* ctx, int bid) {
@@ -484,15 +570,36 @@ void drop_batch(cse_ctx* ctx, int bid) {
     if (it == ctx->batches.end()) return;
     BatchRec& B = it->second;
     if (!B.finished && B.ev_done) (void)hipEventSynchronize(B.ev_done);
-    for (int jid : B.jobs) {
-        auto jt = ctx->jobs.find(jid);
-        if (jt != ctx->jobs.end()) {
-            free_job_device(jt->second);
-            ctx->jobs.erase(jt);
-        }
+    std::vector<int> owned;
+    for (auto& kv : ctx->jobs)
+        if (kv.second.batch == bid) owned.push_back(kv.first);
+    for (int jid : owned) {
+        free_job_device(ctx->jobs[jid]);
+        ctx->jobs.erase(jid);
     }
     free_batch_device(B);
     ctx->batches.erase(it);
+}
+
+int new_batch(cse_ctx* ctx, hipStream_t stream, int* bid) {
+    const int id = ctx->next_batch++;
+    BatchRec& B = ctx->batches[id];
+    B.stream = stream;
+    HIP_TRY(ctx, hipMalloc((void**)&B.d_err, 64));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_done, hipEventDisableTiming));
+    *bid = id;
+    return CSE_OK;
+}
+
+// A job's results may be read once its batch has finished and, for server
+// jobs, once the job itself is done.
+int readable(cse_ctx* ctx, int job_id, JobRec** J, int comp) {
+    BatchRec* B = batch_of(ctx, job_id, J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (comp < -1 || comp >= (*J)->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    if ((*J)->server && (*J)->state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "job %d is not done", job_id);
+    if (!(*J)->allocated) return fail(ctx, CSE_EBUSY, "job %d has no results", job_id);
+    return wait_batch(ctx, *B);
 }
 
 }  // namespace
@@ -609,22 +716,19 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
         int rc = validate_cfg(ctx, &cfgs[i]);
         if (rc) return rc;
     }
-    const int bid = ctx->next_batch++;
+    int bid = -1;
+    int rc = new_batch(ctx, (hipStream_t)stream, &bid);
     BatchRec& B = ctx->batches[bid];
-    B.stream = (hipStream_t)stream;
-    int rc = CSE_OK;
     for (int i = 0; i < n && rc == CSE_OK; ++i) {
-        const SchemeRec& sc = ctx->schemes[scheme_ids[i]];
         const int jid = ctx->next_job++;
         JobRec& J = ctx->jobs[jid];
         J.scheme = scheme_ids[i];
         J.cfg = cfgs[i];
-        J.n_comp = sc.n_comp;
         J.batch = bid;
         B.jobs.push_back(jid);
-        for (int c = 0; c < sc.n_comp && rc == CSE_OK; ++c) rc = alloc_comp_job(ctx, sc.comp[c], J.cfg.n_proc, &J.cj[c]);
+        B.rounds |= shares(J.cfg);
+        rc = alloc_job(ctx, J);
     }
-    if (rc == CSE_OK) rc = setup_batch(ctx, B);
     if (rc == CSE_OK) {
         B.finished = false;
         rc = run_batch(ctx, B);
@@ -650,11 +754,12 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
     JobRec* J = nullptr;
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (B->is_server) return fail(ctx, CSE_EINVAL, "server jobs cannot be relaunched");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // On the batch's own stream the earlier run is ordered before the new
     // one; elsewhere, and whenever the host drives rounds, wait for it.
     int rc = CSE_OK;
-    if ((hipStream_t)stream != B->stream || B->sharing) rc = wait_batch(ctx, *B);
+    if ((hipStream_t)stream != B->stream || B->rounds) rc = wait_batch(ctx, *B);
     if (rc) return rc;
     if (cfg) {
         rc = validate_cfg(ctx, cfg);
@@ -665,13 +770,6 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
         rc = wait_batch(ctx, *B);
         if (rc) return rc;
         J->cfg = *cfg;
-        for (csek::Segment& s : B->segs) s.R = run_args(J->cfg);
-        HIP_TRY(ctx, hipMemcpy(B->d_segs, B->segs.data(), sizeof(csek::Segment) * B->segs.size(),
-                               hipMemcpyHostToDevice));
-        for (Pool& P : B->pools) {
-            uint32_t n_src = (uint32_t)(((unsigned long long)P.n * J->cfg.share_src_pm + 999) / 1000);
-            P.n_src = std::max(1u, std::min(n_src, P.n));
-        }
     }
     B->stream = (hipStream_t)stream;
     B->finished = false;
@@ -683,8 +781,10 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
 
 int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done) {
     if (!ctx || !done) return CSE_EINVAL;
-    BatchRec* B = batch_of(ctx, job_id);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (J->server) { *done = J->state == CSE_JOB_DONE; return CSE_OK; }
     if (B->finished) { *done = 1; return CSE_OK; }
     hipError_t e = hipEventQuery(B->ev_done);
     if (e == hipErrorNotReady) { *done = 0; return CSE_OK; }
@@ -696,8 +796,10 @@ int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done) {
 
 int32_t cse_wait(cse_ctx* ctx, int32_t job_id) {
     if (!ctx) return CSE_EINVAL;
-    BatchRec* B = batch_of(ctx, job_id);
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (J->server && J->state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
     return wait_batch(ctx, *B);
 }
 
@@ -706,12 +808,10 @@ int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t
                              int32_t* strat, uint64_t* finish) {
     if (!ctx) return CSE_EINVAL;
     JobRec* J = nullptr;
-    BatchRec* B = batch_of(ctx, job_id, &J);
-    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
-    if (n != (int32_t)J->cfg.n_proc) return fail(ctx, CSE_ERANGE, "n must equal n_proc (%u)", J->cfg.n_proc);
-    int rc = wait_batch(ctx, *B);
+    int rc = readable(ctx, job_id, &J, comp);
     if (rc) return rc;
+    if (comp < 0) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    if (n != (int32_t)J->cfg.n_proc) return fail(ctx, CSE_ERANGE, "n must equal n_proc (%u)", J->cfg.n_proc);
     const csek::UnitState& S = J->cj[comp].st;
     const size_t b4 = (size_t)n * 4, b8 = (size_t)n * 8;
     if (cost) HIP_TRY(ctx, hipMemcpy(cost, S.cost, b4, hipMemcpyDeviceToHost));
@@ -728,14 +828,12 @@ int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t
 int32_t cse_get_programs(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n, int32_t* triples, int32_t cap) {
     if (!ctx || !triples) return CSE_EINVAL;
     JobRec* J = nullptr;
-    BatchRec* B = batch_of(ctx, job_id, &J);
-    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    int rc = readable(ctx, job_id, &J, comp);
+    if (rc) return rc;
+    if (comp < 0) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
     if (n != (int32_t)J->cfg.n_proc) return fail(ctx, CSE_ERANGE, "n must equal n_proc (%u)", J->cfg.n_proc);
     const DevComp& dc = ctx->schemes[J->scheme].comp[comp];
     if (cap < dc.n_fmax) return fail(ctx, CSE_ERANGE, "cap %d < n_fmax %d", cap, dc.n_fmax);
-    int rc = wait_batch(ctx, *B);
-    if (rc) return rc;
     const int nf = std::max(1, dc.n_fmax);
     std::vector<uint32_t> keys((size_t)n * nf);
     std::vector<int32_t> len(n);
@@ -758,13 +856,11 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
                         int32_t* n_fresh, int32_t* cost, int32_t* needed) {
     if (!ctx) return CSE_EINVAL;
     JobRec* J = nullptr;
-    BatchRec* B = batch_of(ctx, job_id, &J);
-    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    if (comp < 0 || comp >= J->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    int rc = readable(ctx, job_id, &J, comp);
+    if (rc) return rc;
+    if (comp < 0) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
     const int n = (int)J->cfg.n_proc;
     if (proc < -1 || proc >= n) return fail(ctx, CSE_EINVAL, "process %d out of range", proc);
-    int rc = wait_batch(ctx, *B);
-    if (rc) return rc;
     std::vector<int32_t> costs(n), len(n);
     HIP_TRY(ctx, hipMemcpy(costs.data(), J->cj[comp].st.cost, (size_t)n * 4, hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(len.data(), J->cj[comp].st.t, (size_t)n * 4, hipMemcpyDeviceToHost));
@@ -793,9 +889,7 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz) {
     if (!ctx) return CSE_EINVAL;
     JobRec* J = nullptr;
-    BatchRec* B = batch_of(ctx, job_id, &J);
-    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    int rc = wait_batch(ctx, *B);
+    int rc = readable(ctx, job_id, &J, -1);
     if (rc) return rc;
     uint64_t last = 0;
     const int n = (int)J->cfg.n_proc;
@@ -809,28 +903,164 @@ int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* 
     return CSE_OK;
 }
 
-int32_t cse_job_release(cse_ctx* ctx, int32_t job_id) {
-    if (!ctx) return CSE_EINVAL;
+}  // extern "C"
+
+namespace {
+int release_job(cse_ctx* ctx, int32_t job_id) {
     JobRec* J = nullptr;
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     const int bid = J->batch;
     if (!B->finished) (void)wait_batch(ctx, *B);
     B->jobs.erase(std::remove(B->jobs.begin(), B->jobs.end(), job_id), B->jobs.end());
-    B->pools.erase(std::remove_if(B->pools.begin(), B->pools.end(), [&](const Pool& p) { return p.job == job_id; }),
-                   B->pools.end());
     free_job_device(*J);
     ctx->jobs.erase(job_id);
-    if (B->jobs.empty()) {
-        drop_batch(ctx, bid);
-        return CSE_OK;
-    }
-    // The remaining jobs of a batch keep their results; relaunching them
-    // uses a table rebuilt without the released job.
-    build_segments(ctx, *B);
-    HIP_TRY(ctx, hipMemcpy(B->d_segs, B->segs.data(), sizeof(csek::Segment) * B->segs.size(),
-                           hipMemcpyHostToDevice));
+    if (!B->is_server && B->jobs.empty()) drop_batch(ctx, bid);
     return CSE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t cse_job_release(cse_ctx* ctx, int32_t job_id) {
+    if (!ctx) return CSE_EINVAL;
+    auto it = ctx->jobs.find(job_id);
+    if (it == ctx->jobs.end()) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (it->second.server) return fail(ctx, CSE_EINVAL, "server job %d is released with cse_server_release", job_id);
+    return release_job(ctx, job_id);
+}
+
+// ---------------------------------------------------------------------------
+// Server: continuous batching of reduction jobs.
+// ---------------------------------------------------------------------------
+
+int32_t cse_server_create(cse_ctx* ctx, uint64_t max_state_bytes, uint32_t round_steps, void* stream,
+                          cse_server** out) {
+    if (!ctx || !out || round_steps == 0) return CSE_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    cse_server* s = new (std::nothrow) cse_server();
+    if (!s) return CSE_ENOMEM;
+    s->ctx = ctx;
+    s->max_bytes = max_state_bytes;
+    s->round_steps = round_steps;
+    int bid = -1;
+    int rc = new_batch(ctx, (hipStream_t)stream, &bid);
+    if (rc) { delete s; return rc; }
+    BatchRec& B = ctx->batches[bid];
+    B.is_server = true;
+    B.rounds = true;
+    s->batch = bid;
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B.stream, B.d_err, 1, 0);
+    *out = s;
+    return CSE_OK;
+}
+
+int32_t cse_server_submit(cse_server* s, int32_t scheme_id, const cse_run_cfg* cfg, int32_t* job_id) {
+    if (!s || !job_id) return CSE_EINVAL;
+    cse_ctx* ctx = s->ctx;
+    if (!ctx->schemes.count(scheme_id)) return fail(ctx, CSE_ENOENT, "unknown scheme %d", scheme_id);
+    int rc = validate_cfg(ctx, cfg);
+    if (rc) return rc;
+    if (job_bytes(ctx, scheme_id, *cfg) > s->max_bytes)
+        return fail(ctx, CSE_ENOMEM, "job needs %zu B, server budget %llu B", job_bytes(ctx, scheme_id, *cfg),
+                    (unsigned long long)s->max_bytes);
+    const int jid = ctx->next_job++;
+    JobRec& J = ctx->jobs[jid];
+    J.scheme = scheme_id;
+    J.cfg = *cfg;
+    J.batch = s->batch;
+    J.server = true;
+    J.state = CSE_JOB_QUEUED;
+    J.t_submit = now_ns();
+    J.n_comp = ctx->schemes[scheme_id].n_comp;
+    s->queue.push_back(jid);
+    *job_id = jid;
+    return CSE_OK;
+}
+
+int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued) {
+    if (!s) return CSE_EINVAL;
+    cse_ctx* ctx = s->ctx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BatchRec& B = ctx->batches[s->batch];
+    // Admission: first come, first served, while the footprint fits.
+    while (!s->queue.empty()) {
+        JobRec& J = ctx->jobs[s->queue.front()];
+        const size_t need = job_bytes(ctx, J.scheme, J.cfg);
+        if (s->used_bytes + need > s->max_bytes) break;
+        int rc = alloc_job(ctx, J);
+        if (rc) { free_job_device(J); return rc; }
+        s->used_bytes += J.bytes;
+        J.budget = shares(J.cfg) ? (int)J.cfg.share_every : (int)s->round_steps;
+        rc = init_job(ctx, J, B.stream);
+        if (rc) return rc;
+        J.state = CSE_JOB_RUNNING;
+        J.t_admit = now_ns();
+        B.jobs.push_back(s->queue.front());
+        s->queue.pop_front();
+        s->dirty = true;
+    }
+    if (!B.jobs.empty()) {
+        if (s->dirty) {
+            int rc = build_segments(ctx, B);
+            if (rc) return rc;
+            s->dirty = false;
+        }
+        B.finished = false;
+        int rc = round_once(ctx, B);
+        B.finished = true;
+        if (rc) return rc;
+        rc = check_err(ctx, B);
+        if (rc) return rc;
+        const uint64_t t = now_ns();
+        std::vector<int> still;
+        for (int jid : B.jobs) {
+            JobRec& J = ctx->jobs[jid];
+            if (J.done) {
+                J.state = CSE_JOB_DONE;
+                J.t_done = t;
+                s->dirty = true;
+            } else {
+                still.push_back(jid);
+            }
+        }
+        B.jobs.swap(still);
+    }
+    if (n_running) *n_running = (int32_t)B.jobs.size();
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return CSE_OK;
+}
+
+int32_t cse_server_job_info(cse_server* s, int32_t job_id, int32_t* state, uint64_t times_ns[3]) {
+    if (!s) return CSE_EINVAL;
+    cse_ctx* ctx = s->ctx;
+    auto it = ctx->jobs.find(job_id);
+    if (it == ctx->jobs.end() || !it->second.server) return fail(ctx, CSE_ENOENT, "unknown server job %d", job_id);
+    if (state) *state = it->second.state;
+    if (times_ns) {
+        times_ns[0] = it->second.t_submit;
+        times_ns[1] = it->second.t_admit;
+        times_ns[2] = it->second.t_done;
+    }
+    return CSE_OK;
+}
+
+int32_t cse_server_release(cse_server* s, int32_t job_id) {
+    if (!s) return CSE_EINVAL;
+    cse_ctx* ctx = s->ctx;
+    auto it = ctx->jobs.find(job_id);
+    if (it == ctx->jobs.end() || !it->second.server) return fail(ctx, CSE_ENOENT, "unknown server job %d", job_id);
+    if (it->second.state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
+    s->used_bytes -= std::min<uint64_t>(s->used_bytes, it->second.bytes);
+    return release_job(ctx, job_id);
+}
+
+void cse_server_destroy(cse_server* s) {
+    if (!s) return;
+    cse_ctx* ctx = s->ctx;
+    (void)hipSetDevice(ctx->device);
+    drop_batch(ctx, s->batch);
+    delete s;
 }
 
 }  // extern "C"

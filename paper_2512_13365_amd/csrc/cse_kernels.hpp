@@ -782,12 +782,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
 }
 
 // Job start stamp and per-unit state initialisation.
-__global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp, int* err) {
+__global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (stamp && i == 0) {
-        *(unsigned long long*)S.t0 = wall_clock64();
-        *err = 0;
-    }
+    if (stamp && i == 0) *(unsigned long long*)S.t0 = wall_clock64();
     if (i >= n_units) return;
     S.t[i] = 0;
     S.cost[i] = 0;

@@ -240,3 +240,96 @@ def test_hbm_state_large_systems(gpu, oracle, rows, cols, p, cap):
     A = workloads.random_system(rows + 7 * cols, rows, cols, p)
     kw = dict(seed=3, n_proc=12, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True, step_cap=cap)
     check_workload(gpu, oracle, [A], kw, f"hbm-state {rows}x{cols}")
+
+
+def test_sharing_6x6x6_full_size_sampled(gpu, oracle):
+    """The 6x6x6 workload at full size (16384 processes, sharing every 32
+    steps): every sampled unit equals the oracle continued from its last
+    restart prefix and epoch (sources and copies are GPU outputs, the rest of
+    the trajectory depends only on the unit's own draws); every sampled
+    program re-expands to its input and ends with no repeated pair."""
+    from cse_helpers import is_terminal
+    cse, ctx, torch = gpu
+    wl = workloads.plain_6x6x6()
+    sc, rs = wl.schemes[0], wl.runs[0]
+    kw = rs.as_kwargs()
+    say(f"[gpu] 6x6x6 full size: n_proc {rs.n_proc}, sharing every {rs.share_every}")
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    info = cse.cse_scheme_info(ctx, sid)
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    cse.cse_wait(ctx, job)
+    rng = np.random.default_rng(0)
+    for c, A in enumerate(sc.systems):
+        got = cse.cse_get_unit_results(ctx, job, c, rs.n_proc)
+        prog = cse.cse_get_programs(ctx, job, c, rs.n_proc, info[c][2])
+        assert got["epoch"].max() > 0 and (got["steps"] > 0).all()
+        best = int(np.argmin(got["cost"]))
+        sample = np.unique(np.concatenate([[0, best], rng.choice(rs.n_proc, 14, replace=False),
+                                           np.flatnonzero(got["epoch"] > 0)[:8]]))
+        for u in sample:
+            F = check_program(A, prog[u, :got["steps"][u]], int(got["cost"][u]))
+            assert is_terminal(F)
+        init = np.zeros((len(sample), prog.shape[1], 3), np.int32)
+        lens = got["k0"][sample]
+        for j, u in enumerate(sample):
+            init[j, :lens[j]] = prog[u, :lens[j]]
+        ocfg = oracle.make_cfg(**dict(kw, share_every=0))
+        ref = oracle.run_pool(A, ocfg, comp=c, procs=sample, init_prog=init, init_len=lens,
+                              init_epoch=got["epoch"][sample], n_threads=THREADS)
+        bad = [int(u) for j, u in enumerate(sample) if not np.array_equal(ref["prog"][j], prog[u])]
+        assert not bad, f"comp {c}: units {bad} differ from the oracle continuation"
+        assert np.array_equal(ref["cost"], got["cost"][sample])
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+
+
+def test_server_continuous_batching(gpu, oracle):
+    """Jobs submitted while others run join later rounds (continuous
+    batching); admission respects the memory budget; every job's units equal
+    those of the oracle, i.e. the same alone and in the mix."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(55)
+    shapes = [(3, 3, 3), (4, 3, 2), (2, 4, 4), (4, 4, 4), (3, 2, 3), (4, 4, 2)]
+    jobs = []
+    for i, (n, m, p) in enumerate(shapes):
+        r = workloads.scheme_rank(n, m, p)
+        U, V, Wt = workloads.scheme_systems(rng, n, m, p, r, 0.2)
+        kw = dict(seed=100 + i, n_proc=48 + 16 * i, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+        if i % 3 != 1:
+            kw.update(share_every=6, share_src_pm=50, share_dst_pm=150, share_max_rounds=30)
+        jobs.append(((U, V, Wt), kw, cse.cse_scheme_load(ctx, U, V, Wt)))
+    srv = cse.cse_server_create(ctx, max_state_bytes=24 << 20, round_steps=5, stream=torch.cuda.current_stream())
+    ids = {}
+    say(f"[gpu] server: {len(jobs)} jobs, budget 24 MiB")
+    pending = list(range(len(jobs)))
+    ticks = 0
+    max_running = 0
+    while pending or any(cse.cse_server_job_info(srv, j)[0] != cse.CSE_JOB_DONE for j in ids.values()):
+        if pending and ticks % 2 == 0:
+            i = pending.pop(0)
+            ids[i] = cse.cse_server_submit(srv, jobs[i][2], cse.cse_run_cfg(**jobs[i][1]))
+        running, queued = cse.cse_server_tick(srv)
+        max_running = max(max_running, running)
+        ticks += 1
+        assert ticks < 2000
+    assert max_running >= 2, "jobs should overlap on the device"
+    for i, ((U, V, Wt), kw, sid) in enumerate(jobs):
+        job = ids[i]
+        st, (t_sub, t_adm, t_done) = cse.cse_server_job_info(srv, job)
+        assert st == cse.CSE_JOB_DONE and t_sub <= t_adm <= t_done
+        ocfg = oracle.make_cfg(**kw)
+        info = cse.cse_scheme_info(ctx, sid)
+        for c, A in enumerate((U, V, Wt)):
+            got = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+            got["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+            ref = oracle.run_pool(A, ocfg, comp=c, n_threads=THREADS)
+            assert_same(got, ref, f"server job {i} comp {c}")
+        cse.cse_server_release(srv, job)
+    cse.cse_server_destroy(srv)
+    tiny = cse.cse_server_create(ctx, max_state_bytes=1000, round_steps=5)
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_server_submit(tiny, jobs[0][2], cse.cse_run_cfg(**jobs[0][1]))
+    assert e.value.status == -2
+    cse.cse_server_destroy(tiny)
+    for _, _, sid in jobs:
+        cse.cse_scheme_free(ctx, sid)
