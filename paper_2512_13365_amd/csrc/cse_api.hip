@@ -85,6 +85,7 @@ struct LaunchGroup {
     uint32_t n_grid = 0;
     size_t lds = 0;
     int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
+    size_t order_begin = 0;         // slice of the batch's dispatch order
 };
 
 struct Pool {  // the units of one component of one job
@@ -97,10 +98,15 @@ struct Pool {  // the units of one component of one job
 struct BatchRec {
     std::vector<int> jobs;            // jobs launched by this batch (unfinished ones for a server)
     std::vector<csek::Segment> segs;  // host copy of the segment table
+    std::vector<int> seg_job;         // job of each segment
     csek::Segment* d_segs = nullptr;
     size_t segs_cap = 0;
     std::vector<LaunchGroup> groups;
     std::vector<Pool> pools;
+    std::vector<uint32_t> order;      // dispatch order of every group, concatenated
+    uint32_t* d_order = nullptr;
+    size_t order_cap = 0;
+    bool built = false;               // tables match the current jobs and configurations
     bool rounds = false;  // host-driven rounds (sharing or server)
     hipStream_t stream = nullptr;
     hipEvent_t ev_done = nullptr;
@@ -239,6 +245,37 @@ int validate_cfg(cse_ctx* ctx, const cse_run_cfg* cfg) {
     return CSE_OK;
 }
 
+// Strategy of a process (the same per-process draw the kernel makes,
+// Sec. 3.5.1), used only to order the dispatch of units.
+uint32_t host_strategy(const cse_run_cfg& cfg, uint32_t proc) {
+    if (cfg.proc0_greedy && proc == 0 && cfg.iteration == 0) return CSE_STRAT_G;
+    uint32_t c0 = proc, c1 = (1u << 28) | ((cfg.iteration & 0x3FFu) << 16), c2 = 0, c3 = 0;
+    uint32_t k0 = (uint32_t)cfg.seed, k1 = (uint32_t)(cfg.seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    uint64_t total = 0;
+    for (int i = 0; i < 7; ++i) total += cfg.weights[i];
+    const uint64_t x = ((uint64_t)c0 * total) >> 32;
+    uint64_t run = 0;
+    for (uint32_t i = 0; i < 7; ++i) {
+        run += cfg.weights[i];
+        if (run > x) return i;
+    }
+    return 0;
+}
+
+// Expected relative work of a unit: steps ~ n_fmax, each scanning the
+// candidates (~m_cap / 64 chunks); gi scores every intersecting pair.
+double unit_cost(const DevComp& c, uint32_t strat) {
+    const double scan = (double)c.n_fmax * (1.0 + c.m_cap / 64.0);
+    return strat == CSE_STRAT_GI ? 4.0 * scan : strat == CSE_STRAT_MIX ? 2.6 * scan : scan;
+}
+
 csek::RunArgs run_args(const JobRec& J) {
     const cse_run_cfg& cfg = J.cfg;
     csek::RunArgs R{};
@@ -346,16 +383,18 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
 
 void free_batch_device(BatchRec& B) {
     if (B.d_segs) (void)hipFree(B.d_segs);
+    if (B.d_order) (void)hipFree(B.d_order);
     if (B.d_err) (void)hipFree(B.d_err);
     if (B.d_counts) (void)hipFree(B.d_counts);
     if (B.h_counts) (void)hipHostFree(B.h_counts);
     if (B.ev_done) (void)hipEventDestroy(B.ev_done);
     B.d_segs = nullptr;
+    B.d_order = nullptr;
     B.d_err = nullptr;
     B.d_counts = nullptr;
     B.h_counts = nullptr;
     B.ev_done = nullptr;
-    B.segs_cap = B.counts_cap = 0;
+    B.segs_cap = B.counts_cap = B.order_cap = 0;
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -363,6 +402,7 @@ void free_batch_device(BatchRec& B) {
 // specialised on both), then uploaded on the batch's stream.
 int build_segments(cse_ctx* ctx, BatchRec& B) {
     B.segs.clear();
+    B.seg_job.clear();
     B.groups.clear();
     B.pools.clear();
     for (int cls = 0; cls < 16; ++cls) {
@@ -388,11 +428,32 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
                 unit += J.cfg.n_proc;
                 G.lds = std::max(G.lds, lds_bytes(dc));
                 B.segs.push_back(s);
+                B.seg_job.push_back(jid);
             }
         }
         G.n_segs = (int)B.segs.size() - G.seg_begin;
         G.n_grid = unit;
         if (G.n_segs) B.groups.push_back(G);
+    }
+    // Longest expected work first, so that the long units do not form the
+    // tail of the launch (unit results do not depend on the order).
+    B.order.clear();
+    for (LaunchGroup& G : B.groups) {
+        G.order_begin = B.order.size();
+        std::vector<std::pair<double, uint32_t>> key;
+        key.reserve(G.n_grid);
+        for (int si = G.seg_begin; si < G.seg_begin + G.n_segs; ++si) {
+            const csek::Segment& sg = B.segs[si];
+            const JobRec* Jp = &ctx->jobs[B.seg_job[si]];
+            const DevComp& dc = ctx->schemes[Jp->scheme].comp[sg.C.comp];
+            for (uint32_t p = 0; p < sg.R.n_units; ++p)
+                key.emplace_back(-unit_cost(dc, host_strategy(Jp->cfg, p)), sg.unit_begin + p);
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<double, uint32_t>& a, const std::pair<double, uint32_t>& b) {
+                             return a.first < b.first;
+                         });
+        for (auto& k : key) B.order.push_back(k.second);
     }
     for (int jid : B.jobs) {
         JobRec& J = ctx->jobs[jid];
@@ -427,44 +488,56 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
         HIP_TRY(ctx, hipMalloc((void**)&B.d_counts, sizeof(int32_t) * B.counts_cap));
         HIP_TRY(ctx, hipHostMalloc((void**)&B.h_counts, sizeof(int32_t) * B.counts_cap, hipHostMallocDefault));
     }
+    if (B.order.size() > B.order_cap) {
+        if (B.d_order) HIP_TRY(ctx, hipFree(B.d_order));
+        B.d_order = nullptr;
+        B.order_cap = std::max<size_t>(B.order.size(), 2 * B.order_cap);
+        HIP_TRY(ctx, hipMalloc((void**)&B.d_order, sizeof(uint32_t) * B.order_cap));
+    }
     if (!B.segs.empty())
         HIP_TRY(ctx, hipMemcpyAsync(B.d_segs, B.segs.data(), sizeof(csek::Segment) * B.segs.size(),
                                     hipMemcpyHostToDevice, B.stream));
+    if (!B.order.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(B.d_order, B.order.data(), sizeof(uint32_t) * B.order.size(),
+                                    hipMemcpyHostToDevice, B.stream));
+    B.built = true;
     return CSE_OK;
 }
 
 template <int W, bool GS>
-int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
+                   int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
     if (G.lds > 65536)
         HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds));
     hipLaunchKernelGGL((csek::step_kernel<W, GS>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
-                       d_segs + G.seg_begin, G.n_segs, G.n_grid, d_err);
+                       d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;
 }
 
 template <bool GS>
-int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, int* d_err, hipStream_t s) {
+int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
+                    int* d_err, hipStream_t s) {
     switch (G.W) {
-    case 1: return launch_group_w<1, GS>(ctx, G, d_segs, d_err, s);
-    case 2: return launch_group_w<2, GS>(ctx, G, d_segs, d_err, s);
-    case 3: return launch_group_w<3, GS>(ctx, G, d_segs, d_err, s);
-    case 4: return launch_group_w<4, GS>(ctx, G, d_segs, d_err, s);
-    case 5: return launch_group_w<5, GS>(ctx, G, d_segs, d_err, s);
-    case 6: return launch_group_w<6, GS>(ctx, G, d_segs, d_err, s);
-    case 7: return launch_group_w<7, GS>(ctx, G, d_segs, d_err, s);
-    case 8: return launch_group_w<8, GS>(ctx, G, d_segs, d_err, s);
+    case 1: return launch_group_w<1, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 2: return launch_group_w<2, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 3: return launch_group_w<3, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 4: return launch_group_w<4, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 5: return launch_group_w<5, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 6: return launch_group_w<6, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 7: return launch_group_w<7, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 8: return launch_group_w<8, GS>(ctx, G, d_segs, d_order, d_err, s);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
     }
 }
 
 int launch_groups(cse_ctx* ctx, BatchRec& B) {
     for (const LaunchGroup& G : B.groups) {
-        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_err, B.stream)
-                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_err, B.stream);
+        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_order, B.d_err, B.stream)
+                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_order, B.d_err, B.stream);
         if (rc) return rc;
     }
     return CSE_OK;
@@ -553,7 +626,7 @@ int run_batch(cse_ctx* ctx, BatchRec& B) {
         int rc = init_job(ctx, J, B.stream);
         if (rc) return rc;
     }
-    int rc = build_segments(ctx, B);
+    int rc = B.built ? CSE_OK : build_segments(ctx, B);
     if (rc) return rc;
     if (!B.rounds) return launch_groups(ctx, B);
     for (;;) {
@@ -770,6 +843,7 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
         rc = wait_batch(ctx, *B);
         if (rc) return rc;
         J->cfg = *cfg;
+        B->built = false;
     }
     B->stream = (hipStream_t)stream;
     B->finished = false;
@@ -915,6 +989,7 @@ int release_job(cse_ctx* ctx, int32_t job_id) {
     B->jobs.erase(std::remove(B->jobs.begin(), B->jobs.end(), job_id), B->jobs.end());
     free_job_device(*J);
     ctx->jobs.erase(job_id);
+    B->built = false;
     if (!B->is_server && B->jobs.empty()) drop_batch(ctx, bid);
     return CSE_OK;
 }

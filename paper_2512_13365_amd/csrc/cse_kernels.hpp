@@ -51,13 +51,11 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;  // one 32x32->64 multiply each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -156,7 +154,7 @@ struct Segment {
 // The bulk (bitsets, candidates, scratch) lives in LDS, or for systems too
 // large for LDS in a per-unit HBM slot; live/vpos always live in LDS.
 struct BulkLayout {
-    size_t colP, colN, cand, newc, M, bytes;
+    size_t colP, colN, cand, newc, M, wt, bytes;
 };
 __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words) {
     BulkLayout L;
@@ -166,6 +164,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     L.cand = o; o += (size_t)m_cap * 8;
     L.newc = o; o += (size_t)newc_cap * 8;
     L.M = o;    o += (size_t)m_words * 8;
+    L.wt = o;   o += ((size_t)m_cap * 2 + 7) & ~size_t(7);
     L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
@@ -537,76 +536,84 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
     return gi_argmax(best_h, best_p);
 }
 
-// Greedy-Intersections, sparse form: M[v][w] marks (bit i of word w) the
+// Greedy-Intersections, sparse form: M[v] marks (bit i of word w) the
 // candidates 64w + i that contain the live variable at position v.  Lane p
-// walks the set bits of M[a] | M[b] (minus p itself) in increasing index,
-// i.e. exactly the intersecting candidates in canonical order, so the coin
-// order is the same as the dense form's.  D_p = T - (c_p - 1) - I_p with I_p
-// the profit of all intersecting candidates.
+// walks the set bits of M[a] | M[b] (minus p itself) word by word in
+// increasing index, i.e. exactly its intersecting candidates in canonical
+// order, so the coin order is the same as the dense form's; coins are taken
+// 32 at a time from the current Philox block.  D_p = T - (c_p - 1) - I_p with
+// I_p the profit of all intersecting candidates.  wt[q] = c_q - 1 is filled
+// on the way.
 __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M,
-                                uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw,
-                                long long* n_int, long long* n_blk) {
+                                uint16_t* wt, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc,
+                                uint32_t dw, long long* n_int, long long* n_blk) {
     const int l = lane_id();
     const int nw = (m + kWave - 1) / kWave;
     for (int i = l; i < n_live * nw; i += kWave) M[i] = 0ull;
     __syncthreads();
+    int tsum = 0;
     for (int base = 0; base < m; base += kWave) {
         const int q = base + l;
         if (q < m) {
-            const uint32_t key = (uint32_t)cand[q];
-            const int w = base / kWave;
+            const uint64_t e = cand[q];
+            const uint32_t key = (uint32_t)e;
+            const int w = entry_c(e) - 1;
+            wt[q] = (uint16_t)w;
+            tsum += w;
+            const int wd = base / kWave;
             const unsigned long long bit = 1ull << l;
-            atomicOr((unsigned long long*)&M[vpos[key_a(key) - 1] * nw + w], bit);
-            atomicOr((unsigned long long*)&M[vpos[key_b(key) - 1] * nw + w], bit);
+            atomicOr((unsigned long long*)&M[vpos[key_a(key) - 1] * nw + wd], bit);
+            atomicOr((unsigned long long*)&M[vpos[key_b(key) - 1] * nw + wd], bit);
         }
     }
+    const int T = wave_sum(tsum);
     __syncthreads();
-    const int T = total_profit(cand, m);
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
-    long long my_int = 0, my_blk = 0;
+    int my_int = 0, my_blk = 0;
     for (int base = 0; base < m; base += kWave) {
         const int p = base + l;
         const bool valid = p < m;
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
         U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
-        uint64_t cw = (uint64_t)blk.x | ((uint64_t)blk.y << 32);
-        int I = 0, X = 0, j = 0;
         if (valid) {
             const uint64_t* Ma = M + vpos[key_a(kp) - 1] * nw;
             const uint64_t* Mb = M + vpos[key_b(kp) - 1] * nw;
+            const int self_w = p >> 6;
+            uint32_t cw = blk.x;  // the next coins, bit 0 first
+            int left = 32, refills = 0;
+            int I = 0, X = 0, j = 0;
             for (int w = 0; w < nw; ++w) {
                 uint64_t u = Ma[w] | Mb[w];
-                if (w == base / kWave) u &= ~(1ull << l);
+                if (w == self_w) u &= ~(1ull << l);
+                j += popc64(u);
                 while (u) {
-                    const int q = (w << 6) + ctz64(u);
-                    u &= u - 1;
-                    const int wq = entry_c(cand[q]) - 1;
+                    const uint32_t lo = (uint32_t)u;
+                    const int bit = lo ? __ffs((int)lo) - 1 : 31 + __ffs((int)(uint32_t)(u >> 32));
+                    u &= u - 1ull;
+                    const int wq = wt[(w << 6) + bit];
                     I += wq;
-                    X += (cw & 1ull) ? wq : 0;
+                    X += wq * (int)(cw & 1u);
                     cw >>= 1;
-                    ++j;
-                    if ((j & 63) == 0) {
-                        if ((j & 127) == 0) {
-                            blk = philox10(proc, dw, kp, (uint32_t)(j >> 7), k0, k1);
-                            cw = (uint64_t)blk.x | ((uint64_t)blk.y << 32);
-                        } else {
-                            cw = (uint64_t)blk.z | ((uint64_t)blk.w << 32);
-                        }
+                    if (--left == 0) {
+                        const int r = (++refills) & 3;
+                        if (r == 0) blk = philox10(proc, dw, kp, (uint32_t)(refills >> 2), k0, k1);
+                        cw = r == 0 ? blk.x : r == 1 ? blk.y : r == 2 ? blk.z : blk.w;
+                        left = 32;
                     }
                 }
             }
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
-            const long long h = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
-            if (h > best_h) { best_h = h; best_p = p; }
+            const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
+            if (hsc > best_h) { best_h = hsc; best_p = p; }
             my_int += j;
             my_blk += (j + 127) >> 7;
         }
     }
-    *n_int = wave_sum64(my_int);
-    *n_blk = wave_sum64(my_blk);
+    *n_int = wave_sum(my_int);
+    *n_blk = wave_sum(my_blk);
     return gi_argmax(best_h, best_p);
 }
 
@@ -636,15 +643,18 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // replaying its program from the input system, counts all pairs once, then
 // runs up to `budget` selection steps (Selection -> Substitution ->
 // incremental Analysis) or until no pair occurs twice / the program reaches
-// step_cap.  Grid unit g maps to segment s and process g - unit_begin.
+// step_cap.  Grid unit g maps to segment s and process g - unit_begin; block
+// b runs grid unit order[b].
 // ---------------------------------------------------------------------------
 template <int W, bool GS>
 __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
-                                                     uint32_t n_grid, int* err) {
+                                                     const uint32_t* __restrict__ order, uint32_t n_grid,
+                                                     int* err) {
     extern __shared__ uint64_t smem[];
     const int l = lane_id();
-    const uint32_t g = blockIdx.x;
-    if (g >= n_grid) return;
+    if (blockIdx.x >= n_grid) return;
+    // Dispatch order: the host lists grid units longest expected work first.
+    const uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
     const Segment& sg = segs[find_segment(segs, n_segs, g)];
     const CompArgs& C = sg.C;
     const RunArgs& R = sg.R;
@@ -661,6 +671,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     uint64_t* cand = (uint64_t*)(bulk + BL.cand);
     uint64_t* newc = (uint64_t*)(bulk + BL.newc);
     uint64_t* M = (uint64_t*)(bulk + BL.M);
+    uint16_t* wt = (uint16_t*)(bulk + BL.wt);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
 
@@ -743,8 +754,8 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
-                pick = select_gi_sparse(cand, m, vpos, n_live, M, alpha_q, beta_q, k0, k1, proc, dw, &n_int,
-                                        &n_blk);
+                pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw,
+                                        &n_int, &n_blk);
             else
                 pick = select_gi_dense(cand, m, alpha_q, beta_q, k0, k1, proc, dw, &n_int, &n_blk);
         }
