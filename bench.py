@@ -10,8 +10,10 @@ region is K back-to-back relaunches of the job on one stream, bracketed by
 device synchronisation, timed with HIP events on that stream.
 
 Prints one JSON line: substitution steps per second (all units), time to
-the best addition count, the roofline position of the step kernel, and the
-CPU oracle timed on the host cores.
+the best addition count, the roofline position of the step kernel, the CPU
+oracle timed on the host cores, and batched vs plain launches of 32 uneven
+schemes.  Other workloads (--workload 6x6x6 | batch | serve) print their own
+line.
 """
 import argparse
 import json
@@ -35,7 +37,7 @@ def log(*a):
 
 def time_to_best(res, tick_hz):
     """Per component: (best cost, seconds from job start until a unit with
-    that cost finished); scheme total = sum of bests, latest of the times."""
+    that cost finished)."""
     out = []
     for r in res:
         best = int(r["cost"].min())
@@ -53,8 +55,237 @@ def cpu_baseline(systems, kw, n_threads):
     for c, A in enumerate(systems):
         r = cse_oracle.run_pool(A, cfg, comp=c, n_threads=n_threads)
         steps += int(r["executed"].sum())
-    dt = time.perf_counter() - t0
-    return steps, dt
+    return steps, time.perf_counter() - t0
+
+
+def job_results(cse, ctx, job, n_proc, n_comp=3):
+    return [cse.cse_get_unit_results(ctx, job, c, n_proc) for c in range(n_comp)]
+
+
+def base_line(args, **kw):
+    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic"}
+    out.update(kw)
+    return out
+
+
+def timed_relaunch(cse, ctx, job, stream, torch, steps, warmup):
+    for _ in range(warmup):
+        cse.cse_relaunch(ctx, job, None, stream)
+    cse.cse_wait(ctx, job)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        cse.cse_relaunch(ctx, job, None, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    cse.cse_wait(ctx, job)
+    return ev0.elapsed_time(ev1) / 1e3
+
+
+def run_plain44(args, cse, workloads, torch, ctx, stream):
+    wl = workloads.plain_4x4x4()
+    sc, rs = wl.schemes[0], wl.runs[0]
+    kw = rs.as_kwargs()
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    info = cse.cse_scheme_info(ctx, sid)
+    log(f"[bench] workload {wl.name}: shapes {[A.shape for A in sc.systems]} n_proc {rs.n_proc}")
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), stream)
+    cse.cse_wait(ctx, job)
+    gpu_s = timed_relaunch(cse, ctx, job, stream, torch, args.steps, args.warmup)
+    log(f"[bench] timed {args.steps} steps: {gpu_s * 1e3:.3f} ms device")
+    res = job_results(cse, ctx, job, rs.n_proc)
+    _, tick_hz = cse.cse_job_timing(ctx, job)
+    subs = sum(int(r["executed"].sum()) for r in res)
+    ops = sum(int(r["ops"].sum()) for r in res)
+    ttb = time_to_best(res, tick_hz)
+    per_step = gpu_s / args.steps
+    launches = 1  # one step-kernel launch covers the three components of the job
+    avg_launch = per_step / launches
+    achieved = (ops / launches) / avg_launch
+    out = base_line(
+        args, value=subs * args.steps / gpu_s, unit="substitution steps/s", ms_per_step=per_step * 1e3,
+        config={"workload": "plain-4x4x4-r49: U,V 49x16, W^T 16x49 ternary, p=0.30, row nnz in [1,8]; "
+                            "4096 processes gi/ga/wr 1:1:1; seed 0; no sharing",
+                "n_proc": rs.n_proc, "units": 3 * rs.n_proc, "substitutions_per_step": subs},
+        time_to_best_ms={"U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
+                         "scheme": max(t for _, t in ttb) * 1e3},
+        best_additions={"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0], "scheme": sum(b for b, _ in ttb),
+                        "naive": sum(i[3] for i in info)},
+        roofline={"kernel": "step_kernel<1, false>", "bound": "alu", "achieved": achieved / 1e12,
+                  "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
+                  "traffic": None, "algorithmic_ops_per_launch": ops / launches,
+                  "avg_launch_ms": avg_launch * 1e3})
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    if not args.no_cpu_baseline:
+        n_threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu oracle on {n_threads} threads (full workload)")
+        steps, dt = cpu_baseline(sc.systems, kw, n_threads)
+        out["cpu_baseline"] = {"value": steps / dt, "unit": "substitution steps/s", "cores": n_threads,
+                               "kind": "oracle",
+                               "sample": f"full workload: {rs.n_proc} processes x 3 components, "
+                                         f"{steps} substitutions in {dt:.2f} s"}
+    return out
+
+
+def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2):
+    """32 uneven schemes: one batched launch vs 32 sequential plain launches,
+    same pools and seeds (so the same results)."""
+    wl = workloads.batch_uneven()
+    sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc in wl.schemes]
+    cfgs = [cse.cse_run_cfg(**rs.as_kwargs()) for rs in wl.runs]
+    n_procs = [rs.n_proc for rs in wl.runs]
+    stats = {}
+    for mode in ("batched", "plain"):
+        best_t = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "batched":
+                jobs = cse.cse_launch_batch(ctx, sids, cfgs, stream)
+                for j in jobs:
+                    cse.cse_wait(ctx, j)
+                starts = [0.0] * len(jobs)
+            else:
+                jobs, starts = [], []
+                for s, c in zip(sids, cfgs):
+                    starts.append(time.perf_counter() - t0)
+                    j = cse.cse_launch(ctx, s, c, stream)
+                    cse.cse_wait(ctx, j)
+                    jobs.append(j)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            steps, bests, ttbs = 0, [], []
+            for j, n, st in zip(jobs, n_procs, starts):
+                res = job_results(cse, ctx, j, n)
+                _, hz = cse.cse_job_timing(ctx, j)
+                steps += sum(int(r["executed"].sum()) for r in res)
+                tb = time_to_best(res, hz)
+                bests.append(sum(b for b, _ in tb))
+                ttbs.append(st + max(t for _, t in tb))
+            for j in jobs:
+                cse.cse_job_release(ctx, j)
+            if best_t is None or dt < best_t:
+                best_t = dt
+                stats[mode] = {"seconds": dt, "substitutions": steps, "steps_per_s": steps / dt,
+                               "mean_time_to_best_ms": 1e3 * sum(ttbs) / len(ttbs),
+                               "max_time_to_best_ms": 1e3 * max(ttbs), "best_additions": bests}
+        log(f"[bench] batch-32 {mode}: {stats[mode]['seconds'] * 1e3:.1f} ms, "
+            f"{stats[mode]['steps_per_s'] / 1e6:.1f} M steps/s")
+    for s in sids:
+        cse.cse_scheme_free(ctx, s)
+    same = stats["batched"]["best_additions"] == stats["plain"]["best_additions"]
+    return {"workload": "batch-32-uneven: (n,m,p) in {2..7}^3, r=round((nmp)^0.93), p=0.2; pools ~ r summing "
+                        "to 65536; paper weights; sharing 32 steps 1% -> 10%",
+            "batched": {k: v for k, v in stats["batched"].items() if k != "best_additions"},
+            "plain": {k: v for k, v in stats["plain"].items() if k != "best_additions"},
+            "speedup": stats["batched"]["steps_per_s"] / stats["plain"]["steps_per_s"],
+            "scheme_best_additions": stats["batched"]["best_additions"], "identical_results": same}
+
+
+def run_6x6x6(args, cse, workloads, torch, ctx, stream):
+    wl = workloads.plain_6x6x6()
+    sc, rs = wl.schemes[0], wl.runs[0]
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    info = cse.cse_scheme_info(ctx, sid)
+    cfg = cse.cse_run_cfg(**rs.as_kwargs())
+    job = cse.cse_launch(ctx, sid, cfg, stream)
+    cse.cse_wait(ctx, job)
+    gpu_s = timed_relaunch(cse, ctx, job, stream, torch, args.steps, args.warmup)
+    res = job_results(cse, ctx, job, rs.n_proc)
+    _, tick_hz = cse.cse_job_timing(ctx, job)
+    subs = sum(int(r["executed"].sum()) for r in res)
+    ttb = time_to_best(res, tick_hz)
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    return base_line(
+        args, value=subs * args.steps / gpu_s, unit="substitution steps/s",
+        ms_per_step=gpu_s / args.steps * 1e3,
+        config={"workload": "plain-6x6x6-r160: U,V 160x36, W^T 36x160, p=0.15, row nnz in [1,12]; 16384 "
+                            "processes, paper weights, proc0 = g; sharing every 32 steps, 1% -> 10%",
+                "n_proc": rs.n_proc, "substitutions_per_step": subs},
+        time_to_best_ms={"U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
+                         "scheme": max(t for _, t in ttb) * 1e3},
+        best_additions={"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0], "scheme": sum(b for b, _ in ttb),
+                        "naive": sum(i[3] for i in info)})
+
+
+def run_serve(args, cse, workloads, torch, ctx, stream):
+    """Poisson stream of jobs: a continuous-batching server vs one plain
+    launch per job in arrival order; latency = completion - arrival."""
+    import numpy as np
+    wl = workloads.serving_stream(n_jobs=args.jobs)
+    sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc in wl.schemes]
+    cfgs = [cse.cse_run_cfg(**rs.as_kwargs()) for rs in wl.runs]
+    arr = wl.arrivals_s
+    out = {}
+    # Served.
+    srv = cse.cse_server_create(ctx, max_state_bytes=args.serve_budget_gib << 30, round_steps=32, stream=stream)
+    ids = {}
+    t0 = time.perf_counter()
+    nxt = 0
+    done_t = {}
+    steps = 0
+    while len(done_t) < len(cfgs):
+        now = time.perf_counter() - t0
+        while nxt < len(cfgs) and arr[nxt] <= now:
+            ids[nxt] = cse.cse_server_submit(srv, sids[nxt], cfgs[nxt])
+            nxt += 1
+        running, queued = cse.cse_server_tick(srv)
+        now = time.perf_counter() - t0
+        for i, j in list(ids.items()):
+            if i in done_t:
+                continue
+            st, _ = cse.cse_server_job_info(srv, j)
+            if st == cse.CSE_JOB_DONE:
+                done_t[i] = now
+                steps += sum(int(cse.cse_get_unit_results(ctx, j, c, cfgs[i].n_proc)["executed"].sum())
+                             for c in range(3))
+                cse.cse_server_release(srv, j)
+                if len(done_t) % 50 == 0:
+                    log(f"[bench] served {len(done_t)}/{len(cfgs)}")
+        if running == 0 and queued == 0 and nxt < len(cfgs):
+            time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    cse.cse_server_destroy(srv)
+    lat = np.array([done_t[i] - arr[i] for i in range(len(cfgs))])
+    out["served"] = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                     "steps_per_s": steps / wall, "wall_s": wall, "substitutions": steps}
+    log(f"[bench] served: p50 {out['served']['p50_latency_ms']:.1f} ms p99 {out['served']['p99_latency_ms']:.1f} ms")
+    # Plain per-job launches in arrival order.
+    t0 = time.perf_counter()
+    lat = []
+    steps = 0
+    for i, (sid, cfg) in enumerate(zip(sids, cfgs)):
+        now = time.perf_counter() - t0
+        if arr[i] > now:
+            time.sleep(arr[i] - now)
+        j = cse.cse_launch(ctx, sid, cfg, stream)
+        cse.cse_wait(ctx, j)
+        lat.append(time.perf_counter() - t0 - arr[i])
+        steps += sum(int(cse.cse_get_unit_results(ctx, j, c, cfg.n_proc)["executed"].sum()) for c in range(3))
+        cse.cse_job_release(ctx, j)
+        if (i + 1) % 50 == 0:
+            log(f"[bench] plain {i + 1}/{len(cfgs)}")
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    out["plain"] = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+                    "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                    "steps_per_s": steps / wall, "wall_s": wall, "substitutions": steps}
+    for s in sids:
+        cse.cse_scheme_free(ctx, s)
+    return base_line(
+        args, value=out["served"]["steps_per_s"], unit="substitution steps/s",
+        ms_per_step=None,
+        config={"workload": f"serve-poisson: {args.jobs} jobs, exponential gaps mean 50 ms; (n,m,p) in "
+                            "{2..8}^3, r=round((nmp)^0.93), p=0.12; 2048 processes per job, paper weights, "
+                            "step cap 4000, sharing 32 steps 1% -> 10%"},
+        serving=out)
 
 
 def main():
@@ -62,7 +293,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
+    ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
+    ap.add_argument("--serve-budget-gib", type=int, default=96, help="serving: device state budget")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -71,7 +306,6 @@ def main():
               "runs on a single MI355X (see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2512_13365_amd import cse, workloads
@@ -87,98 +321,22 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_calibrate} MiB read + {args.copy_calibrate} MiB written")
         del src, dst
-    wl = workloads.plain_4x4x4()
-    sc, rs = wl.schemes[0], wl.runs[0]
-    kw = rs.as_kwargs()
     ctx = cse.cse_ctx_create(0)
-    sid = cse.cse_scheme_load(ctx, *sc.systems)
-    info = cse.cse_scheme_info(ctx, sid)
-    cfg = cse.cse_run_cfg(**kw)
-    log(f"[bench] workload {wl.name}: shapes {[A.shape for A in sc.systems]} n_proc {rs.n_proc}")
-
-    job = cse.cse_launch(ctx, sid, cfg, stream)
-    cse.cse_wait(ctx, job)
-    for _ in range(args.warmup):
-        cse.cse_relaunch(ctx, job, None, stream)
-    cse.cse_wait(ctx, job)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        cse.cse_relaunch(ctx, job, None, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    cse.cse_wait(ctx, job)
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    log(f"[bench] timed {args.steps} steps: {gpu_s * 1e3:.3f} ms device, {wall * 1e3:.3f} ms host")
-
-    res = [cse.cse_get_unit_results(ctx, job, c, rs.n_proc) for c in range(3)]
-    _, tick_hz = cse.cse_job_timing(ctx, job)
-    subs = sum(int(r["executed"].sum()) for r in res)
-    ops = sum(int(r["ops"].sum()) for r in res)
-    ttb = time_to_best(res, tick_hz)
-    per_step = gpu_s / args.steps
-    launches = 1  # one step-kernel launch covers the three components of the job
-    avg_launch = per_step / launches
-    achieved = (ops / launches) / avg_launch
-
-    out = {
-        "metric": METRIC,
-        "value": subs * args.steps / gpu_s,
-        "unit": "substitution steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": per_step * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": "plain-4x4x4-r49: U,V 49x16, W^T 16x49 ternary, p=0.30, row nnz in [1,8]; "
-                        "4096 processes gi/ga/wr 1:1:1; seed 0; no sharing",
-            "n_proc": rs.n_proc,
-            "units": 3 * rs.n_proc,
-            "substitutions_per_step": subs,
-        },
-        "time_to_best_ms": {
-            "U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
-            "scheme": max(t for _, t in ttb) * 1e3,
-        },
-        "best_additions": {"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0],
-                           "scheme": sum(b for b, _ in ttb),
-                           "naive": sum(i[3] for i in info)},
-        "roofline": {
-            "kernel": "step_kernel<1, false>",
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_ALU_OPS / 1e12,
-            "unit": "T int32 lane-op/s",
-            "frac": achieved / PEAK_ALU_OPS,
-            "traffic": None,
-            "algorithmic_ops_per_launch": ops / launches,
-            "avg_launch_ms": avg_launch * 1e3,
-        },
-    }
-
-    if not args.no_cpu_baseline:
-        n_threads = min(16, os.cpu_count() or 1)
-        log(f"[bench] cpu oracle on {n_threads} threads (full workload)")
-        steps, dt = cpu_baseline(sc.systems, kw, n_threads)
-        out["cpu_baseline"] = {"value": steps / dt, "unit": "substitution steps/s", "cores": n_threads,
-                               "kind": "oracle",
-                               "sample": f"full workload: {rs.n_proc} processes x 3 components, "
-                                         f"{steps} substitutions in {dt:.2f} s"}
-    cse.cse_job_release(ctx, job)
-    cse.cse_scheme_free(ctx, sid)
-    cse.cse_ctx_destroy(ctx)
+    try:
+        if args.workload == "4x4x4":
+            out = run_plain44(args, cse, workloads, torch, ctx, stream)
+            if not args.no_batch:
+                out["batched_vs_plain"] = batch_vs_plain(cse, workloads, torch, ctx, stream)
+        elif args.workload == "6x6x6":
+            out = run_6x6x6(args, cse, workloads, torch, ctx, stream)
+        elif args.workload == "batch":
+            bp = batch_vs_plain(cse, workloads, torch, ctx, stream)
+            out = base_line(args, value=bp["batched"]["steps_per_s"], unit="substitution steps/s",
+                            ms_per_step=None, config={"workload": bp["workload"]}, batched_vs_plain=bp)
+        else:
+            out = run_serve(args, cse, workloads, torch, ctx, stream)
+    finally:
+        cse.cse_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
 
 

@@ -43,11 +43,14 @@ uint64_t now_ns() {
 }
 
 struct DevComp {
-    int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0;
-    bool gs = false;  // bulk state in HBM
+    int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0, m0 = 0;
+    bool gs = false;   // bulk state in HBM
+    bool adj = false;  // gi over per-variable ranges (large candidate sets)
     long long occ0 = 0;
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
+    uint64_t* d_cand0 = nullptr;  // candidates of the input system, canonical order
+    uint32_t* d_tl0 = nullptr;    // the same by (second, first, sign)
 };
 
 struct SchemeRec {
@@ -161,7 +164,7 @@ int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
     } while (0)
 
 size_t bulk_bytes(const DevComp& c) {
-    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words).bytes;
+    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0).bytes;
 }
 size_t lds_bytes(const DevComp& c) {
     return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
@@ -200,7 +203,6 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
     const long long full_masks = (long long)n_vmax * ((c.m_cap + 63) / 64);
     c.m_words = (int)std::min<long long>(full_masks, kMaskBudgetWords);
-    c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
     std::vector<uint64_t> P((size_t)cols * c.W, 0), N((size_t)cols * c.W, 0);
     for (int i = 0; i < rows; ++i)
         for (int j = 0; j < cols; ++j) {
@@ -208,11 +210,42 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
             if (v > 0) P[(size_t)j * c.W + i / 64] |= 1ull << (i % 64);
             if (v < 0) N[(size_t)j * c.W + i / 64] |= 1ull << (i % 64);
         }
+    // The input's candidates, shared by every unit at its first step: pairs
+    // (a, b) with a < b in canonical order, '+' before '-', kept when c >= 2.
+    std::vector<uint64_t> cand0;
+    for (int a = 0; a < cols; ++a)
+        for (int b = a + 1; b < cols; ++b) {
+            int cp = 0, cm = 0;
+            for (int w = 0; w < c.W; ++w) {
+                const uint64_t Pa = P[(size_t)a * c.W + w], Na = N[(size_t)a * c.W + w];
+                const uint64_t Pb = P[(size_t)b * c.W + w], Nb = N[(size_t)b * c.W + w];
+                cp += __builtin_popcountll(Pa & Pb) + __builtin_popcountll(Na & Nb);
+                cm += __builtin_popcountll(Pa & Nb) + __builtin_popcountll(Na & Pb);
+            }
+            const uint64_t key = ((uint64_t)(a + 1) << 16) | ((uint64_t)(b + 1) << 1);
+            if (cp >= 2) cand0.push_back(key | ((uint64_t)cp << 32));
+            if (cm >= 2) cand0.push_back(key | 1ull | ((uint64_t)cm << 32));
+        }
+    c.m0 = (int)cand0.size();
+    std::vector<uint32_t> tl0(cand0.size());
+    for (size_t i = 0; i < tl0.size(); ++i) tl0[i] = (uint32_t)i;
+    std::stable_sort(tl0.begin(), tl0.end(), [&](uint32_t x, uint32_t y) {
+        return ((cand0[x] >> 1) & 0x7FFFu) < ((cand0[y] >> 1) & 0x7FFFu);
+    });
+    // Large candidate sets walk per-variable ranges in gi instead of masks.
+    c.adj = (long long)cols * ((c.m0 + 63) / 64) > kMaskBudgetWords * 3 / 4;
+    c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
     const size_t bytes = P.size() * 8;
     HIP_TRY(ctx, hipMalloc(&c.d_P, bytes));
     HIP_TRY(ctx, hipMalloc(&c.d_N, bytes));
     HIP_TRY(ctx, hipMemcpy(c.d_P, P.data(), bytes, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(c.d_N, N.data(), bytes, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMalloc(&c.d_cand0, std::max<size_t>(1, cand0.size()) * 8));
+    HIP_TRY(ctx, hipMalloc(&c.d_tl0, std::max<size_t>(1, tl0.size()) * 4));
+    if (!cand0.empty()) {
+        HIP_TRY(ctx, hipMemcpy(c.d_cand0, cand0.data(), cand0.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemcpy(c.d_tl0, tl0.data(), tl0.size() * 4, hipMemcpyHostToDevice));
+    }
     *out = c;
     return CSE_OK;
 }
@@ -220,7 +253,10 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
 void free_component(DevComp& c) {
     if (c.d_P) (void)hipFree(c.d_P);
     if (c.d_N) (void)hipFree(c.d_N);
-    c.d_P = c.d_N = nullptr;
+    if (c.d_cand0) (void)hipFree(c.d_cand0);
+    if (c.d_tl0) (void)hipFree(c.d_tl0);
+    c.d_P = c.d_N = c.d_cand0 = nullptr;
+    c.d_tl0 = nullptr;
 }
 
 bool shares(const cse_run_cfg& c) { return c.share_every > 0 && c.share_src_pm > 0 && c.share_max_rounds > 0; }
@@ -295,6 +331,10 @@ csek::CompArgs comp_args(const DevComp& c, int comp) {
     csek::CompArgs C{};
     C.P0 = c.d_P;
     C.N0 = c.d_N;
+    C.cand0 = c.d_cand0;
+    C.tl0 = c.d_tl0;
+    C.m0 = c.m0;
+    C.adj = c.adj ? 1 : 0;
     C.n_e = c.n_e;
     C.n_x = c.n_x;
     C.n_fmax = c.n_fmax;

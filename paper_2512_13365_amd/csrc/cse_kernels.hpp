@@ -105,14 +105,17 @@ __device__ __forceinline__ int entry_c(uint64_t e) { return (int)((e >> 32) & 0x
 // Kernel arguments.
 // ---------------------------------------------------------------------------
 struct CompArgs {
-    const uint64_t* P0;   // n_x columns of W words: positive coefficients
-    const uint64_t* N0;   // negative coefficients
+    const uint64_t* P0;    // n_x columns of W words: positive coefficients
+    const uint64_t* N0;    // negative coefficients
+    const uint64_t* cand0; // candidates of the input system, canonical order
+    const uint32_t* tl0;   // the same ordered by (second, first, sign): indices into cand0
     int32_t n_e, n_x, n_fmax, m_cap;
-    int32_t naive0;
+    int32_t naive0, m0;    // naive count and number of candidates of the input
     uint32_t comp;
-    int32_t prog_stride;  // max(1, n_fmax): program entries per unit
-    int32_t newc_cap;     // capacity of the fresh-variable pair list
-    int32_t m_words;      // capacity of the gi masks (64-bit words)
+    int32_t prog_stride;   // max(1, n_fmax): program entries per unit
+    int32_t newc_cap;      // capacity of the fresh-variable pair list
+    int32_t m_words;       // capacity of the gi masks (64-bit words)
+    int32_t adj;           // 1: gi walks per-variable ranges (large candidate sets)
     int32_t pad;
 };
 
@@ -153,18 +156,27 @@ struct Segment {
 // Layout of a unit's state (the host sizes launches with the same formulas).
 // The bulk (bitsets, candidates, scratch) lives in LDS, or for systems too
 // large for LDS in a per-unit HBM slot; live/vpos always live in LDS.
+// Systems with large candidate sets (adj) keep a second candidate buffer,
+// the candidates ordered by (second, first, sign), an index remap and
+// per-variable ranges instead of the gi masks.
 struct BulkLayout {
-    size_t colP, colN, cand, newc, M, wt, bytes;
+    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, bytes;
 };
-__host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words) {
+__host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words,
+                                                  int adj) {
     BulkLayout L;
     size_t o = 0;
-    L.colP = o; o += (size_t)n_vmax * W * 8;
-    L.colN = o; o += (size_t)n_vmax * W * 8;
-    L.cand = o; o += (size_t)m_cap * 8;
-    L.newc = o; o += (size_t)newc_cap * 8;
-    L.M = o;    o += (size_t)m_words * 8;
-    L.wt = o;   o += ((size_t)m_cap * 2 + 7) & ~size_t(7);
+    L.colP = o;  o += (size_t)n_vmax * W * 8;
+    L.colN = o;  o += (size_t)n_vmax * W * 8;
+    L.cand = o;  o += (size_t)m_cap * 8;
+    L.cand2 = o; o += adj ? (size_t)m_cap * 8 : 0;
+    L.newc = o;  o += (size_t)newc_cap * 8;
+    L.M = o;     o += adj ? 0 : (size_t)m_words * 8;
+    L.wt = o;    o += adj ? 0 : ((size_t)m_cap * 2 + 7) & ~size_t(7);
+    L.tl = o;    o += adj ? (size_t)m_cap * 4 : 0;
+    L.remap = o; o += adj ? (size_t)m_cap * 4 : 0;
+    L.kpre = o;  o += adj ? ((size_t)m_cap * 4 + 8) & ~size_t(7) : 0;
+    L.rng = o;   o += adj ? (size_t)n_vmax * 16 : 0;
     L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
@@ -486,6 +498,265 @@ __device__ __forceinline__ int gi_argmax(long long best_h, int best_p) {
     return wave_min(best_h == hmax ? best_p : 0x7FFFFFFF);
 }
 
+// Incremental Analysis for large candidate sets, double-buffered: the same
+// update as update_candidates, written from src into dst in one pass.  Each
+// kept pair lands at (kept pairs before it) + (new pairs with a smaller first
+// variable); each new pair (x, k) at its index + (kept pairs with first
+// variable <= x).  remap[i] receives the new index of old pair i (-1 when
+// dropped) and the new pairs' indices are kept in bits 42+ of newc, for the
+// maintenance of the second ordering.  Returns the new count; *n_new_out
+// receives the number of new pairs.
+template <int W>
+__device__ int update_candidates_db(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                                    const uint64_t* src, int m, uint64_t* dst, uint64_t* newc, int newc_cap,
+                                    int m_cap, int32_t* remap, int32_t* kpre, int a, int b, int k, int* n_new_out,
+                                    int* err_flags) {
+    const int l = lane_id();
+    // 1. Pairs of the fresh variable k (the last live entry), by first variable.
+    int n_new = 0;
+    for (int base = 0; base < n_live - 1; base += kWave) {
+        const int i = base + l;
+        const bool valid = i < n_live - 1;
+        const int x = valid ? (int)live[i] : k;
+        const int2 c = valid ? pair_counts<W>(colP, colN, x - 1, k - 1) : make_int2(0, 0);
+        const bool hp = c.x >= 2, hm = c.y >= 2;
+        const uint64_t bp = ballot(hp), bm = ballot(hm);
+        const int pos = n_new + lanes_below(bp) + lanes_below(bm);
+        if (hp) {
+            if (pos < newc_cap) newc[pos] = pair_key(x, k, 0) | ((uint64_t)c.x << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        if (hm) {
+            const int q = pos + (hp ? 1 : 0);
+            if (q < newc_cap) newc[q] = pair_key(x, k, 1) | ((uint64_t)c.y << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        n_new += popc64(bp) + popc64(bm);
+    }
+    if (n_new > newc_cap) n_new = newc_cap;
+    __syncthreads();
+    // 2. Old pairs: recount those touching a or b, keep c >= 2, place.
+    int mf = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int i = base + l;
+        const bool valid = i < m;
+        uint64_t e = valid ? src[i] : 0ull;
+        const uint32_t key = (uint32_t)e;
+        const int qa = key_a(key), qb = key_b(key);
+        int c = entry_c(e);
+        if (valid && (qa == a || qa == b || qb == a || qb == b)) {
+            const int2 cc = pair_counts<W>(colP, colN, qa - 1, qb - 1);
+            c = (key & 1u) ? cc.y : cc.x;
+            e = (uint64_t)key | ((uint64_t)c << 32);
+        }
+        const bool keep = valid && c >= 2;
+        const uint64_t bk = ballot(keep);
+        const int kept = mf + lanes_below(bk);
+        if (valid) {
+            int lo = 0, hi = n_new;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)newc[mid]) < qa) lo = mid + 1; else hi = mid;
+            }
+            const int dest = kept + lo;
+            kpre[i] = kept;
+            if (keep) {
+                if (dest < m_cap) dst[dest] = e;
+                else *err_flags |= ERR_CAND_OVERFLOW;
+            }
+            remap[i] = keep ? dest : -1;
+        }
+        mf += popc64(bk);
+    }
+    if (l == 0) kpre[m] = mf;
+    if (mf + n_new > m_cap) { *err_flags |= ERR_CAND_OVERFLOW; n_new = m_cap > mf ? m_cap - mf : 0; }
+    __syncthreads();
+    // 3. New pairs.
+    for (int base = 0; base < n_new; base += kWave) {
+        const int e = base + l;
+        if (e < n_new) {
+            const uint64_t v = newc[e] & ((1ull << 42) - 1);
+            const int x = key_a((uint32_t)v);
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)src[mid]) <= x) lo = mid + 1; else hi = mid;
+            }
+            const int dest = e + kpre[lo];
+            dst[dest] = v;
+            newc[e] = v | ((uint64_t)dest << 42);
+        }
+    }
+    __syncthreads();
+    *n_new_out = n_new;
+    return mf + n_new;
+}
+
+// The candidates ordered by (second, first, sign), as indices into the
+// canonical list, after an update: kept entries keep their relative order
+// (their keys did not change) and take their new indices; the new pairs
+// (x, k) all have the largest second variable k and come last, by x.
+__device__ void update_tl(uint32_t* tl, int m_old, const int32_t* remap, const uint64_t* newc, int n_new) {
+    const int l = lane_id();
+    int mt = 0;
+    for (int base = 0; base < m_old; base += kWave) {
+        const int i = base + l;
+        const int v = i < m_old ? remap[tl[i]] : -1;
+        const bool keep = v >= 0;
+        const uint64_t bk = ballot(keep);
+        __syncthreads();
+        if (keep) tl[mt + lanes_below(bk)] = (uint32_t)v;
+        mt += popc64(bk);
+    }
+    __syncthreads();
+    for (int base = 0; base < n_new; base += kWave) {
+        const int e = base + l;
+        if (e < n_new) tl[mt + e] = (uint32_t)(newc[e] >> 42);
+    }
+    __syncthreads();
+}
+
+// Second ordering from scratch after a full Analysis: enumerate pairs by
+// (second, first) position in the live list, count them again, and look up
+// each kept pair's index in the canonical list.
+template <int W>
+__device__ void build_tl(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                         const uint64_t* cand, int m, uint32_t* tl) {
+    const int l = lane_id();
+    int mt = 0;
+    for (int j = 1; j < n_live; ++j) {
+        const int b = (int)live[j];
+        for (int ib = 0; ib < j; ib += kWave) {
+            const int i = ib + l;
+            const bool valid = i < j;
+            const int a = valid ? (int)live[i] : b;
+            const int2 c = valid ? pair_counts<W>(colP, colN, a - 1, b - 1) : make_int2(0, 0);
+            const bool hp = c.x >= 2, hm = c.y >= 2;
+            const uint64_t bp = ballot(hp), bm = ballot(hm);
+            const int pos = mt + lanes_below(bp) + lanes_below(bm);
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const bool has = sgn ? hm : hp;
+                if (!has) continue;
+                const uint32_t key = pair_key(a, b, sgn);
+                int lo = 0, hi = m;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((uint32_t)cand[mid] < key) lo = mid + 1; else hi = mid;
+                }
+                const int q = pos + (sgn && hp ? 1 : 0);
+                if (q < m) tl[q] = (uint32_t)lo;
+            }
+            mt += popc64(bp) + popc64(bm);
+        }
+    }
+    __syncthreads();
+}
+
+// Per-variable ranges for gi: fs/fe = the canonical-list range of the pairs
+// whose first variable is v, ts/te = the range in the second ordering of the
+// pairs whose second variable is v (indexed by live position).
+__device__ void gi_ranges(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
+                          int32_t* rng) {
+    const int l = lane_id();
+    int32_t* fs = rng;
+    int32_t* fe = rng + n_live;
+    int32_t* ts = rng + 2 * n_live;
+    int32_t* te = rng + 3 * n_live;
+    for (int i = l; i < 4 * n_live; i += kWave) rng[i] = 0;
+    __syncthreads();
+    for (int base = 0; base < m; base += kWave) {
+        const int i = base + l;
+        if (i < m) {
+            const int a = key_a((uint32_t)cand[i]);
+            const int pa = i > 0 ? key_a((uint32_t)cand[i - 1]) : -1;
+            const int na = i + 1 < m ? key_a((uint32_t)cand[i + 1]) : -1;
+            const int va = vpos[a - 1];
+            if (a != pa) fs[va] = i;
+            if (a != na) fe[va] = i + 1;
+            const int b = key_b((uint32_t)cand[tl[i]]);
+            const int pb = i > 0 ? key_b((uint32_t)cand[tl[i - 1]]) : -1;
+            const int nb = i + 1 < m ? key_b((uint32_t)cand[tl[i + 1]]) : -1;
+            const int vb = vpos[b - 1];
+            if (b != pb) ts[vb] = i;
+            if (b != nb) te[vb] = i + 1;
+        }
+    }
+    __syncthreads();
+}
+
+// Greedy-Intersections over per-variable ranges (any number of candidates).
+// The candidates containing v, in canonical order, are its range in the
+// second ordering (pairs (x, v), x < v) followed by its range in the
+// canonical list (pairs (v, y)); lane p merges the two ascending streams of
+// a and b, visiting its intersecting candidates in canonical order once
+// each, so coins are consumed as in the other forms.
+__device__ int select_gi_adj(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
+                             const int32_t* rng, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
+                             uint32_t proc, uint32_t dw, long long* n_int, long long* n_blk) {
+    const int l = lane_id();
+    const int32_t* fs = rng;
+    const int32_t* fe = rng + n_live;
+    const int32_t* ts = rng + 2 * n_live;
+    const int32_t* te = rng + 3 * n_live;
+    const int T = total_profit(cand, m);
+    constexpr int kEnd = 0x7FFFFFFF;
+    long long best_h = -1;
+    int best_p = 0x7FFFFFFF;
+    int my_int = 0, my_blk = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int p = base + l;
+        const bool valid = p < m;
+        const uint64_t ep = valid ? cand[p] : 0ull;
+        const uint32_t kp = (uint32_t)ep;
+        U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
+        if (valid) {
+            const int va = vpos[key_a(kp) - 1], vb = vpos[key_b(kp) - 1];
+            // Stream s: positions 0 .. nt-1 read tl[t0 + pos], then nt .. n-1 give f0 + pos - nt.
+            const int ta0 = ts[va], nta = te[va] - ta0, fa0 = fs[va], na = nta + fe[va] - fa0;
+            const int tb0 = ts[vb], ntb = te[vb] - tb0, fb0 = fs[vb], nb = ntb + fe[vb] - fb0;
+            int sa = 0, sb = 0;
+            int qa = na > 0 ? (nta > 0 ? (int)tl[ta0] : fa0) : kEnd;
+            int qb = nb > 0 ? (ntb > 0 ? (int)tl[tb0] : fb0) : kEnd;
+            uint32_t cw = blk.x;
+            int left = 32, refills = 0;
+            int I = 0, X = 0, j = 0;
+            while (qa != kEnd || qb != kEnd) {
+                const int q = qa < qb ? qa : qb;
+                if (q != p) {
+                    const int wq = entry_c(cand[q]) - 1;
+                    I += wq;
+                    X += wq * (int)(cw & 1u);
+                    cw >>= 1;
+                    ++j;
+                    if (--left == 0) {
+                        const int r = (++refills) & 3;
+                        if (r == 0) blk = philox10(proc, dw, kp, (uint32_t)(refills >> 2), k0, k1);
+                        cw = r == 0 ? blk.x : r == 1 ? blk.y : r == 2 ? blk.z : blk.w;
+                        left = 32;
+                    }
+                }
+                if (qa == q) {
+                    ++sa;
+                    qa = sa < nta ? (int)tl[ta0 + sa] : sa < na ? fa0 + sa - nta : kEnd;
+                }
+                if (qb == q) {
+                    ++sb;
+                    qb = sb < ntb ? (int)tl[tb0 + sb] : sb < nb ? fb0 + sb - ntb : kEnd;
+                }
+            }
+            const long long wp = (long long)entry_c(ep) - 1;
+            const long long D = (long long)T - wp - I;
+            const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
+            if (hsc > best_h) { best_h = hsc; best_p = p; }
+            my_int += j;
+            my_blk += (j + 127) >> 7;
+        }
+    }
+    *n_int = wave_sum(my_int);
+    *n_blk = wave_sum(my_blk);
+    return gi_argmax(best_h, best_p);
+}
+
 // Greedy-Intersections (Sec. 3.4.2).  Lane p scores candidate p:
 //   2^32 H = (c_p - 1) 2^32 + alpha_q (D_p 2^16 + beta_q X_p)
 // with D_p the profit of the disjoint candidates and X_p that of the
@@ -663,15 +934,20 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words);
+    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, C.adj);
     char* bulk = GS ? S.gs_base + (size_t)proc * S.gs_stride : (char*)smem;
     char* lists = GS ? (char*)smem : (char*)smem + BL.bytes;
     uint64_t* colP = (uint64_t*)(bulk + BL.colP);
     uint64_t* colN = (uint64_t*)(bulk + BL.colN);
     uint64_t* cand = (uint64_t*)(bulk + BL.cand);
+    uint64_t* cand2 = (uint64_t*)(bulk + BL.cand2);
     uint64_t* newc = (uint64_t*)(bulk + BL.newc);
     uint64_t* M = (uint64_t*)(bulk + BL.M);
     uint16_t* wt = (uint16_t*)(bulk + BL.wt);
+    uint32_t* tl = (uint32_t*)(bulk + BL.tl);
+    int32_t* remap = (int32_t*)(bulk + BL.remap);
+    int32_t* kpre = (int32_t*)(bulk + BL.kpre);
+    int32_t* rng = (int32_t*)(bulk + BL.rng);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
 
@@ -684,6 +960,8 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     else strat = weighted_pick(R.weights, N_STRAT, pu.x);
     const uint32_t alpha_q = pu.y >> 17;
     const uint32_t beta_q = 32768u + (pu.z >> 17);
+    // The second candidate ordering is kept only where gi walks ranges.
+    const bool need_tl = C.adj && (strat == S_GI || strat == S_MIX);
 
     for (int i = l; i < n_vmax * W; i += kWave) {
         const bool in = i < C.n_x * W;
@@ -729,13 +1007,28 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     }
 
     int err_flags = 0;
-    int m = analyse_full<W>(colP, colN, live, n_live, cand, C.m_cap, &err_flags);
+    int m;
+    if (t == 0) {
+        // Every unit of a component starts from the same input: its
+        // candidates (and second ordering) were counted once, on load.
+        m = C.m0;
+        for (int i = l; i < m; i += kWave) cand[i] = C.cand0[i];
+        if (need_tl)
+            for (int i = l; i < m; i += kWave) tl[i] = C.tl0[i];
+        __syncthreads();
+    } else {
+        m = analyse_full<W>(colP, colN, live, n_live, cand, C.m_cap, &err_flags);
+        if (need_tl) build_tl<W>(colP, colN, live, n_live, cand, m, tl);
+    }
     int active = 1;
     for (int done = 0;; ++done) {
         if (m == 0 || (R.step_cap && (uint32_t)t >= R.step_cap) || t >= C.n_fmax) { active = 0; break; }
         if (R.budget >= 0 && done >= R.budget) break;
 
-        const U4 su = philox10(proc, domain(TAG_STEP, C.comp, (uint32_t)epoch, (uint32_t)t), 0u, 0u, k0, k1);
+        // The step draw is consumed by ga, wr, gr and mix only.
+        U4 su = {0u, 0u, 0u, 0u};
+        if (strat != S_G && strat != S_GI)
+            su = philox10(proc, domain(TAG_STEP, C.comp, (uint32_t)epoch, (uint32_t)t), 0u, 0u, k0, k1);
         int s = strat;
         if (s == S_MIX) {
             const int mi = weighted_pick(R.mix_weights, 4, su.x);
@@ -753,7 +1046,11 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
             pick = select_wr(cand, m, su.z);
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
-            if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
+            if (C.adj) {
+                gi_ranges(cand, tl, m, vpos, n_live, rng);
+                pick = select_gi_adj(cand, tl, m, vpos, n_live, rng, alpha_q, beta_q, k0, k1, proc, dw, &n_int,
+                                     &n_blk);
+            } else if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
                 pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw,
                                         &n_int, &n_blk);
             else
@@ -775,8 +1072,19 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         cost -= c - 1;
         ++executed;
         ops += step_ops(s, m, n_int, n_blk, C.n_e, n_live);
-        m = update_candidates<W>(colP, colN, live, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
-                                 key_b(key), k, &err_flags);
+        if (C.adj) {
+            int n_new = 0;
+            const int m_old = m;
+            m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
+                                        remap, kpre, key_a(key), key_b(key), k, &n_new, &err_flags);
+            uint64_t* sw = cand;
+            cand = cand2;
+            cand2 = sw;
+            if (need_tl) update_tl(tl, m_old, remap, newc, n_new);
+        } else {
+            m = update_candidates<W>(colP, colN, live, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
+                                     key_b(key), k, &err_flags);
+        }
     }
     const unsigned any_err = __ockl_wfred_or_u32((unsigned)err_flags);
     if (any_err && l == 0) atomicOr(err, (int)any_err);

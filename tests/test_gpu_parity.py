@@ -333,3 +333,14 @@ def test_server_continuous_batching(gpu, oracle):
     cse.cse_server_destroy(tiny)
     for _, _, sid in jobs:
         cse.cse_scheme_free(ctx, sid)
+
+
+@pytest.mark.parametrize("rows,cols,p", [(42, 197, 0.2), (100, 60, 0.25)])
+def test_large_candidate_sets_with_sharing(gpu, oracle, rows, cols, p):
+    """Large candidate sets (gi over per-variable ranges) through sharing
+    rounds: restarted units rebuild both candidate orderings after replay."""
+    A = workloads.random_system(rows * 3 + cols, rows, cols, p)
+    kw = dict(seed=8, n_proc=24, weights={"gi": 4, "mix": 2, "wr": 1}, proc0_greedy=True, step_cap=36,
+              share_every=6, share_src_pm=100, share_dst_pm=400, share_max_rounds=5)
+    got, _ = check_workload(gpu, oracle, [A], kw, f"adj+share {rows}x{cols}")
+    assert got[0]["epoch"].max() > 0
