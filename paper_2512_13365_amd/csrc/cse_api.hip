@@ -46,6 +46,7 @@ struct DevComp {
     int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0, m0 = 0;
     bool gs = false;   // bulk state in HBM
     bool adj = false;  // gi over per-variable ranges (large candidate sets)
+    int kbits = 1;     // weight bit-planes per ordering
     long long occ0 = 0;
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
@@ -164,7 +165,7 @@ int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
     } while (0)
 
 size_t bulk_bytes(const DevComp& c) {
-    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0).bytes;
+    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0, c.kbits).bytes;
 }
 size_t lds_bytes(const DevComp& c) {
     return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
@@ -197,7 +198,10 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
         return fail(ctx, CSE_EINVAL, "variables %lld exceed %d", (long long)cols + c.n_fmax, kMaxVars);
     c.W = (rows + 63) / 64;
     c.occ0 = occ;
+    // The range form of gi packs candidate indices in 23 bits.
+    if (occ / 2 >= (1ll << 23)) return fail(ctx, CSE_EINVAL, "%lld candidates exceed 2^23", occ / 2);
     c.m_cap = (int)std::max<long long>(1, occ / 2);
+    c.kbits = csek::weight_bits(rows);
     c.naive0 = (int)naive;
     const int n_vmax = cols + c.n_fmax;
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
@@ -344,6 +348,7 @@ csek::CompArgs comp_args(const DevComp& c, int comp) {
     C.prog_stride = std::max(1, c.n_fmax);
     C.newc_cap = c.newc_cap;
     C.m_words = c.m_words;
+    C.kbits = c.kbits;
     return C;
 }
 

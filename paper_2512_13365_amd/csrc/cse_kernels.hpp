@@ -116,7 +116,7 @@ struct CompArgs {
     int32_t newc_cap;      // capacity of the fresh-variable pair list
     int32_t m_words;       // capacity of the gi masks (64-bit words)
     int32_t adj;           // 1: gi walks per-variable ranges (large candidate sets)
-    int32_t pad;
+    int32_t kbits;         // bit-planes per ordering: bit length of the largest c - 1
 };
 
 struct RunArgs {
@@ -157,13 +157,22 @@ struct Segment {
 // The bulk (bitsets, candidates, scratch) lives in LDS, or for systems too
 // large for LDS in a per-unit HBM slot; live/vpos always live in LDS.
 // Systems with large candidate sets (adj) keep a second candidate buffer,
-// the candidates ordered by (second, first, sign), an index remap and
-// per-variable ranges instead of the gi masks.
+// the candidates ordered by (second, first, sign), an index remap,
+// per-variable ranges, the second ordering packed with weights and the
+// weight bit-planes of both orderings instead of the gi masks.
 struct BulkLayout {
-    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, bytes;
+    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, tp, pl, bytes;
 };
+// Words of one bit-plane (one bit per candidate, 64-candidate granules).
+__host__ __device__ inline int plane_words(int m_cap) { return 2 * ((m_cap + 63) / 64); }
+// Bit-planes needed for the weights c - 1 <= n_e - 1.
+__host__ __device__ inline int weight_bits(int n_e) {
+    int k = 1;
+    while (k < 31 && (1 << k) <= n_e - 1) ++k;
+    return k;
+}
 __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words,
-                                                  int adj) {
+                                                  int adj, int kbits) {
     BulkLayout L;
     size_t o = 0;
     L.colP = o;  o += (size_t)n_vmax * W * 8;
@@ -176,7 +185,10 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     L.tl = o;    o += adj ? (size_t)m_cap * 4 : 0;
     L.remap = o; o += adj ? (size_t)m_cap * 4 : 0;
     L.kpre = o;  o += adj ? ((size_t)m_cap * 4 + 8) & ~size_t(7) : 0;
+    o = (o + 15) & ~size_t(15);
     L.rng = o;   o += adj ? (size_t)n_vmax * 16 : 0;
+    L.tp = o;    o += adj ? ((size_t)m_cap * 4 + 7) & ~size_t(7) : 0;
+    L.pl = o;    o += adj ? (size_t)2 * kbits * plane_words(m_cap) * 4 : 0;
     L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
@@ -652,98 +664,219 @@ __device__ void build_tl(const uint64_t* colP, const uint64_t* colN, const uint3
     __syncthreads();
 }
 
-// Per-variable ranges for gi: fs/fe = the canonical-list range of the pairs
-// whose first variable is v, ts/te = the range in the second ordering of the
-// pairs whose second variable is v (indexed by live position).
-__device__ void gi_ranges(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
-                          int32_t* rng) {
+// Per-step tables of the range form of gi, indexed by live position v:
+// rng[v] = (first, end) of the canonical-list range of the pairs whose first
+// variable is v, then (first, end) of the range of the second ordering
+// holding the pairs whose second variable is v.  tp[i] packs entry i of the
+// second ordering with its weight: index | (c - 1) << 23.  pl holds kbits
+// bit-planes of the weights c - 1 in canonical order, then kbits in the
+// second ordering (bit i of word w is candidate 32 w + i).  Returns the
+// number of planes in use: the bit length of the largest weight.
+__device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
+                          int32_t* rng, uint32_t* tp, uint32_t* pl, int pw, int kbits) {
     const int l = lane_id();
-    int32_t* fs = rng;
-    int32_t* fe = rng + n_live;
-    int32_t* ts = rng + 2 * n_live;
-    int32_t* te = rng + 3 * n_live;
     for (int i = l; i < 4 * n_live; i += kWave) rng[i] = 0;
     __syncthreads();
+    int wmax = 0;
     for (int base = 0; base < m; base += kWave) {
         const int i = base + l;
-        if (i < m) {
-            const int a = key_a((uint32_t)cand[i]);
-            const int pa = i > 0 ? key_a((uint32_t)cand[i - 1]) : -1;
-            const int na = i + 1 < m ? key_a((uint32_t)cand[i + 1]) : -1;
-            const int va = vpos[a - 1];
-            if (a != pa) fs[va] = i;
-            if (a != na) fe[va] = i + 1;
-            const int b = key_b((uint32_t)cand[tl[i]]);
-            const int pb = i > 0 ? key_b((uint32_t)cand[tl[i - 1]]) : -1;
-            const int nb = i + 1 < m ? key_b((uint32_t)cand[tl[i + 1]]) : -1;
-            const int vb = vpos[b - 1];
-            if (b != pb) ts[vb] = i;
-            if (b != nb) te[vb] = i + 1;
+        const bool valid = i < m;
+        const uint64_t e = valid ? cand[i] : 0ull;
+        const uint32_t q = valid ? tl[i] : 0u;
+        const uint64_t eq = valid ? cand[q] : 0ull;
+        const int w = valid ? entry_c(e) - 1 : 0;
+        const int wq = valid ? entry_c(eq) - 1 : 0;
+        const int a = key_a((uint32_t)e), b = key_b((uint32_t)eq);
+        // Neighbours in each ordering: other lanes of the chunk, or memory at its edges.
+        int pa = __shfl_up(a, 1), na = __shfl_down(a, 1);
+        int pb = __shfl_up(b, 1), nb = __shfl_down(b, 1);
+        if (l == 0) {
+            pa = i > 0 && valid ? key_a((uint32_t)cand[i - 1]) : -1;
+            pb = i > 0 && valid ? key_b((uint32_t)cand[tl[i - 1]]) : -1;
+        }
+        if (l == kWave - 1 || i + 1 >= m) {
+            na = i + 1 < m ? key_a((uint32_t)cand[i + 1]) : -1;
+            nb = i + 1 < m ? key_b((uint32_t)cand[tl[i + 1]]) : -1;
+        }
+        if (valid) {
+            const int va = vpos[a - 1], vb = vpos[b - 1];
+            if (a != pa) rng[4 * va + 0] = i;
+            if (a != na) rng[4 * va + 1] = i + 1;
+            if (b != pb) rng[4 * vb + 2] = i;
+            if (b != nb) rng[4 * vb + 3] = i + 1;
+            tp[i] = q | ((uint32_t)wq << 23);
+        }
+        wmax = w > wmax ? w : wmax;
+        const int word = 2 * (base / kWave);
+        for (int k = 0; k < kbits; ++k) {
+            const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
+            if (l < 2) {
+                pl[k * pw + word + l] = (uint32_t)(l ? bc >> 32 : bc);
+                pl[(kbits + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
+            }
         }
     }
     __syncthreads();
+    wmax = wave_max(wmax);
+    int K = 0;
+    while (K < kbits && (wmax >> K) != 0) ++K;
+    return K;
+}
+
+// The coin stream of one candidate p: bit j is coin j, taken from Philox
+// block (proc, dw, key(p), j div 128), bit j mod 32 of its word
+// (j mod 128) / 32.  Holds the current block and, once needed, the next.
+struct CoinStream {
+    uint32_t proc, dw, kp, k0, k1;
+    int cb;
+    bool has_nb;
+    uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
+
+    __device__ void init(uint32_t proc_, uint32_t dw_, uint32_t kp_, uint32_t k0_, uint32_t k1_) {
+        proc = proc_; dw = dw_; kp = kp_; k0 = k0_; k1 = k1_;
+        cb = 0;
+        has_nb = false;
+        const U4 x = philox10(proc, dw, kp, 0u, k0, k1);
+        a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
+        b0 = b1 = b2 = b3 = 0u;
+    }
+    __device__ void next_block() {
+        if (!has_nb) {
+            const U4 x = philox10(proc, dw, kp, (uint32_t)(cb + 1), k0, k1);
+            b0 = x.x; b1 = x.y; b2 = x.z; b3 = x.w;
+            has_nb = true;
+        }
+    }
+    // Word u (coins 32u .. 32u + 31); u never decreases between calls by more
+    // than stays within the held blocks.
+    __device__ uint32_t word(int u) {
+        const int blk = u >> 2;
+        if (blk != cb) {
+            if (blk == cb + 1) {
+                next_block();
+                a0 = b0; a1 = b1; a2 = b2; a3 = b3;
+            } else {
+                const U4 x = philox10(proc, dw, kp, (uint32_t)blk, k0, k1);
+                a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
+            }
+            cb = blk;
+            has_nb = false;
+        }
+        const int s = u & 3;
+        return s == 0 ? a0 : s == 1 ? a1 : s == 2 ? a2 : a3;
+    }
+    // Coins j .. j + 31 (bit i is coin j + i).
+    __device__ uint32_t bits32(int j) {
+        const int u = j >> 5, sh = j & 31;
+        const uint32_t w0 = word(u);
+        if (sh == 0) return w0;
+        uint32_t w1;
+        if ((u & 3) != 3) {
+            const int s = (u & 3) + 1;
+            w1 = s == 1 ? a1 : s == 2 ? a2 : a3;
+        } else {
+            next_block();
+            w1 = b0;
+        }
+        return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)sh);
+    }
+};
+
+// Weighted coin sum over a contiguous range [pos, end) of one ordering whose
+// candidates take the consecutive coins j, j + 1, ...: I += sum of c - 1,
+// X += sum of c - 1 over coin 1, 32 candidates per plane word.
+__device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, int pos, int end, int& j,
+                                             CoinStream& co, int& I, int& X) {
+    while (pos < end) {
+        const int sh = pos & 31;
+        const int n = min(32 - sh, end - pos);
+        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint32_t cw = co.bits32(j) << sh;
+        const int wi = pos >> 5;
+        for (int k = 0; k < K; ++k) {
+            const uint32_t x = pl[k * pw + wi] & msk;
+            I += __popc(x) << k;
+            X += __popc(x & cw) << k;
+        }
+        pos += n;
+        j += n;
+    }
 }
 
 // Greedy-Intersections over per-variable ranges (any number of candidates).
-// The candidates containing v, in canonical order, are its range in the
-// second ordering (pairs (x, v), x < v) followed by its range in the
-// canonical list (pairs (v, y)); lane p merges the two ascending streams of
-// a and b, visiting its intersecting candidates in canonical order once
-// each, so coins are consumed as in the other forms.
-__device__ int select_gi_adj(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
-                             const int32_t* rng, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
-                             uint32_t proc, uint32_t dw, long long* n_int, long long* n_blk) {
+// For p = (a, b, s), a < b, the candidates sharing a variable with p, in
+// canonical order, are: the pairs (x, a) and (x, b) with x < a, merged by x;
+// the pairs (a, y) (a canonical range holding p and its twin of the other
+// sign); the pairs (x, b) with a < x < b (a range of the second ordering);
+// the pairs (b, y) (a canonical range).  Lane p merges the first part
+// candidate by candidate and sums the three ranges through the weight
+// bit-planes; coins are consumed in that order, as in the other forms.
+__device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
+                                const uint32_t* tp, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
+                                uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw,
+                                long long* n_int, long long* n_blk) {
     const int l = lane_id();
-    const int32_t* fs = rng;
-    const int32_t* fe = rng + n_live;
-    const int32_t* ts = rng + 2 * n_live;
-    const int32_t* te = rng + 3 * n_live;
     const int T = total_profit(cand, m);
-    constexpr int kEnd = 0x7FFFFFFF;
+    const uint32_t* plc = pl;               // canonical order
+    const uint32_t* plt = pl + kbits * pw;  // second ordering
+    constexpr uint32_t kQ = (1u << 23) - 1u;
+    constexpr uint32_t kEnd = 0xFFFFFFFFu;
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
     for (int base = 0; base < m; base += kWave) {
         const int p = base + l;
-        const bool valid = p < m;
-        const uint64_t ep = valid ? cand[p] : 0ull;
-        const uint32_t kp = (uint32_t)ep;
-        U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
-        if (valid) {
+        if (p < m) {
+            const uint64_t ep = cand[p];
+            const uint32_t kp = (uint32_t)ep;
             const int va = vpos[key_a(kp) - 1], vb = vpos[key_b(kp) - 1];
-            // Stream s: positions 0 .. nt-1 read tl[t0 + pos], then nt .. n-1 give f0 + pos - nt.
-            const int ta0 = ts[va], nta = te[va] - ta0, fa0 = fs[va], na = nta + fe[va] - fa0;
-            const int tb0 = ts[vb], ntb = te[vb] - tb0, fb0 = fs[vb], nb = ntb + fe[vb] - fb0;
-            int sa = 0, sb = 0;
-            int qa = na > 0 ? (nta > 0 ? (int)tl[ta0] : fa0) : kEnd;
-            int qb = nb > 0 ? (ntb > 0 ? (int)tl[tb0] : fb0) : kEnd;
-            uint32_t cw = blk.x;
-            int left = 32, refills = 0;
+            const int4 ra = *(const int4*)(rng + 4 * va);
+            const int4 rb = *(const int4*)(rng + 4 * vb);
+            // The twin (a, b, other sign) is adjacent in canonical order.
+            const bool tprev = p > 0 && ((uint32_t)cand[p - 1] >> 1) == (kp >> 1);
+            const bool tnext = p + 1 < m && ((uint32_t)cand[p + 1] >> 1) == (kp >> 1);
+            const uint32_t q_lo = (uint32_t)(tprev ? p - 1 : p);
+            const int n_ab = (tprev || tnext) ? 2 : 1;
+            CoinStream co;
+            co.init(proc, dw, kp, k0, k1);
             int I = 0, X = 0, j = 0;
-            while (qa != kEnd || qb != kEnd) {
-                const int q = qa < qb ? qa : qb;
-                if (q != p) {
-                    const int wq = entry_c(cand[q]) - 1;
-                    I += wq;
-                    X += wq * (int)(cw & 1u);
-                    cw >>= 1;
-                    ++j;
-                    if (--left == 0) {
-                        const int r = (++refills) & 3;
-                        if (r == 0) blk = philox10(proc, dw, kp, (uint32_t)(refills >> 2), k0, k1);
-                        cw = r == 0 ? blk.x : r == 1 ? blk.y : r == 2 ? blk.z : blk.w;
-                        left = 32;
-                    }
+            // 1. (x, a) and (x, b), x < a: every (x, a) entry, and the (x, b)
+            //    entries before (a, b).
+            int ia = ra.z, ib = rb.z;
+            uint32_t ea = ia < ra.w ? tp[ia] : kEnd;
+            uint32_t eb = ib < rb.w ? tp[ib] : kEnd;
+            uint32_t qa = ea == kEnd ? kEnd : (ea & kQ);
+            uint32_t qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
+            uint32_t cw = co.word(0);
+            int left = 32;
+            while ((qa & qb) != kEnd) {
+                const bool ta = qa < qb;
+                const int w = (int)((ta ? ea : eb) >> 23);
+                I += w;
+                X += w & -(int)(cw & 1u);
+                cw >>= 1;
+                ++j;
+                if (--left == 0) {
+                    cw = co.word(j >> 5);
+                    left = 32;
                 }
-                if (qa == q) {
-                    ++sa;
-                    qa = sa < nta ? (int)tl[ta0 + sa] : sa < na ? fa0 + sa - nta : kEnd;
-                }
-                if (qb == q) {
-                    ++sb;
-                    qb = sb < ntb ? (int)tl[tb0 + sb] : sb < nb ? fb0 + sb - ntb : kEnd;
+                if (ta) {
+                    ++ia;
+                    ea = ia < ra.w ? tp[ia] : kEnd;
+                    qa = ea == kEnd ? kEnd : (ea & kQ);
+                } else {
+                    ++ib;
+                    eb = ib < rb.w ? tp[ib] : kEnd;
+                    qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
                 }
             }
+            // 2. (a, y): the canonical range of a without p.
+            plane_window(plc, pw, K, ra.x, p, j, co, I, X);
+            plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
+            // 3. (x, b), a < x < b: after (a, b) in b's range of the second ordering.
+            plane_window(plt, pw, K, ib + n_ab, rb.w, j, co, I, X);
+            // 4. (b, y): the canonical range of b.
+            plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
@@ -934,7 +1067,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, C.adj);
+    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, C.adj, C.kbits);
     char* bulk = GS ? S.gs_base + (size_t)proc * S.gs_stride : (char*)smem;
     char* lists = GS ? (char*)smem : (char*)smem + BL.bytes;
     uint64_t* colP = (uint64_t*)(bulk + BL.colP);
@@ -948,6 +1081,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     int32_t* remap = (int32_t*)(bulk + BL.remap);
     int32_t* kpre = (int32_t*)(bulk + BL.kpre);
     int32_t* rng = (int32_t*)(bulk + BL.rng);
+    uint32_t* tp = (uint32_t*)(bulk + BL.tp);
+    uint32_t* pl = (uint32_t*)(bulk + BL.pl);
+    const int pw = plane_words(C.m_cap);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
 
@@ -1047,9 +1183,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             if (C.adj) {
-                gi_ranges(cand, tl, m, vpos, n_live, rng);
-                pick = select_gi_adj(cand, tl, m, vpos, n_live, rng, alpha_q, beta_q, k0, k1, proc, dw, &n_int,
-                                     &n_blk);
+                const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tp, pl, pw, C.kbits);
+                pick = select_gi_planes(cand, m, vpos, rng, tp, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
+                                        dw, &n_int, &n_blk);
             } else if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
                 pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw,
                                         &n_int, &n_blk);
