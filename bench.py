@@ -31,6 +31,26 @@ METRIC = "CSE substitution steps/s and time-to-best additions; batched vs plain,
 PEAK_ALU_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "step_kernel_plain_4x4x4_hbm_counters.txt")
+    try:
+        with open(path) as f:
+            fields = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in ("cse_kernels.hpp", "cse_api.hip"):
+        with open(os.path.join(ROOT, "paper_2512_13365_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_sources_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -117,7 +137,8 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
                         "naive": sum(i[3] for i in info)},
         roofline={"kernel": "step_kernel<1, false>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
-                  "traffic": None, "algorithmic_ops_per_launch": ops / launches,
+                  "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
+                  "algorithmic_ops_per_launch": ops / launches,
                   "avg_launch_ms": avg_launch * 1e3})
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
@@ -132,7 +153,7 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     return out
 
 
-def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2):
+def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=1):
     """32 uneven schemes: one batched launch vs 32 sequential plain launches,
     same pools and seeds (so the same results)."""
     wl = workloads.batch_uneven()
@@ -330,7 +351,7 @@ def main():
         elif args.workload == "6x6x6":
             out = run_6x6x6(args, cse, workloads, torch, ctx, stream)
         elif args.workload == "batch":
-            bp = batch_vs_plain(cse, workloads, torch, ctx, stream)
+            bp = batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2)
             out = base_line(args, value=bp["batched"]["steps_per_s"], unit="substitution steps/s",
                             ms_per_step=None, config={"workload": bp["workload"]}, batched_vs_plain=bp)
         else:
