@@ -143,10 +143,23 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
  * allocation in between; on the same stream the call does not block. */
 int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void* stream);
 
-/* *done = 1 when the job's device work has completed, else 0. */
-int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done);
-/* Block until the job is done. */
+/* Non-blocking: *done = 1 when the job's device work has completed, else 0.
+ * best_cost (3 entries, may be NULL) receives, once done, the lowest cost
+ * over the units of each component (the best of each pool, Sec. 3.5, and
+ * Sec. 4's per-component bests); -1 for absent components and while the
+ * job runs.  Computing it waits briefly on the job's stream. */
+int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done, int32_t best_cost[3]);
+/* Block until the job is done.  CSE_ECANCELED if it was cancelled (its
+ * results are still readable). */
 int32_t cse_wait(cse_ctx* ctx, int32_t job_id);
+/* Stop a job early.  A running launch checks the request every 32
+ * selection steps of each unit; a unit that stops keeps a consistent state
+ * whose program is a prefix of the one it would have built.  A queued server
+ * job leaves the queue; a running server job stops after the current round.
+ * A job whose device work already completed is left as it is.  Returns
+ * CSE_OK once the request is recorded; cse_wait then returns CSE_ECANCELED.
+ * A relaunch clears the request. */
+int32_t cse_cancel(cse_ctx* ctx, int32_t job_id);
 
 /* Per-unit results of component `comp` for processes 0..n-1 (n = n_proc);
  * any pointer may be NULL.  cost: Sec. 3.2.1 cost; steps: program length;

@@ -29,8 +29,8 @@ STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4:
 # Every symbol declared in include/cse.h.
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
            "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_launch", "cse_launch_batch",
-           "cse_relaunch", "cse_poll", "cse_wait", "cse_get_unit_results", "cse_get_programs", "cse_get_program",
-           "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
+           "cse_relaunch", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results", "cse_get_programs",
+           "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy")
 CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE = 0, 1, 2
 
@@ -95,8 +95,10 @@ def load_library(path: str = LIB_PATH):
     L.cse_launch_batch.restype = i32
     L.cse_relaunch.argtypes = [vp, i32, P(CseRunCfg), vp]
     L.cse_relaunch.restype = i32
-    L.cse_poll.argtypes = [vp, i32, P(i32)]
+    L.cse_poll.argtypes = [vp, i32, P(i32), P(i32)]
     L.cse_poll.restype = i32
+    L.cse_cancel.argtypes = [vp, i32]
+    L.cse_cancel.restype = i32
     L.cse_wait.argtypes = [vp, i32]
     L.cse_wait.restype = i32
     L.cse_get_unit_results.argtypes = [vp, i32, i32, i32, P(i32), P(i32), P(i32), P(i32), P(i32),
@@ -245,14 +247,22 @@ def cse_relaunch(ctx, job_id, cfg: CseRunCfg | None = None, stream=None):
                                             _stream_ptr(stream)))
 
 
-def cse_poll(ctx, job_id) -> bool:
+def cse_poll(ctx, job_id, best=False):
+    """done (bool); with best=True, (done, [best cost per component] or None)."""
     done = ctypes.c_int32()
-    _check(ctx, load_library().cse_poll(ctx, job_id, ctypes.byref(done)))
-    return bool(done.value)
+    bc = (ctypes.c_int32 * 3)()
+    _check(ctx, load_library().cse_poll(ctx, job_id, ctypes.byref(done), bc if best else None))
+    if not best:
+        return bool(done.value)
+    return bool(done.value), (list(bc) if done.value else None)
 
 
 def cse_wait(ctx, job_id):
     _check(ctx, load_library().cse_wait(ctx, job_id))
+
+
+def cse_cancel(ctx, job_id):
+    _check(ctx, load_library().cse_cancel(ctx, job_id))
 
 
 def cse_get_unit_results(ctx, job_id, comp, n_proc):

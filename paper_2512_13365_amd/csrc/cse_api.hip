@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "cse.h"
+#include "cse_input.hpp"
 #include "cse_kernels.hpp"
 #include "cse_share.hpp"
 
@@ -36,6 +37,8 @@ constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit
 // Units whose state exceeds this many bytes of LDS keep the bulk of it in
 // HBM (one slot per unit) and only the variable lists in LDS.
 constexpr size_t kLdsUnitBudget = 64 * 1024;
+// Cancellation flags (pinned host memory read by the kernels): jobs alive at once.
+constexpr int kCancelSlots = 1 << 16;
 
 uint64_t now_ns() {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -48,10 +51,13 @@ struct DevComp {
     bool adj = false;  // gi over per-variable ranges (large candidate sets)
     int kbits = 1;     // weight bit-planes per ordering
     long long occ0 = 0;
+    int8_t* d_A = nullptr;        // the input, rows x cols row-major
     uint64_t* d_P = nullptr;
     uint64_t* d_N = nullptr;
     uint64_t* d_cand0 = nullptr;  // candidates of the input system, canonical order
     uint32_t* d_tl0 = nullptr;    // the same by (second, first, sign)
+    uint64_t* d_cand0_g = nullptr;  // the same two lists counted on the matrix cores
+    uint32_t* d_tl0_g = nullptr;
 };
 
 struct SchemeRec {
@@ -79,6 +85,9 @@ struct JobRec {
     bool allocated = false;
     bool server = false;                 // owned by a server
     int state = CSE_JOB_DONE;            // CSE_JOB_* (server jobs)
+    int cancel_slot = -1;                // its flag in the context's cancellation array
+    bool cancelled = false;
+    int32_t* d_best = nullptr;           // per-component best cost (cse_poll)
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     size_t bytes = 0;                    // device footprint
 };
@@ -120,6 +129,7 @@ struct BatchRec {
     int32_t* h_counts = nullptr;  // pinned copy
     size_t counts_cap = 0;
     bool is_server = false;
+    cse_server* owner = nullptr;      // the server running this batch
 };
 
 }  // namespace
@@ -133,6 +143,9 @@ struct cse_ctx {
     int next_scheme = 1, next_job = 1, next_batch = 1;
     size_t lds_max = 65536;
     uint64_t tick_hz = 100000000ull;
+    int32_t* h_cancel = nullptr;  // kCancelSlots flags, pinned host memory
+    int32_t* d_cancel = nullptr;  // the same as seen by the device
+    std::vector<int> free_slots;
 };
 
 struct cse_server {
@@ -171,6 +184,97 @@ size_t lds_bytes(const DevComp& c) {
     return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
 }
 
+void free_component(DevComp& c) {
+    for (void* p : {(void*)c.d_A, (void*)c.d_P, (void*)c.d_N, (void*)c.d_cand0, (void*)c.d_tl0,
+                    (void*)c.d_cand0_g, (void*)c.d_tl0_g})
+        if (p) (void)hipFree(p);
+    c.d_A = nullptr;
+    c.d_P = c.d_N = c.d_cand0 = c.d_cand0_g = nullptr;
+    c.d_tl0 = c.d_tl0_g = nullptr;
+}
+
+// Analysis of the input system on the device (Sec. 3.3), synchronous: pair
+// counts by popcounts of the column bitsets, or (gram) from the int8 Gram
+// matrix [P N]^T [P N] on the matrix cores; then the candidate list in
+// canonical order and the second ordering.  *m receives the candidate count.
+int analyse_input(cse_ctx* ctx, const DevComp& c, bool gram, uint64_t** cand_out, uint32_t** tl_out, int* m) {
+    const int n = c.n_x;
+    int32_t* buf = nullptr;  // row_n, col_n, row_off, col_off, totals
+    int8_t* X = nullptr;
+    int32_t* G = nullptr;
+    uint64_t* cand = nullptr;
+    uint32_t* tl = nullptr;
+    int rc = CSE_OK;
+    int32_t tot[2] = {0, 0};
+    const int F = (2 * n + 31) / 32 * 32, Kp = (c.n_e + 15) / 16 * 16;
+    csek::PairSource src{c.d_P, c.d_N, c.W, nullptr, F, n};
+    auto cleanup = [&]() {
+        if (buf) (void)hipFree(buf);
+        if (X) (void)hipFree(X);
+        if (G) (void)hipFree(G);
+    };
+#define IN_TRY(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            rc = fail(ctx, CSE_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                          \
+            cleanup();                                                                                 \
+            if (cand) (void)hipFree(cand);                                                             \
+            if (tl) (void)hipFree(tl);                                                                 \
+            return rc;                                                                                 \
+        }                                                                                              \
+    } while (0)
+    IN_TRY(hipMalloc((void**)&buf, sizeof(int32_t) * (4 * (size_t)n + 4)));
+    int32_t* row_n = buf;
+    int32_t* col_n = buf + n;
+    int32_t* row_off = buf + 2 * n;
+    int32_t* col_off = buf + 3 * n + 1;
+    int32_t* d_tot = buf + 4 * n + 2;
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((2 * n + 255) / 256), dim3(256), 0, nullptr, buf, 2 * n, 0);
+    if (gram) {
+        IN_TRY(hipMalloc((void**)&X, (size_t)F * Kp));
+        IN_TRY(hipMalloc((void**)&G, (size_t)F * F * 4));
+        const size_t nx = (size_t)F * Kp;
+        hipLaunchKernelGGL(csek::input_features_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, nullptr,
+                           c.d_A, c.n_e, n, Kp, F, X);
+        hipLaunchKernelGGL(csek::input_gram_kernel, dim3(F / 32, F / 32), dim3(64), 0, nullptr, X, Kp, F, G);
+        src.G = G;
+    }
+    hipLaunchKernelGGL(csek::input_count_kernel, dim3(n), dim3(csek::kInputBlock), 0, nullptr, src, row_n, col_n);
+    hipLaunchKernelGGL(csek::input_scan_kernel, dim3(1), dim3(csek::kInputBlock), 0, nullptr, row_n, col_n, n,
+                       row_off, col_off, d_tot);
+    IN_TRY(hipGetLastError());
+    IN_TRY(hipMemcpy(tot, d_tot, sizeof tot, hipMemcpyDeviceToHost));
+    if (tot[0] != tot[1] || tot[0] < 0) {
+        cleanup();
+        return fail(ctx, CSE_EHIP, "input analysis: %d candidates by first variable, %d by second", tot[0], tot[1]);
+    }
+    IN_TRY(hipMalloc((void**)&cand, std::max<size_t>(1, tot[0]) * 8));
+    IN_TRY(hipMalloc((void**)&tl, std::max<size_t>(1, tot[0]) * 4));
+    hipLaunchKernelGGL(csek::input_rows_kernel, dim3(n), dim3(csek::kInputBlock), 0, nullptr, src, row_off, cand);
+    hipLaunchKernelGGL(csek::input_cols_kernel, dim3(n), dim3(csek::kInputBlock), 0, nullptr, src, row_off, col_off,
+                       cand, tl);
+    IN_TRY(hipGetLastError());
+    IN_TRY(hipStreamSynchronize(nullptr));
+#undef IN_TRY
+    cleanup();
+    *cand_out = cand;
+    *tl_out = tl;
+    *m = tot[0];
+    return CSE_OK;
+}
+
+// Candidate lists counted on the matrix cores, computed on first use; they
+// must equal the popcount lists' size (the counts are the same integers).
+int ensure_gram_lists(cse_ctx* ctx, DevComp& c) {
+    if (c.d_cand0_g) return CSE_OK;
+    int m = 0;
+    int rc = analyse_input(ctx, c, true, &c.d_cand0_g, &c.d_tl0_g, &m);
+    if (rc) return rc;
+    if (m != c.m0) return fail(ctx, CSE_EHIP, "matrix-core count path found %d candidates, popcounts %d", m, c.m0);
+    return CSE_OK;
+}
+
 int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
     if (!A || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
     if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
@@ -207,60 +311,31 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
     const long long full_masks = (long long)n_vmax * ((c.m_cap + 63) / 64);
     c.m_words = (int)std::min<long long>(full_masks, kMaskBudgetWords);
-    std::vector<uint64_t> P((size_t)cols * c.W, 0), N((size_t)cols * c.W, 0);
-    for (int i = 0; i < rows; ++i)
-        for (int j = 0; j < cols; ++j) {
-            const int8_t v = A[(size_t)i * cols + j];
-            if (v > 0) P[(size_t)j * c.W + i / 64] |= 1ull << (i % 64);
-            if (v < 0) N[(size_t)j * c.W + i / 64] |= 1ull << (i % 64);
-        }
-    // The input's candidates, shared by every unit at its first step: pairs
-    // (a, b) with a < b in canonical order, '+' before '-', kept when c >= 2.
-    std::vector<uint64_t> cand0;
-    for (int a = 0; a < cols; ++a)
-        for (int b = a + 1; b < cols; ++b) {
-            int cp = 0, cm = 0;
-            for (int w = 0; w < c.W; ++w) {
-                const uint64_t Pa = P[(size_t)a * c.W + w], Na = N[(size_t)a * c.W + w];
-                const uint64_t Pb = P[(size_t)b * c.W + w], Nb = N[(size_t)b * c.W + w];
-                cp += __builtin_popcountll(Pa & Pb) + __builtin_popcountll(Na & Nb);
-                cm += __builtin_popcountll(Pa & Nb) + __builtin_popcountll(Na & Pb);
-            }
-            const uint64_t key = ((uint64_t)(a + 1) << 16) | ((uint64_t)(b + 1) << 1);
-            if (cp >= 2) cand0.push_back(key | ((uint64_t)cp << 32));
-            if (cm >= 2) cand0.push_back(key | 1ull | ((uint64_t)cm << 32));
-        }
-    c.m0 = (int)cand0.size();
-    std::vector<uint32_t> tl0(cand0.size());
-    for (size_t i = 0; i < tl0.size(); ++i) tl0[i] = (uint32_t)i;
-    std::stable_sort(tl0.begin(), tl0.end(), [&](uint32_t x, uint32_t y) {
-        return ((cand0[x] >> 1) & 0x7FFFu) < ((cand0[y] >> 1) & 0x7FFFu);
-    });
+    const size_t col_bytes = (size_t)cols * c.W * 8;
+    hipError_t e = hipMalloc(&c.d_A, (size_t)rows * cols);
+    if (e == hipSuccess) e = hipMemcpy(c.d_A, A, (size_t)rows * cols, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&c.d_P, col_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c.d_N, col_bytes);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(csek::input_columns_kernel, dim3((cols * c.W + 255) / 256), dim3(256), 0, nullptr,
+                           c.d_A, rows, cols, c.W, c.d_P, c.d_N);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        free_component(c);
+        return fail(ctx, CSE_EHIP, "loading a %d x %d system: %s", rows, cols, hipGetErrorString(e));
+    }
+    // The input's candidates, shared by every unit at its first step.
+    int rc = analyse_input(ctx, c, false, &c.d_cand0, &c.d_tl0, &c.m0);
+    if (rc) {
+        free_component(c);
+        return rc;
+    }
     // Large candidate sets walk per-variable ranges in gi instead of masks.
     c.adj = (long long)cols * ((c.m0 + 63) / 64) > kMaskBudgetWords * 3 / 4;
     c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
-    const size_t bytes = P.size() * 8;
-    HIP_TRY(ctx, hipMalloc(&c.d_P, bytes));
-    HIP_TRY(ctx, hipMalloc(&c.d_N, bytes));
-    HIP_TRY(ctx, hipMemcpy(c.d_P, P.data(), bytes, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMemcpy(c.d_N, N.data(), bytes, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMalloc(&c.d_cand0, std::max<size_t>(1, cand0.size()) * 8));
-    HIP_TRY(ctx, hipMalloc(&c.d_tl0, std::max<size_t>(1, tl0.size()) * 4));
-    if (!cand0.empty()) {
-        HIP_TRY(ctx, hipMemcpy(c.d_cand0, cand0.data(), cand0.size() * 8, hipMemcpyHostToDevice));
-        HIP_TRY(ctx, hipMemcpy(c.d_tl0, tl0.data(), tl0.size() * 4, hipMemcpyHostToDevice));
-    }
     *out = c;
     return CSE_OK;
-}
-
-void free_component(DevComp& c) {
-    if (c.d_P) (void)hipFree(c.d_P);
-    if (c.d_N) (void)hipFree(c.d_N);
-    if (c.d_cand0) (void)hipFree(c.d_cand0);
-    if (c.d_tl0) (void)hipFree(c.d_tl0);
-    c.d_P = c.d_N = c.d_cand0 = nullptr;
-    c.d_tl0 = nullptr;
 }
 
 bool shares(const cse_run_cfg& c) { return c.share_every > 0 && c.share_src_pm > 0 && c.share_max_rounds > 0; }
@@ -316,7 +391,7 @@ double unit_cost(const DevComp& c, uint32_t strat) {
     return strat == CSE_STRAT_GI ? 4.0 * scan : strat == CSE_STRAT_MIX ? 2.6 * scan : scan;
 }
 
-csek::RunArgs run_args(const JobRec& J) {
+csek::RunArgs run_args(cse_ctx* ctx, const JobRec& J) {
     const cse_run_cfg& cfg = J.cfg;
     csek::RunArgs R{};
     R.seed = cfg.seed;
@@ -328,15 +403,17 @@ csek::RunArgs run_args(const JobRec& J) {
     R.iteration = cfg.iteration;
     R.budget = J.budget;
     R.n_units = cfg.n_proc;
+    R.cancel = J.cancel_slot >= 0 ? ctx->d_cancel + J.cancel_slot : nullptr;
     return R;
 }
 
-csek::CompArgs comp_args(const DevComp& c, int comp) {
+// gram: the initial lists counted on the matrix cores (count_path MFMA).
+csek::CompArgs comp_args(const DevComp& c, int comp, bool gram) {
     csek::CompArgs C{};
     C.P0 = c.d_P;
     C.N0 = c.d_N;
-    C.cand0 = c.d_cand0;
-    C.tl0 = c.d_tl0;
+    C.cand0 = gram ? c.d_cand0_g : c.d_cand0;
+    C.tl0 = gram ? c.d_tl0_g : c.d_tl0;
     C.m0 = c.m0;
     C.adj = c.adj ? 1 : 0;
     C.n_e = c.n_e;
@@ -395,15 +472,19 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     return CSE_OK;
 }
 
-void free_job_device(JobRec& J) {
+void free_job_device(cse_ctx* ctx, JobRec& J) {
     for (int c = 0; c < J.n_comp; ++c) {
         if (J.cj[c].block) (void)hipFree(J.cj[c].block);
         J.cj[c].block = nullptr;
     }
     if (J.d_t0) (void)hipFree(J.d_t0);
     if (J.d_share) (void)hipFree(J.d_share);
+    if (J.d_best) (void)hipFree(J.d_best);
     J.d_t0 = nullptr;
     J.d_share = nullptr;
+    J.d_best = nullptr;
+    if (J.cancel_slot >= 0) ctx->free_slots.push_back(J.cancel_slot);
+    J.cancel_slot = -1;
     J.allocated = false;
 }
 
@@ -419,6 +500,13 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
         J.cj[c].st.t0 = nullptr;
     }
     HIP_TRY(ctx, hipMalloc((void**)&J.d_t0, 64));
+    HIP_TRY(ctx, hipMalloc((void**)&J.d_best, 16));
+    if (!ctx->free_slots.empty()) {
+        J.cancel_slot = ctx->free_slots.back();
+        ctx->free_slots.pop_back();
+        __atomic_store_n(&ctx->h_cancel[J.cancel_slot], 0, __ATOMIC_SEQ_CST);
+    }
+    J.cancelled = false;
     for (int c = 0; c < sc.n_comp; ++c) J.cj[c].st.t0 = J.d_t0;
     if (shares(J.cfg))
         HIP_TRY(ctx, hipMalloc((void**)&J.d_share, csek::share_scratch_bytes(J.cfg.n_proc) * sc.n_comp));
@@ -446,6 +534,15 @@ void free_batch_device(BatchRec& B) {
 // components grouped by row-word count W and state placement (the kernel is
 // specialised on both), then uploaded on the batch's stream.
 int build_segments(cse_ctx* ctx, BatchRec& B) {
+    for (int jid : B.jobs) {
+        JobRec& J = ctx->jobs[jid];
+        if (J.done || J.cfg.count_path != CSE_COUNT_MFMA) continue;
+        SchemeRec& sc = ctx->schemes[J.scheme];
+        for (int c = 0; c < sc.n_comp; ++c) {
+            int rc = ensure_gram_lists(ctx, sc.comp[c]);
+            if (rc) return rc;
+        }
+    }
     B.segs.clear();
     B.seg_job.clear();
     B.groups.clear();
@@ -466,8 +563,8 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
                 const DevComp& dc = sc.comp[c];
                 if (dc.W != W || dc.gs != gs) continue;
                 csek::Segment s{};
-                s.C = comp_args(dc, c);
-                s.R = run_args(J);
+                s.C = comp_args(dc, c, J.cfg.count_path == CSE_COUNT_MFMA);
+                s.R = run_args(ctx, J);
                 s.S = J.cj[c].st;
                 s.unit_begin = unit;
                 unit += J.cfg.n_proc;
@@ -692,7 +789,7 @@ void drop_batch(cse_ctx* ctx, int bid) {
     for (auto& kv : ctx->jobs)
         if (kv.second.batch == bid) owned.push_back(kv.first);
     for (int jid : owned) {
-        free_job_device(ctx->jobs[jid]);
+        free_job_device(ctx, ctx->jobs[jid]);
         ctx->jobs.erase(jid);
     }
     free_batch_device(B);
@@ -741,6 +838,17 @@ int32_t cse_ctx_create(int32_t device, cse_ctx** out) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         ctx->tick_hz = (uint64_t)khz * 1000ull;
+    // Cancellation flags: coherent pinned host memory, read by the kernels.
+    if (hipHostMalloc((void**)&ctx->h_cancel, sizeof(int32_t) * kCancelSlots,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&ctx->d_cancel, ctx->h_cancel, 0) != hipSuccess) {
+        if (ctx->h_cancel) (void)hipHostFree(ctx->h_cancel);
+        delete ctx;
+        return CSE_EHIP;
+    }
+    std::memset(ctx->h_cancel, 0, sizeof(int32_t) * kCancelSlots);
+    ctx->free_slots.reserve(kCancelSlots);
+    for (int i = kCancelSlots - 1; i >= 0; --i) ctx->free_slots.push_back(i);
     *out = ctx;
     return CSE_OK;
 }
@@ -753,6 +861,7 @@ void cse_ctx_destroy(cse_ctx* ctx) {
     for (int b : bids) drop_batch(ctx, b);
     for (auto& kv : ctx->schemes)
         for (int c = 0; c < kv.second.n_comp; ++c) free_component(kv.second.comp[c]);
+    if (ctx->h_cancel) (void)hipHostFree(ctx->h_cancel);
     delete ctx;
 }
 
@@ -890,6 +999,11 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
         J->cfg = *cfg;
         B->built = false;
     }
+    for (int jid : B->jobs) {
+        JobRec& Jb = ctx->jobs[jid];
+        if (Jb.cancel_slot >= 0) __atomic_store_n(&ctx->h_cancel[Jb.cancel_slot], 0, __ATOMIC_SEQ_CST);
+        Jb.cancelled = false;
+    }
     B->stream = (hipStream_t)stream;
     B->finished = false;
     rc = run_batch(ctx, *B);
@@ -898,19 +1012,37 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
     return CSE_OK;
 }
 
-int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done) {
+int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done, int32_t best_cost[3]) {
     if (!ctx || !done) return CSE_EINVAL;
     JobRec* J = nullptr;
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
-    if (J->server) { *done = J->state == CSE_JOB_DONE; return CSE_OK; }
-    if (B->finished) { *done = 1; return CSE_OK; }
-    hipError_t e = hipEventQuery(B->ev_done);
-    if (e == hipErrorNotReady) { *done = 0; return CSE_OK; }
-    if (e != hipSuccess) return fail(ctx, CSE_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
-    B->finished = true;
+    if (best_cost) best_cost[0] = best_cost[1] = best_cost[2] = -1;
+    *done = 0;
+    if (J->server) {
+        if (J->state != CSE_JOB_DONE) return CSE_OK;
+    } else if (!B->finished) {
+        hipError_t e = hipEventQuery(B->ev_done);
+        if (e == hipErrorNotReady) return CSE_OK;
+        if (e != hipSuccess) return fail(ctx, CSE_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+        B->finished = true;
+        int rc = check_err(ctx, *B);
+        if (rc) return rc;
+    }
     *done = 1;
-    return check_err(ctx, *B);
+    if (!best_cost || !J->allocated) return CSE_OK;
+    // The best of each pool (Sec. 3.5): a min over the units on the device.
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B->stream, J->d_best, 4, 0x7FFFFFFF);
+    for (int c = 0; c < J->n_comp; ++c)
+        hipLaunchKernelGGL(csek::best_cost_kernel, dim3((J->cfg.n_proc + 255) / 256), dim3(256), 0, B->stream,
+                           J->cj[c].st.cost, J->cfg.n_proc, J->d_best + c);
+    HIP_TRY(ctx, hipGetLastError());
+    int32_t h[4];
+    HIP_TRY(ctx, hipMemcpyAsync(h, J->d_best, sizeof h, hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(B->stream));
+    for (int c = 0; c < J->n_comp; ++c) best_cost[c] = h[c];
+    return CSE_OK;
 }
 
 int32_t cse_wait(cse_ctx* ctx, int32_t job_id) {
@@ -919,7 +1051,36 @@ int32_t cse_wait(cse_ctx* ctx, int32_t job_id) {
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (J->server && J->state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
-    return wait_batch(ctx, *B);
+    int rc = J->server ? CSE_OK : wait_batch(ctx, *B);
+    if (rc) return rc;
+    if (J->cancelled) return fail(ctx, CSE_ECANCELED, "job %d was cancelled", job_id);
+    return CSE_OK;
+}
+
+int32_t cse_cancel(cse_ctx* ctx, int32_t job_id) {
+    if (!ctx) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (J->server) {
+        if (J->state == CSE_JOB_DONE) return CSE_OK;
+        J->cancelled = true;
+        if (J->state == CSE_JOB_QUEUED && B->owner) {
+            auto& q = B->owner->queue;
+            q.erase(std::remove(q.begin(), q.end(), job_id), q.end());
+            J->state = CSE_JOB_DONE;
+            J->t_done = now_ns();
+        }
+        return CSE_OK;  // a running server job stops at the end of the current round
+    }
+    if (B->finished) return CSE_OK;
+    hipError_t e = hipEventQuery(B->ev_done);
+    if (e == hipSuccess) return CSE_OK;
+    if (e != hipErrorNotReady) return fail(ctx, CSE_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+    if (J->cancel_slot < 0) return fail(ctx, CSE_EINVAL, "job %d has no cancellation flag", job_id);
+    __atomic_store_n(&ctx->h_cancel[J->cancel_slot], 1, __ATOMIC_SEQ_CST);
+    J->cancelled = true;
+    return CSE_OK;
 }
 
 int32_t cse_get_unit_results(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t n, int32_t* cost,
@@ -1032,7 +1193,7 @@ int release_job(cse_ctx* ctx, int32_t job_id) {
     const int bid = J->batch;
     if (!B->finished) (void)wait_batch(ctx, *B);
     B->jobs.erase(std::remove(B->jobs.begin(), B->jobs.end(), job_id), B->jobs.end());
-    free_job_device(*J);
+    free_job_device(ctx, *J);
     ctx->jobs.erase(job_id);
     B->built = false;
     if (!B->is_server && B->jobs.empty()) drop_batch(ctx, bid);
@@ -1068,6 +1229,7 @@ int32_t cse_server_create(cse_ctx* ctx, uint64_t max_state_bytes, uint32_t round
     if (rc) { delete s; return rc; }
     BatchRec& B = ctx->batches[bid];
     B.is_server = true;
+    B.owner = s;
     B.rounds = true;
     s->batch = bid;
     hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B.stream, B.d_err, 1, 0);
@@ -1109,7 +1271,7 @@ int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued) {
         const size_t need = job_bytes(ctx, J.scheme, J.cfg);
         if (s->used_bytes + need > s->max_bytes) break;
         int rc = alloc_job(ctx, J);
-        if (rc) { free_job_device(J); return rc; }
+        if (rc) { free_job_device(ctx, J); return rc; }
         s->used_bytes += J.bytes;
         J.budget = shares(J.cfg) ? (int)J.cfg.share_every : (int)s->round_steps;
         rc = init_job(ctx, J, B.stream);
@@ -1136,7 +1298,7 @@ int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued) {
         std::vector<int> still;
         for (int jid : B.jobs) {
             JobRec& J = ctx->jobs[jid];
-            if (J.done) {
+            if (J.done || J.cancelled) {
                 J.state = CSE_JOB_DONE;
                 J.t_done = t;
                 s->dirty = true;

@@ -126,6 +126,7 @@ struct RunArgs {
     uint32_t proc0_greedy, gr_p_q16, step_cap, iteration;
     int32_t budget;        // selection steps per launch; < 0 = until the unit finishes
     uint32_t n_units;
+    const int32_t* cancel; // host-visible flag: nonzero stops the job's units (or null)
 };
 
 struct UnitState {         // per process arrays of one component
@@ -1160,6 +1161,10 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     for (int done = 0;; ++done) {
         if (m == 0 || (R.step_cap && (uint32_t)t >= R.step_cap) || t >= C.n_fmax) { active = 0; break; }
         if (R.budget >= 0 && done >= R.budget) break;
+        // Cancellation is checked every 32 steps; the unit keeps its prefix.
+        if ((done & 31) == 31 && R.cancel &&
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(R.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
+            break;
 
         // The step draw is consumed by ga, wr, gr and mix only.
         U4 su = {0u, 0u, 0u, 0u};
@@ -1234,6 +1239,12 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         S.active[proc] = active;
         if (!active) S.finish[proc] = wall_clock64() - *S.t0;
     }
+}
+
+// Lowest cost over a component's units (out starts at INT_MAX).
+__global__ void best_cost_kernel(const int32_t* cost, uint32_t n, int32_t* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMin(out, cost[i]);
 }
 
 // Job start stamp and per-unit state initialisation.

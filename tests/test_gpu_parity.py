@@ -56,7 +56,7 @@ def run_gpu(gpu, systems, kw):
 
 
 def compare(oracle, systems, kw, label, procs=None):
-    ocfg = oracle.make_cfg(**kw)
+    ocfg = oracle.make_cfg(**{k: v for k, v in kw.items() if k != "count_path"})
     res = []
     for c, A in enumerate(systems):
         ref = oracle.run_pool(A, ocfg, comp=c, procs=procs, n_threads=THREADS)
@@ -344,3 +344,65 @@ def test_large_candidate_sets_with_sharing(gpu, oracle, rows, cols, p):
               share_every=6, share_src_pm=100, share_dst_pm=400, share_max_rounds=5)
     got, _ = check_workload(gpu, oracle, [A], kw, f"adj+share {rows}x{cols}")
     assert got[0]["epoch"].max() > 0
+
+
+@pytest.mark.parametrize("rows,cols,p,hi", [
+    (7, 5, 0.5, None), (49, 16, 0.3, 8), (63, 33, 0.2, 10), (160, 36, 0.15, 12),
+    (42, 197, 0.2, None), (512, 12, 0.4, 6)])
+def test_count_paths_match(gpu, oracle, rows, cols, p, hi):
+    """The input's pair counts from popcounts and from the int8 Gram product
+    on the matrix cores (Sec. 3.3) give the same runs, equal to the oracle's."""
+    A = workloads.random_system(rows * 7919 + cols, rows, cols, p, 1, hi)
+    kw = dict(seed=rows * cols, n_proc=64, weights=dict(ALL_W), proc0_greedy=True)
+    ref = compare(oracle, [A], kw, "count paths")
+    cse = gpu[0]
+    for path in (cse.CSE_COUNT_POPCOUNT, cse.CSE_COUNT_MFMA, cse.CSE_COUNT_AUTO):
+        say(f"[gpu] count path {path}: system {rows}x{cols}")
+        got = run_gpu(gpu, [A], dict(kw, count_path=path))
+        assert_same(got[0], ref[0], f"count path {path} {rows}x{cols}")
+
+
+def test_cancel_keeps_prefixes_and_poll_reports_best(gpu, oracle):
+    """cse_cancel stops a running launch: every unit keeps a prefix of the
+    run it would have made (Algorithm 1 is deterministic per unit), its cost
+    matches that prefix, cse_wait reports the cancellation; a relaunch clears
+    it; cse_poll gives each pool's lowest cost."""
+    from cse_helpers import naive_count, replay
+    cse, ctx, torch = gpu
+    A = workloads.random_system(4242, 42, 197, 0.2)
+    n = 4096
+    kw = dict(seed=11, n_proc=n, weights={"gi": 1})
+    sid = cse.cse_system_load(ctx, A)
+    info = cse.cse_scheme_info(ctx, sid)
+    st = torch.cuda.current_stream()
+    say(f"[gpu] cancel: 42x197, {n} gi units")
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), st)
+    cse.cse_cancel(ctx, job)
+    with pytest.raises(cse.CseError) as err:
+        cse.cse_wait(ctx, job)
+    assert "CSE_ECANCELED" in str(err.value)
+    done, best = cse.cse_poll(ctx, job, best=True)
+    r = cse.cse_get_unit_results(ctx, job, 0, n)
+    prog = cse.cse_get_programs(ctx, job, 0, n, max(1, info[0][2]))
+    assert done and best[0] == int(r["cost"].min()) and best[1:] == [-1, -1]
+    procs = list(range(0, n, 512))
+    ref = oracle.run_pool(A, oracle.make_cfg(**dict(kw, step_cap=64)), procs=procs, n_threads=THREADS)
+    stopped = 0
+    for i, u in enumerate(procs):
+        t = int(r["steps"][u])
+        k = min(t, 64)
+        assert (prog[u][:k] == ref["prog"][i][:k]).all(), f"unit {u}: cancelled program is not a prefix"
+        _, cs = replay(A, prog[u][:t])
+        assert int(r["cost"][u]) == naive_count(A) - sum(c - 1 for c in cs)
+        stopped += t < info[0][2]
+    assert stopped == len(procs), "cancellation did not stop the sampled units"
+    # A relaunch clears the request and runs to its cap like the oracle.
+    cse.cse_relaunch(ctx, job, cse.cse_run_cfg(**dict(kw, step_cap=40)), st)
+    cse.cse_wait(ctx, job)
+    r = cse.cse_get_unit_results(ctx, job, 0, n)
+    prog = cse.cse_get_programs(ctx, job, 0, n, max(1, info[0][2]))
+    for i, u in enumerate(procs):
+        assert int(r["steps"][u]) == min(40, int(ref["steps"][i]))
+        assert (prog[u][:40] == ref["prog"][i][:40]).all()
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
