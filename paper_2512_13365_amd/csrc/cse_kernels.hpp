@@ -941,20 +941,20 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
     return gi_argmax(best_h, best_p);
 }
 
-// Greedy-Intersections, sparse form: M[v] marks (bit i of word w) the
-// candidates 64w + i that contain the live variable at position v.  Lane p
-// walks the set bits of M[a] | M[b] (minus p itself) word by word in
-// increasing index, i.e. exactly its intersecting candidates in canonical
-// order, so the coin order is the same as the dense form's; coins are taken
-// 32 at a time from the current Philox block.  D_p = T - (c_p - 1) - I_p with
-// I_p the profit of all intersecting candidates.  wt[q] = c_q - 1 is filled
-// on the way.
-__device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M,
+// Greedy-Intersections, sparse form: M[v] marks (bit i of 32-bit word w)
+// the candidates 32 w + i that contain the live variable at position v.
+// Lane p walks the set bits of M[a] | M[b] (minus p itself) in increasing
+// index, i.e. exactly its intersecting candidates in canonical order, so the
+// coin order is the same as the other forms'; each word's members take the
+// next 32-coin window.  D_p = T - (c_p - 1) - I_p with I_p the profit of all
+// intersecting candidates.  wt[q] = c_q - 1 is filled on the way.
+__device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M64,
                                 uint16_t* wt, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc,
                                 uint32_t dw, long long* n_int, long long* n_blk) {
     const int l = lane_id();
-    const int nw = (m + kWave - 1) / kWave;
-    for (int i = l; i < n_live * nw; i += kWave) M[i] = 0ull;
+    const int nw = (m + 31) >> 5;
+    uint32_t* M = (uint32_t*)M64;
+    for (int i = l; i < n_live * nw; i += kWave) M[i] = 0u;
     __syncthreads();
     int tsum = 0;
     for (int base = 0; base < m; base += kWave) {
@@ -965,10 +965,9 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
             const int w = entry_c(e) - 1;
             wt[q] = (uint16_t)w;
             tsum += w;
-            const int wd = base / kWave;
-            const unsigned long long bit = 1ull << l;
-            atomicOr((unsigned long long*)&M[vpos[key_a(key) - 1] * nw + wd], bit);
-            atomicOr((unsigned long long*)&M[vpos[key_b(key) - 1] * nw + wd], bit);
+            const uint32_t bit = 1u << (q & 31);
+            atomicOr(&M[vpos[key_a(key) - 1] * nw + (q >> 5)], bit);
+            atomicOr(&M[vpos[key_b(key) - 1] * nw + (q >> 5)], bit);
         }
     }
     const int T = wave_sum(tsum);
@@ -981,33 +980,30 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
         const bool valid = p < m;
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
-        U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
+        CoinStream co;
+        co.init(proc, dw, kp, k0, k1);
         if (valid) {
-            const uint64_t* Ma = M + vpos[key_a(kp) - 1] * nw;
-            const uint64_t* Mb = M + vpos[key_b(kp) - 1] * nw;
-            const int self_w = p >> 6;
-            uint32_t cw = blk.x;  // the next coins, bit 0 first
-            int left = 32, refills = 0;
+            const uint32_t* Ma = M + vpos[key_a(kp) - 1] * nw;
+            const uint32_t* Mb = M + vpos[key_b(kp) - 1] * nw;
+            const int self_w = p >> 5;
+            const uint32_t self_bit = 1u << (p & 31);
             int I = 0, X = 0, j = 0;
+            // Word by word (the same word in every lane); coins j .. j+31 are
+            // the window for the word's members, taken in increasing index.
             for (int w = 0; w < nw; ++w) {
-                uint64_t u = Ma[w] | Mb[w];
-                if (w == self_w) u &= ~(1ull << l);
-                j += popc64(u);
-                while (u) {
-                    const uint32_t lo = (uint32_t)u;
-                    const int bit = lo ? __ffs((int)lo) - 1 : 31 + __ffs((int)(uint32_t)(u >> 32));
-                    u &= u - 1ull;
-                    const int wq = wt[(w << 6) + bit];
-                    I += wq;
-                    X += wq * (int)(cw & 1u);
+                uint32_t u = (Ma[w] | Mb[w]) & (w == self_w ? ~self_bit : 0xFFFFFFFFu);
+                if (u == 0) continue;
+                uint32_t cw = co.bits32(j);
+                j += __popc(u);
+                const uint16_t* wrow = wt + (w << 5);
+                do {
+                    const int bit = __builtin_ctz(u);
+                    u &= u - 1u;
+                    const uint32_t wq = wrow[bit];
+                    I += (int)wq;
+                    X += (int)((cw & 1u) * wq);
                     cw >>= 1;
-                    if (--left == 0) {
-                        const int r = (++refills) & 3;
-                        if (r == 0) blk = philox10(proc, dw, kp, (uint32_t)(refills >> 2), k0, k1);
-                        cw = r == 0 ? blk.x : r == 1 ? blk.y : r == 2 ? blk.z : blk.w;
-                        left = 32;
-                    }
-                }
+                } while (u);
             }
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
@@ -1161,8 +1157,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     for (int done = 0;; ++done) {
         if (m == 0 || (R.step_cap && (uint32_t)t >= R.step_cap) || t >= C.n_fmax) { active = 0; break; }
         if (R.budget >= 0 && done >= R.budget) break;
-        // Cancellation is checked every 32 steps; the unit keeps its prefix.
-        if ((done & 31) == 31 && R.cancel &&
+        // Cancellation is checked every 256 steps (a read of host memory);
+        // the unit keeps its prefix.
+        if ((done & 255) == 255 && R.cancel &&
             __builtin_amdgcn_readfirstlane(__hip_atomic_load(R.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
             break;
 
@@ -1191,7 +1188,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tp, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tp, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
                                         dw, &n_int, &n_blk);
-            } else if (n_live * ((m + kWave - 1) / kWave) <= C.m_words)
+            } else if (n_live * ((m + 31) / 32) <= 2 * C.m_words)
                 pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw,
                                         &n_int, &n_blk);
             else
