@@ -110,6 +110,8 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     wl = workloads.plain_4x4x4()
     sc, rs = wl.schemes[0], wl.runs[0]
     kw = rs.as_kwargs()
+    if args.strategy:
+        kw["weights"] = {args.strategy: 1}
     sid = cse.cse_scheme_load(ctx, *sc.systems)
     info = cse.cse_scheme_info(ctx, sid)
     log(f"[bench] workload {wl.name}: shapes {[A.shape for A in sc.systems]} n_proc {rs.n_proc}")
@@ -117,7 +119,12 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     cse.cse_wait(ctx, job)
     gpu_s = timed_relaunch(cse, ctx, job, stream, torch, args.steps, args.warmup)
     log(f"[bench] timed {args.steps} steps: {gpu_s * 1e3:.3f} ms device")
+    # Host copy of every unit's results and program (PCIe), timed apart.
+    t0 = time.perf_counter()
     res = job_results(cse, ctx, job, rs.n_proc)
+    for c in range(3):
+        cse.cse_get_programs(ctx, job, c, rs.n_proc, max(1, info[c][2]))
+    readback_s = time.perf_counter() - t0
     _, tick_hz = cse.cse_job_timing(ctx, job)
     subs = sum(int(r["executed"].sum()) for r in res)
     ops = sum(int(r["ops"].sum()) for r in res)
@@ -129,12 +136,16 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     out = base_line(
         args, value=subs * args.steps / gpu_s, unit="substitution steps/s", ms_per_step=per_step * 1e3,
         config={"workload": "plain-4x4x4-r49: U,V 49x16, W^T 16x49 ternary, p=0.30, row nnz in [1,8]; "
-                            "4096 processes gi/ga/wr 1:1:1; seed 0; no sharing",
+                            + (f"4096 processes, {args.strategy} only" if args.strategy
+                               else "4096 processes gi/ga/wr 1:1:1") + "; seed 0; no sharing",
                 "n_proc": rs.n_proc, "units": 3 * rs.n_proc, "substitutions_per_step": subs},
         time_to_best_ms={"U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
                          "scheme": max(t for _, t in ttb) * 1e3},
         best_additions={"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0], "scheme": sum(b for b, _ in ttb),
                         "naive": sum(i[3] for i in info)},
+        pcie_inclusive={"readback_ms": readback_s * 1e3,
+                        "steps_per_s": subs / (per_step + readback_s),
+                        "note": "job plus host copy of all unit results and programs"},
         roofline={"kernel": "step_kernel<1, false>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
                   "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
@@ -316,6 +327,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
+                    help="4x4x4 only: every process uses this strategy (per-strategy cost)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
     ap.add_argument("--serve-budget-gib", type=int, default=96, help="serving: device state budget")
