@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kMaxRows = 512;          // W <= 8 row words
 constexpr int kMaxVars = 32767;        // 15-bit variable ids
-constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit
+constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit (64-bit words)
 // Units whose state exceeds this many bytes of LDS keep the bulk of it in
 // HBM (one slot per unit) and only the variable lists in LDS.
 constexpr size_t kLdsUnitBudget = 64 * 1024;
@@ -309,8 +309,6 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     c.naive0 = (int)naive;
     const int n_vmax = cols + c.n_fmax;
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
-    const long long full_masks = (long long)n_vmax * ((c.m_cap + 63) / 64);
-    c.m_words = (int)std::min<long long>(full_masks, kMaskBudgetWords);
     const size_t col_bytes = (size_t)cols * c.W * 8;
     hipError_t e = hipMalloc(&c.d_A, (size_t)rows * cols);
     if (e == hipSuccess) e = hipMemcpy(c.d_A, A, (size_t)rows * cols, hipMemcpyHostToDevice);
@@ -333,6 +331,13 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     }
     // Large candidate sets walk per-variable ranges in gi instead of masks.
     c.adj = (long long)cols * ((c.m0 + 63) / 64) > kMaskBudgetWords * 3 / 4;
+    // Mask capacity: twice the input's need (live variables x 32-bit words of
+    // candidates), at least 1 KB, at most the budget; a step that needs more
+    // takes the exact O(m^2) form.
+    const long long full32 = (long long)n_vmax * ((c.m_cap + 31) / 32);
+    const long long want32 = std::max<long long>(2ll * cols * ((c.m0 + 31) / 32), 256);
+    const long long words32 = std::min<long long>({full32, want32, 2ll * kMaskBudgetWords});
+    c.m_words = (int)std::max<long long>(1, (words32 + 1) / 2);
     c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
     *out = c;
     return CSE_OK;

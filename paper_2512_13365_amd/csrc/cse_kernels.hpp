@@ -160,7 +160,8 @@ struct Segment {
 // Systems with large candidate sets (adj) keep a second candidate buffer,
 // the candidates ordered by (second, first, sign), an index remap,
 // per-variable ranges, the second ordering packed with weights and the
-// weight bit-planes of both orderings instead of the gi masks.
+// weight bit-planes of both orderings instead of the gi masks.  m_words is
+// the mask capacity in 64-bit words.
 struct BulkLayout {
     size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, tp, pl, bytes;
 };
@@ -179,17 +180,29 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     L.colP = o;  o += (size_t)n_vmax * W * 8;
     L.colN = o;  o += (size_t)n_vmax * W * 8;
     L.cand = o;  o += (size_t)m_cap * 8;
-    L.cand2 = o; o += adj ? (size_t)m_cap * 8 : 0;
+    if (!adj) {
+        // The fresh-variable pairs (update) and the gi masks and weights
+        // (selection) are never live at the same time: one region.
+        const size_t gi = (size_t)m_words * 8 + (((size_t)m_cap * 2 + 7) & ~size_t(7));
+        const size_t up = (size_t)newc_cap * 8;
+        L.newc = o;
+        L.M = o;
+        L.wt = o + (size_t)m_words * 8;
+        o += gi > up ? gi : up;
+        L.cand2 = L.tl = L.remap = L.kpre = L.rng = L.tp = L.pl = o;
+        L.bytes = (o + 255) & ~size_t(255);
+        return L;
+    }
+    L.M = L.wt = o;
+    L.cand2 = o; o += (size_t)m_cap * 8;
     L.newc = o;  o += (size_t)newc_cap * 8;
-    L.M = o;     o += adj ? 0 : (size_t)m_words * 8;
-    L.wt = o;    o += adj ? 0 : ((size_t)m_cap * 2 + 7) & ~size_t(7);
-    L.tl = o;    o += adj ? (size_t)m_cap * 4 : 0;
-    L.remap = o; o += adj ? (size_t)m_cap * 4 : 0;
-    L.kpre = o;  o += adj ? ((size_t)m_cap * 4 + 8) & ~size_t(7) : 0;
+    L.tl = o;    o += (size_t)m_cap * 4;
+    L.remap = o; o += (size_t)m_cap * 4;
+    L.kpre = o;  o += ((size_t)m_cap * 4 + 8) & ~size_t(7);
     o = (o + 15) & ~size_t(15);
-    L.rng = o;   o += adj ? (size_t)n_vmax * 16 : 0;
-    L.tp = o;    o += adj ? ((size_t)m_cap * 4 + 7) & ~size_t(7) : 0;
-    L.pl = o;    o += adj ? (size_t)2 * kbits * plane_words(m_cap) * 4 : 0;
+    L.rng = o;   o += (size_t)n_vmax * 16;
+    L.tp = o;    o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
+    L.pl = o;    o += (size_t)2 * kbits * plane_words(m_cap) * 4;
     L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
