@@ -130,6 +130,15 @@ struct BatchRec {
     size_t counts_cap = 0;
     bool is_server = false;
     cse_server* owner = nullptr;      // the server running this batch
+    // Round-driven batches: the pools' table, and one round (every group's
+    // launch, the pool kernels, the count copy) captured as a graph and
+    // replayed on an internal stream.
+    csek::PoolDev* d_pools = nullptr;
+    size_t dpools_cap = 0;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_order = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint32_t pool_grid_x = 1;
 };
 
 }  // namespace
@@ -504,7 +513,7 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
         if (rc) return rc;
         J.cj[c].st.t0 = nullptr;
     }
-    HIP_TRY(ctx, hipMalloc((void**)&J.d_t0, 64));
+    HIP_TRY(ctx, hipMalloc((void**)&J.d_t0, 64));  // start stamp (8 B), round counter (4 B)
     HIP_TRY(ctx, hipMalloc((void**)&J.d_best, 16));
     if (!ctx->free_slots.empty()) {
         J.cancel_slot = ctx->free_slots.back();
@@ -512,7 +521,10 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
         __atomic_store_n(&ctx->h_cancel[J.cancel_slot], 0, __ATOMIC_SEQ_CST);
     }
     J.cancelled = false;
-    for (int c = 0; c < sc.n_comp; ++c) J.cj[c].st.t0 = J.d_t0;
+    for (int c = 0; c < sc.n_comp; ++c) {
+        J.cj[c].st.t0 = J.d_t0;
+        J.cj[c].st.round = (int32_t*)((char*)J.d_t0 + 8);
+    }
     if (shares(J.cfg))
         HIP_TRY(ctx, hipMalloc((void**)&J.d_share, csek::share_scratch_bytes(J.cfg.n_proc) * sc.n_comp));
     J.bytes = job_bytes(ctx, J.scheme, J.cfg);
@@ -520,6 +532,15 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
 }
 
 void free_batch_device(BatchRec& B) {
+    if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
+    if (B.gstream) (void)hipStreamDestroy(B.gstream);
+    if (B.ev_order) (void)hipEventDestroy(B.ev_order);
+    if (B.d_pools) (void)hipFree(B.d_pools);
+    B.gexec = nullptr;
+    B.gstream = nullptr;
+    B.ev_order = nullptr;
+    B.d_pools = nullptr;
+    B.dpools_cap = 0;
     if (B.d_segs) (void)hipFree(B.d_segs);
     if (B.d_order) (void)hipFree(B.d_order);
     if (B.d_err) (void)hipFree(B.d_err);
@@ -533,6 +554,33 @@ void free_batch_device(BatchRec& B) {
     B.h_counts = nullptr;
     B.ev_done = nullptr;
     B.segs_cap = B.counts_cap = B.order_cap = 0;
+}
+
+// Dynamic LDS above 64 KB must be allowed per kernel before launches (and
+// before a launch is captured into a graph).
+template <int W, bool GS>
+int set_lds_limit_w(cse_ctx* ctx, size_t lds) {
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return CSE_OK;
+}
+template <bool GS>
+int set_lds_limit_gs(cse_ctx* ctx, int W, size_t lds) {
+    switch (W) {
+    case 1: return set_lds_limit_w<1, GS>(ctx, lds);
+    case 2: return set_lds_limit_w<2, GS>(ctx, lds);
+    case 3: return set_lds_limit_w<3, GS>(ctx, lds);
+    case 4: return set_lds_limit_w<4, GS>(ctx, lds);
+    case 5: return set_lds_limit_w<5, GS>(ctx, lds);
+    case 6: return set_lds_limit_w<6, GS>(ctx, lds);
+    case 7: return set_lds_limit_w<7, GS>(ctx, lds);
+    case 8: return set_lds_limit_w<8, GS>(ctx, lds);
+    default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", W);
+    }
+}
+int set_lds_limit(cse_ctx* ctx, const LaunchGroup& G) {
+    if (G.lds <= 65536) return CSE_OK;
+    return G.gs ? set_lds_limit_gs<true>(ctx, G.W, G.lds) : set_lds_limit_gs<false>(ctx, G.W, G.lds);
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -617,9 +665,46 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             B.pools.push_back(P);
         }
     }
-    for (const LaunchGroup& G : B.groups)
+    for (const LaunchGroup& G : B.groups) {
         if (G.lds > ctx->lds_max)
             return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
+        int rc = set_lds_limit(ctx, G);
+        if (rc) return rc;
+    }
+    if (B.rounds) {
+        std::vector<csek::PoolDev> pd;
+        uint32_t nmax = 1;
+        for (size_t i = 0; i < B.pools.size(); ++i) {
+            const Pool& P = B.pools[i];
+            const JobRec& J = ctx->jobs[P.job];
+            csek::PoolDev d{};
+            d.S = J.cj[P.comp].st;
+            if (P.shares) d.sc = csek::share_scratch(P.scratch, P.n);
+            d.seed = J.cfg.seed;
+            d.n = P.n;
+            d.n_src = P.n_src;
+            d.comp = (uint32_t)P.comp;
+            d.dst_pm = J.cfg.share_dst_pm;
+            d.max_rounds = J.cfg.share_max_rounds;
+            d.shares = P.shares ? 1u : 0u;
+            d.n_fmax = ctx->schemes[J.scheme].comp[P.comp].n_fmax;
+            d.first_of_job = P.comp == 0 ? 1u : 0u;
+            pd.push_back(d);
+            nmax = std::max(nmax, P.n);
+        }
+        B.pool_grid_x = (nmax + 255) / 256;
+        if (pd.size() > B.dpools_cap) {
+            if (B.d_pools) HIP_TRY(ctx, hipFree(B.d_pools));
+            B.d_pools = nullptr;
+            B.dpools_cap = std::max(pd.size(), 2 * B.dpools_cap);
+            HIP_TRY(ctx, hipMalloc((void**)&B.d_pools, sizeof(csek::PoolDev) * B.dpools_cap));
+        }
+        if (!pd.empty())
+            HIP_TRY(ctx, hipMemcpyAsync(B.d_pools, pd.data(), sizeof(csek::PoolDev) * pd.size(),
+                                        hipMemcpyHostToDevice, B.stream));
+        if (B.gexec) HIP_TRY(ctx, hipGraphExecDestroy(B.gexec));
+        B.gexec = nullptr;  // the captured round no longer matches
+    }
     if (B.segs.size() > B.segs_cap) {
         if (B.d_segs) HIP_TRY(ctx, hipFree(B.d_segs));
         B.d_segs = nullptr;
@@ -656,9 +741,6 @@ int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_se
                    int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    if (G.lds > 65536)
-        HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds));
     hipLaunchKernelGGL((csek::step_kernel<W, GS>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
                        d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
     HIP_TRY(ctx, hipGetLastError());
@@ -681,10 +763,10 @@ int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_s
     }
 }
 
-int launch_groups(cse_ctx* ctx, BatchRec& B) {
+int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
     for (const LaunchGroup& G : B.groups) {
-        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_order, B.d_err, B.stream)
-                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_order, B.d_err, B.stream);
+        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         if (rc) return rc;
     }
     return CSE_OK;
@@ -728,30 +810,51 @@ int init_job(cse_ctx* ctx, JobRec& J, hipStream_t s) {
 // One round for every unfinished job of the batch (Sec. 3.5.2): one launch
 // per group advances each active unit by at most its job's budget; then every
 // pool counts its active units and, if its job shares and is below
-// share_max_rounds, ranks its units and copies prefixes into targets.  The
-// host waits for the counts; a job with no active unit left is done.
-int round_once(cse_ctx* ctx, BatchRec& B) {
-    int rc = launch_groups(ctx, B);
-    if (rc) return rc;
+// share_max_rounds, ranks its units and copies prefixes into targets; each
+// job's round counter advances.  The round is captured once as a graph (its
+// arguments never change: budgets, pools and round counters live in device
+// memory) and replayed on the batch's internal stream, after the work the
+// caller queued on the batch's stream.  The host waits for the counts; a job
+// with no active unit left is done.
+int capture_round(cse_ctx* ctx, BatchRec& B) {
     const int n_pools = (int)B.pools.size();
-    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), dim3(256), 0, B.stream, B.d_counts,
-                       n_pools, 0);
-    for (int p = 0; p < n_pools; ++p) {
-        const Pool& P = B.pools[p];
-        JobRec& J = ctx->jobs[P.job];
-        const csek::UnitState& S = J.cj[P.comp].st;
-        const dim3 blk(256), grd((P.n + 255) / 256);
-        hipLaunchKernelGGL(csek::count_active_kernel, grd, blk, 0, B.stream, S, P.n, B.d_counts + p);
-        if (!P.shares || J.round >= J.cfg.share_max_rounds) continue;
-        const csek::ShareScratch ss = csek::share_scratch(P.scratch, P.n);
-        hipLaunchKernelGGL(csek::share_rank_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src, ss);
-        hipLaunchKernelGGL(csek::share_target_kernel, grd, blk, 0, B.stream, S, P.n, P.n_src,
-                           ctx->schemes[J.scheme].comp[P.comp].n_fmax, (uint32_t)P.comp, J.cfg.seed,
-                           J.cfg.share_dst_pm, J.round, ss);
+    HIP_TRY(ctx, hipStreamBeginCapture(B.gstream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_groups(ctx, B, B.gstream);
+    if (rc == CSE_OK) {
+        const dim3 pg(B.pool_grid_x, (unsigned)n_pools), blk(256);
+        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), blk, 0, B.gstream, B.d_counts,
+                           n_pools, 0);
+        hipLaunchKernelGGL(csek::pools_count_kernel, pg, blk, 0, B.gstream, B.d_pools, B.d_counts);
+        hipLaunchKernelGGL(csek::pools_rank_kernel, pg, blk, 0, B.gstream, B.d_pools);
+        hipLaunchKernelGGL(csek::pools_target_kernel, pg, blk, 0, B.gstream, B.d_pools);
+        hipLaunchKernelGGL(csek::pools_round_kernel, dim3(1), blk, 0, B.gstream, B.d_pools, n_pools);
+        hipError_t e = hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost,
+                                      B.gstream);
+        if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
     }
-    HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost, B.stream));
-    HIP_TRY(ctx, hipStreamSynchronize(B.stream));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B.gstream, &g);
+    if (rc == CSE_OK && e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (rc == CSE_OK) {
+        e = hipGraphInstantiate(&B.gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+}
+
+int round_once(cse_ctx* ctx, BatchRec& B) {
+    if (!B.gstream) HIP_TRY(ctx, hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking));
+    if (!B.ev_order) HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_order, hipEventDisableTiming));
+    if (!B.gexec) {
+        int rc = capture_round(ctx, B);
+        if (rc) return rc;
+    }
+    HIP_TRY(ctx, hipEventRecord(B.ev_order, B.stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(B.gstream, B.ev_order, 0));
+    HIP_TRY(ctx, hipGraphLaunch(B.gexec, B.gstream));
+    HIP_TRY(ctx, hipStreamSynchronize(B.gstream));
+    const int n_pools = (int)B.pools.size();
     std::map<int, long long> active;
     for (int p = 0; p < n_pools; ++p) active[B.pools[p].job] += B.h_counts[p];
     for (auto& kv : active) {
@@ -775,7 +878,7 @@ int run_batch(cse_ctx* ctx, BatchRec& B) {
     }
     int rc = B.built ? CSE_OK : build_segments(ctx, B);
     if (rc) return rc;
-    if (!B.rounds) return launch_groups(ctx, B);
+    if (!B.rounds) return launch_groups(ctx, B, B.stream);
     for (;;) {
         rc = round_once(ctx, B);
         if (rc) return rc;

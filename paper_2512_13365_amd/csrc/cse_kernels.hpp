@@ -141,6 +141,7 @@ struct UnitState {         // per process arrays of one component
     unsigned long long* ops;
     unsigned long long* finish;
     const unsigned long long* t0;
+    int32_t* round;        // the job's sharing-round counter (shared by its components)
     char* gs_base;         // HBM-resident unit state (large systems), else null
     unsigned long long gs_stride;  // bytes of HBM state per unit
 };
@@ -1260,7 +1261,10 @@ __global__ void best_cost_kernel(const int32_t* cost, uint32_t n, int32_t* out) 
 // Job start stamp and per-unit state initialisation.
 __global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (stamp && i == 0) *(unsigned long long*)S.t0 = wall_clock64();
+    if (stamp && i == 0) {
+        *(unsigned long long*)S.t0 = wall_clock64();
+        *S.round = 0;
+    }
     if (i >= n_units) return;
     S.t[i] = 0;
     S.cost[i] = 0;

@@ -37,52 +37,77 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int v) {
     if (i < n) p[i] = v;
 }
 
-// Number of active units of a pool, added to *out.
-__global__ void count_active_kernel(UnitState S, uint32_t n, int32_t* out) {
+// One pool (the units of one component of one job) for the round kernels,
+// which cover every pool of a batch in one launch each (grid y = pool).
+struct PoolDev {
+    UnitState S;
+    ShareScratch sc;
+    uint64_t seed;
+    uint32_t n, n_src, comp, dst_pm, max_rounds, shares;
+    int32_t n_fmax;
+    uint32_t first_of_job;  // advances the job's round counter
+};
+
+// Active units per pool (counts[p] starts at 0).
+__global__ void pools_count_kernel(const PoolDev* __restrict__ pools, int32_t* counts) {
+    const PoolDev& P = pools[blockIdx.y];
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool a = u < n && S.active[u] != 0;
+    const bool a = u < P.n && P.S.active[u] != 0;
     const int c = __popcll(__ballot(a));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&counts[blockIdx.y], c);
 }
 
-// Rank every unit by (cost, process); mark the first n_src and list them in
-// rank order.
-__global__ void share_rank_kernel(UnitState S, uint32_t n, uint32_t n_src, ShareScratch sc) {
+// Sources of every sharing pool below its round limit: rank by (cost,
+// process), mark the first n_src and list them in rank order.
+__global__ void pools_rank_kernel(const PoolDev* __restrict__ pools) {
+    const PoolDev& P = pools[blockIdx.y];
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const unsigned long long mine = ((unsigned long long)(uint32_t)S.cost[u] << 32) | u;
+    if (!P.shares || (uint32_t)*P.S.round >= P.max_rounds || u >= P.n) return;
+    const int32_t* cost = P.S.cost;
+    const unsigned long long mine = ((unsigned long long)(uint32_t)cost[u] << 32) | u;
     uint32_t below = 0;
-    for (uint32_t v = 0; v < n && below < n_src; ++v) {
-        const unsigned long long kv = ((unsigned long long)(uint32_t)S.cost[v] << 32) | v;
+    for (uint32_t v = 0; v < P.n && below < P.n_src; ++v) {
+        const unsigned long long kv = ((unsigned long long)(uint32_t)cost[v] << 32) | v;
         below += kv < mine ? 1u : 0u;
     }
-    const bool src = below < n_src;
-    sc.is_src[u] = src ? 1 : 0;
-    if (src) sc.src_list[below] = (int32_t)u;
+    const bool src = below < P.n_src;
+    P.sc.is_src[u] = src ? 1 : 0;
+    if (src) P.sc.src_list[below] = (int32_t)u;
 }
 
-// Targets copy a prefix of their source's program; the step kernel replays
-// it at its next launch.  Sources are never targets of the same event, so
-// every copy reads a program that no thread writes concurrently.
-__global__ void share_target_kernel(UnitState S, uint32_t n, uint32_t n_src, int n_fmax, uint32_t comp,
-                                    uint64_t seed, uint32_t dst_pm, uint32_t round, ShareScratch sc) {
+// Targets of every sharing pool copy a prefix of their source's program
+// (the step kernel replays it at its next launch).  Sources are never
+// targets of the same event, so every copy reads a program nobody writes.
+__global__ void pools_target_kernel(const PoolDev* __restrict__ pools) {
+    const PoolDev& P = pools[blockIdx.y];
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n || !S.active[u] || sc.is_src[u]) return;
-    const U4 r = philox10(u, domain(TAG_SHARE, comp, 0, 0), round, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
-    if (scale_u32(r.x, 1000u) >= dst_pm) return;
-    const int src = sc.src_list[scale_u32(r.y, n_src)];
+    if (!P.shares || u >= P.n) return;
+    const uint32_t round = (uint32_t)*P.S.round;
+    if (round >= P.max_rounds) return;
+    const UnitState& S = P.S;
+    if (!S.active[u] || P.sc.is_src[u]) return;
+    const U4 r = philox10(u, domain(TAG_SHARE, P.comp, 0, 0), round, 0u, (uint32_t)P.seed,
+                          (uint32_t)(P.seed >> 32));
+    if (scale_u32(r.x, 1000u) >= P.dst_pm) return;
+    const int src = P.sc.src_list[scale_u32(r.y, P.n_src)];
     const int L = S.t[src];
     if (L == 0) return;
     int kmax = (3 * L) / 4;
     if (kmax < 1) kmax = 1;
     const int k = 1 + (int)scale_u32(r.z, (uint32_t)kmax);
-    const size_t nf = (size_t)(n_fmax > 0 ? n_fmax : 1);
+    const size_t nf = (size_t)(P.n_fmax > 0 ? P.n_fmax : 1);
     const uint32_t* from = S.prog + (size_t)src * nf;
     uint32_t* to = S.prog + (size_t)u * nf;
     for (int i = 0; i < k; ++i) to[i] = from[i];
     S.t[u] = k;
     S.epoch[u] += 1;
     S.k0[u] = k;
+}
+
+// End of a round: every job's round counter advances once.
+__global__ void pools_round_kernel(const PoolDev* __restrict__ pools, int n_pools) {
+    for (int p = threadIdx.x; p < n_pools; p += blockDim.x)
+        if (pools[p].first_of_job) *pools[p].S.round += 1;
 }
 
 }  // namespace csek
