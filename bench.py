@@ -110,6 +110,7 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     wl = workloads.plain_4x4x4()
     sc, rs = wl.schemes[0], wl.runs[0]
     kw = rs.as_kwargs()
+    kw["count_path"] = COUNT_PATHS[args.count_path]
     if args.strategy:
         kw["weights"] = {args.strategy: 1}
     sid = cse.cse_scheme_load(ctx, *sc.systems)
@@ -156,7 +157,7 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     if not args.no_cpu_baseline:
         n_threads = min(16, os.cpu_count() or 1)
         log(f"[bench] cpu oracle on {n_threads} threads (full workload)")
-        steps, dt = cpu_baseline(sc.systems, kw, n_threads)
+        steps, dt = cpu_baseline(sc.systems, {k: v for k, v in kw.items() if k != "count_path"}, n_threads)
         out["cpu_baseline"] = {"value": steps / dt, "unit": "substitution steps/s", "cores": n_threads,
                                "kind": "oracle",
                                "sample": f"full workload: {rs.n_proc} processes x 3 components, "
@@ -164,14 +165,22 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     return out
 
 
-def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=1):
+def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=1, autotune=False):
     """32 uneven schemes: one batched launch vs 32 sequential plain launches,
-    same pools and seeds (so the same results)."""
+    same pools and seeds (so the same results).  With autotune, every
+    component first gets its fastest layout from cse_autotune (timed apart)."""
     wl = workloads.batch_uneven()
     sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc in wl.schemes]
     cfgs = [cse.cse_run_cfg(**rs.as_kwargs()) for rs in wl.runs]
     n_procs = [rs.n_proc for rs in wl.runs]
     stats = {}
+    tuning = None
+    if autotune:
+        t0 = time.perf_counter()
+        chosen = [cse.cse_autotune(ctx, s, c, stream) for s, c in zip(sids, cfgs)]
+        tuning = {"seconds": time.perf_counter() - t0,
+                  "layouts": [[x for x in ch if x >= 0] for ch in chosen]}
+        log(f"[bench] autotune: {tuning['seconds']:.1f} s")
     for mode in ("batched", "plain"):
         best_t = None
         for _ in range(reps):
@@ -216,7 +225,11 @@ def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=1):
             "batched": {k: v for k, v in stats["batched"].items() if k != "best_additions"},
             "plain": {k: v for k, v in stats["plain"].items() if k != "best_additions"},
             "speedup": stats["batched"]["steps_per_s"] / stats["plain"]["steps_per_s"],
-            "scheme_best_additions": stats["batched"]["best_additions"], "identical_results": same}
+            "scheme_best_additions": stats["batched"]["best_additions"], "identical_results": same,
+            "autotune": tuning}
+
+
+COUNT_PATHS = {"auto": 0, "popcount": 1, "mfma": 2}
 
 
 def run_6x6x6(args, cse, workloads, torch, ctx, stream):
@@ -224,7 +237,7 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
     sc, rs = wl.schemes[0], wl.runs[0]
     sid = cse.cse_scheme_load(ctx, *sc.systems)
     info = cse.cse_scheme_info(ctx, sid)
-    cfg = cse.cse_run_cfg(**rs.as_kwargs())
+    cfg = cse.cse_run_cfg(**rs.as_kwargs(), count_path=COUNT_PATHS[args.count_path])
     job = cse.cse_launch(ctx, sid, cfg, stream)
     cse.cse_wait(ctx, job)
     gpu_s = timed_relaunch(cse, ctx, job, stream, torch, args.steps, args.warmup)
@@ -239,7 +252,7 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
         ms_per_step=gpu_s / args.steps * 1e3,
         config={"workload": "plain-6x6x6-r160: U,V 160x36, W^T 36x160, p=0.15, row nnz in [1,12]; 16384 "
                             "processes, paper weights, proc0 = g; sharing every 32 steps, 1% -> 10%",
-                "n_proc": rs.n_proc, "substitutions_per_step": subs},
+                "n_proc": rs.n_proc, "substitutions_per_step": subs, "count_path": args.count_path},
         time_to_best_ms={"U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
                          "scheme": max(t for _, t in ttb) * 1e3},
         best_additions={"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0], "scheme": sum(b for b, _ in ttb),
@@ -330,6 +343,9 @@ def main():
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
+    ap.add_argument("--autotune", action="store_true", help="batch: pick component layouts with cse_autotune first")
+    ap.add_argument("--count-path", default="auto", choices=list(COUNT_PATHS),
+                    help="4x4x4 / 6x6x6: how the input's pair counts are computed (same results)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
     ap.add_argument("--serve-budget-gib", type=int, default=96, help="serving: device state budget")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -364,7 +380,7 @@ def main():
         elif args.workload == "6x6x6":
             out = run_6x6x6(args, cse, workloads, torch, ctx, stream)
         elif args.workload == "batch":
-            bp = batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2)
+            bp = batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2, autotune=args.autotune)
             out = base_line(args, value=bp["batched"]["steps_per_s"], unit="substitution steps/s",
                             ms_per_step=None, config={"workload": bp["workload"]}, batched_vs_plain=bp)
         else:

@@ -65,6 +65,10 @@ extern "C" {
 #define CSE_COUNT_POPCOUNT 1   /* wavefront popcount over column bitsets */
 #define CSE_COUNT_MFMA     2   /* int8 MFMA Gram product for the first count */
 
+/* Layout of a component's unit state (results never depend on it). */
+#define CSE_LAYOUT_HBM     1   /* bulk state in per-unit HBM slots instead of LDS */
+#define CSE_LAYOUT_RANGE   2   /* gi over per-variable ranges instead of masks */
+
 /* States of a job submitted to a server. */
 #define CSE_JOB_QUEUED  0   /* waiting for admission */
 #define CSE_JOB_RUNNING 1   /* admitted; advances one round per tick */
@@ -120,6 +124,21 @@ int32_t cse_scheme_load(cse_ctx* ctx,
 int32_t cse_scheme_info(cse_ctx* ctx, int32_t scheme_id, int32_t* n_comp, int32_t info[12]);
 /* Free a scheme; CSE_EBUSY while a job of it has not been released. */
 int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
+
+/* Query (layout < 0) or set the layout (CSE_LAYOUT_* bits) of component
+ * `comp`; *current (may be NULL) receives the layout in effect before the
+ * call.  Loading picks a layout from the system's size (state in HBM when it
+ * exceeds 64 KB of LDS, range form of gi for large candidate sets).
+ * CSE_EBUSY while a job of the scheme exists; CSE_ENOMEM if the state does not
+ * fit in LDS for an LDS layout.  Unit results are the same in every layout. */
+int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t layout, int32_t* current);
+
+/* Pick each component's fastest layout by timing bounded probe runs of
+ * `cfg` (at most 1024 processes, 32 steps each, no sharing) on `stream`, for
+ * every layout that fits (the mask form of gi only where the input's masks
+ * fit their capacity); layouts[c] (may be NULL) receives the choice.
+ * Blocking.  CSE_EBUSY while a job of the scheme exists. */
+int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream, int32_t layouts[3]);
 
 /* Launch n_proc processes on every component of a scheme (Algorithm 1 per
  * unit, strategies of Sec. 3.4, sharing rounds of Sec. 3.5.2 when

@@ -22,13 +22,15 @@ LIB_PATH = os.path.join(HERE, "libcse.so")
 
 STRATEGIES = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
 CSE_COUNT_AUTO, CSE_COUNT_POPCOUNT, CSE_COUNT_MFMA = 0, 1, 2
+CSE_LAYOUT_HBM, CSE_LAYOUT_RANGE = 1, 2
 
 STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4: "CSE_EHIP",
           -5: "CSE_EBUSY", -6: "CSE_ENOENT", -7: "CSE_ECANCELED"}
 
 # Every symbol declared in include/cse.h.
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
-           "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_launch", "cse_launch_batch",
+           "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_scheme_layout", "cse_autotune",
+           "cse_launch", "cse_launch_batch",
            "cse_relaunch", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results", "cse_get_programs",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy")
@@ -99,6 +101,10 @@ def load_library(path: str = LIB_PATH):
     L.cse_poll.restype = i32
     L.cse_cancel.argtypes = [vp, i32]
     L.cse_cancel.restype = i32
+    L.cse_scheme_layout.argtypes = [vp, i32, i32, i32, P(i32)]
+    L.cse_scheme_layout.restype = i32
+    L.cse_autotune.argtypes = [vp, i32, ctypes.c_void_p, vp, P(i32)]
+    L.cse_autotune.restype = i32
     L.cse_wait.argtypes = [vp, i32]
     L.cse_wait.restype = i32
     L.cse_get_unit_results.argtypes = [vp, i32, i32, i32, P(i32), P(i32), P(i32), P(i32), P(i32),
@@ -263,6 +269,21 @@ def cse_wait(ctx, job_id):
 
 def cse_cancel(ctx, job_id):
     _check(ctx, load_library().cse_cancel(ctx, job_id))
+
+
+def cse_scheme_layout(ctx, scheme_id, comp, layout=-1) -> int:
+    """Set (layout >= 0) or query the layout of a component; returns the
+    layout in effect before the call."""
+    cur = ctypes.c_int32()
+    _check(ctx, load_library().cse_scheme_layout(ctx, scheme_id, comp, layout, ctypes.byref(cur)))
+    return cur.value
+
+
+def cse_autotune(ctx, scheme_id, cfg, stream):
+    """Pick each component's fastest layout; returns the chosen layouts."""
+    out = (ctypes.c_int32 * 3)(-1, -1, -1)
+    _check(ctx, load_library().cse_autotune(ctx, scheme_id, ctypes.byref(cfg), _stream_ptr(stream), out))
+    return list(out)
 
 
 def cse_get_unit_results(ctx, job_id, comp, n_proc):

@@ -284,6 +284,15 @@ int ensure_gram_lists(cse_ctx* ctx, DevComp& c) {
     return CSE_OK;
 }
 
+// Layout of a component (CSE_LAYOUT_*): bulk state in HBM slots instead of
+// LDS, and gi over per-variable ranges instead of masks.  Results do not
+// depend on it.
+int layout_code(const DevComp& c) { return (c.gs ? CSE_LAYOUT_HBM : 0) | (c.adj ? CSE_LAYOUT_RANGE : 0); }
+void set_layout(DevComp& c, int layout) {
+    c.gs = (layout & CSE_LAYOUT_HBM) != 0;
+    c.adj = (layout & CSE_LAYOUT_RANGE) != 0;
+}
+
 int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
     if (!A || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
     if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
@@ -1040,6 +1049,119 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id) {
 
 int32_t cse_launch(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream, int32_t* job_id) {
     return cse_launch_batch(ctx, &scheme_id, cfg, 1, stream, job_id);
+}
+
+}  // extern "C"
+
+namespace {
+bool scheme_busy(cse_ctx* ctx, int scheme_id) {
+    for (auto& kv : ctx->jobs)
+        if (kv.second.scheme == scheme_id) return true;
+    return false;
+}
+
+// Time one layout of a component: a job on a temporary one-component scheme
+// that shares the component's device buffers, launched once, then two timed
+// relaunches on the stream.
+// relaunches on the stream.  A layout whose first launch already takes more
+// than three times `bound` ms is not timed further (*ms = that time).
+int probe_layout(cse_ctx* ctx, const DevComp& probe, const cse_run_cfg& pc, hipStream_t s, float bound,
+                 float* ms) {
+    const int sid = ctx->next_scheme++;
+    SchemeRec& tmp = ctx->schemes[sid];
+    tmp.n_comp = 1;
+    tmp.comp[0] = probe;
+    int32_t job = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        ctx->schemes.erase(sid);
+        return fail(ctx, CSE_EHIP, "hipEventCreate failed");
+    }
+    int rc = hipEventRecord(e0, s) == hipSuccess ? CSE_OK : fail(ctx, CSE_EHIP, "hipEventRecord failed");
+    if (rc == CSE_OK) rc = cse_launch(ctx, sid, &pc, s, &job);
+    if (rc == CSE_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+        rc = fail(ctx, CSE_EHIP, "probe timing failed");
+    if (rc == CSE_OK) rc = cse_wait(ctx, job);
+    if (rc == CSE_OK && !(bound > 0.f && *ms > 3.f * bound)) {
+        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipEventRecord failed");
+        for (int r = 0; r < 2 && rc == CSE_OK; ++r) rc = cse_relaunch(ctx, job, nullptr, s);
+        if (rc == CSE_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+            rc = fail(ctx, CSE_EHIP, "probe timing failed");
+        if (rc == CSE_OK) rc = cse_wait(ctx, job);
+        *ms *= 0.5f;
+    }
+    std::string keep = ctx->err;
+    if (job >= 0) (void)cse_job_release(ctx, job);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ctx->schemes.erase(sid);  // the buffers belong to the real component
+    ctx->err = keep;
+    return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t layout, int32_t* current) {
+    if (!ctx) return CSE_EINVAL;
+    auto it = ctx->schemes.find(scheme_id);
+    if (it == ctx->schemes.end()) return fail(ctx, CSE_ENOENT, "unknown scheme %d", scheme_id);
+    if (comp < 0 || comp >= it->second.n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    DevComp& dc = it->second.comp[comp];
+    if (current) *current = layout_code(dc);
+    if (layout < 0) return CSE_OK;
+    if (layout > (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE)) return fail(ctx, CSE_EINVAL, "unknown layout %d", layout);
+    if (scheme_busy(ctx, scheme_id)) return fail(ctx, CSE_EBUSY, "scheme %d has jobs; release them first", scheme_id);
+    DevComp probe = dc;
+    set_layout(probe, layout);
+    if (!probe.gs && lds_bytes(probe) > ctx->lds_max)
+        return fail(ctx, CSE_ENOMEM, "layout %d needs %zu B of LDS per unit (max %zu)", layout, lds_bytes(probe),
+                    ctx->lds_max);
+    set_layout(dc, layout);
+    return CSE_OK;
+}
+
+int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream, int32_t layouts[3]) {
+    if (!ctx) return CSE_EINVAL;
+    auto it = ctx->schemes.find(scheme_id);
+    if (it == ctx->schemes.end()) return fail(ctx, CSE_ENOENT, "unknown scheme %d", scheme_id);
+    int rc = validate_cfg(ctx, cfg);
+    if (rc) return rc;
+    if (scheme_busy(ctx, scheme_id)) return fail(ctx, CSE_EBUSY, "scheme %d has jobs; release them first", scheme_id);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // A bounded probe: at most 1024 processes, 32 steps each, no sharing.
+    cse_run_cfg pc = *cfg;
+    pc.n_proc = std::min<uint32_t>(cfg->n_proc, 1024);
+    pc.step_cap = cfg->step_cap ? std::min<uint32_t>(cfg->step_cap, 32) : 32;
+    pc.share_every = pc.share_src_pm = pc.share_dst_pm = pc.share_max_rounds = 0;
+    pc.count_path = CSE_COUNT_POPCOUNT;
+    for (int c = 0; c < it->second.n_comp; ++c) {
+        DevComp& dc = ctx->schemes[scheme_id].comp[c];
+        int best = layout_code(dc);
+        float best_ms = -1.f;
+        // The mask form of gi is skipped where the input's masks already
+        // exceed their capacity (its steps would take the O(m^2) form).
+        const bool masks_fit = (long long)dc.n_x * ((dc.m0 + 31) / 32) <= 2ll * dc.m_words;
+        for (int lay = 0; lay <= (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE); ++lay) {
+            DevComp probe = dc;
+            set_layout(probe, lay);
+            if (!probe.gs && lds_bytes(probe) > ctx->lds_max) continue;
+            if (!probe.adj && !masks_fit) continue;
+            float ms = 0.f;
+            rc = probe_layout(ctx, probe, pc, (hipStream_t)stream, best_ms, &ms);
+            if (rc) return rc;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best = lay;
+            }
+        }
+        set_layout(dc, best);
+        if (layouts) layouts[c] = best;
+    }
+    return CSE_OK;
 }
 
 int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs, int32_t n,

@@ -406,3 +406,48 @@ def test_cancel_keeps_prefixes_and_poll_reports_best(gpu, oracle):
         assert (prog[u][:40] == ref["prog"][i][:40]).all()
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
+
+
+def run_loaded(gpu, sid, kw):
+    """Run a job on an already loaded one-component scheme."""
+    cse, ctx, torch = gpu
+    info = cse.cse_scheme_info(ctx, sid)
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    cse.cse_wait(ctx, job)
+    r = cse.cse_get_unit_results(ctx, job, 0, kw["n_proc"])
+    r["prog"] = cse.cse_get_programs(ctx, job, 0, kw["n_proc"], max(1, info[0][2]))
+    return job, r
+
+
+@pytest.mark.parametrize("rows,cols,p,cap", [(60, 18, 0.3, 0), (160, 36, 0.15, 40), (42, 197, 0.2, 30)])
+def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
+    """Every layout (unit state in LDS or in HBM slots, gi over masks or over
+    ranges) and the autotuner's choice reproduce the oracle's runs."""
+    cse, ctx, torch = gpu
+    A = workloads.random_system(rows * 31 + cols, rows, cols, p)
+    kw = dict(seed=rows + 5, n_proc=64, weights=dict(ALL_W), proc0_greedy=True, step_cap=cap)
+    ref = compare(oracle, [A], kw, "layouts")[0]
+    sid = cse.cse_system_load(ctx, A)
+    tried = 0
+    for lay in range(4):
+        try:
+            cse.cse_scheme_layout(ctx, sid, 0, lay)
+        except cse.CseError as e:
+            assert "CSE_ENOMEM" in str(e) and not lay & cse.CSE_LAYOUT_HBM
+            continue
+        assert cse.cse_scheme_layout(ctx, sid, 0) == lay
+        say(f"[gpu] layout {lay}: system {rows}x{cols}")
+        job, got = run_loaded(gpu, sid, kw)
+        with pytest.raises(cse.CseError, match="CSE_EBUSY"):
+            cse.cse_scheme_layout(ctx, sid, 0, lay ^ cse.CSE_LAYOUT_RANGE)
+        cse.cse_job_release(ctx, job)
+        assert_same(got, ref, f"layout {lay} {rows}x{cols}")
+        tried += 1
+    assert tried >= 2
+    say(f"[gpu] autotune: system {rows}x{cols}")
+    chosen = cse.cse_autotune(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    assert chosen[0] == cse.cse_scheme_layout(ctx, sid, 0) and chosen[1:] == [-1, -1]
+    job, got = run_loaded(gpu, sid, kw)
+    cse.cse_job_release(ctx, job)
+    assert_same(got, ref, f"autotuned layout {chosen[0]} {rows}x{cols}")
+    cse.cse_scheme_free(ctx, sid)
