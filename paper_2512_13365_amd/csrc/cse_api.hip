@@ -95,6 +95,7 @@ struct JobRec {
 struct LaunchGroup {
     int W = 0;
     bool gs = false;
+    bool adj = false;
     uint32_t n_grid = 0;
     size_t lds = 0;
     int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
@@ -567,29 +568,30 @@ void free_batch_device(BatchRec& B) {
 
 // Dynamic LDS above 64 KB must be allowed per kernel before launches (and
 // before a launch is captured into a graph).
-template <int W, bool GS>
+template <int W, bool GS, bool ADJ>
 int set_lds_limit_w(cse_ctx* ctx, size_t lds) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS>,
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS, ADJ>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return CSE_OK;
 }
-template <bool GS>
+template <bool GS, bool ADJ>
 int set_lds_limit_gs(cse_ctx* ctx, int W, size_t lds) {
     switch (W) {
-    case 1: return set_lds_limit_w<1, GS>(ctx, lds);
-    case 2: return set_lds_limit_w<2, GS>(ctx, lds);
-    case 3: return set_lds_limit_w<3, GS>(ctx, lds);
-    case 4: return set_lds_limit_w<4, GS>(ctx, lds);
-    case 5: return set_lds_limit_w<5, GS>(ctx, lds);
-    case 6: return set_lds_limit_w<6, GS>(ctx, lds);
-    case 7: return set_lds_limit_w<7, GS>(ctx, lds);
-    case 8: return set_lds_limit_w<8, GS>(ctx, lds);
+    case 1: return set_lds_limit_w<1, GS, ADJ>(ctx, lds);
+    case 2: return set_lds_limit_w<2, GS, ADJ>(ctx, lds);
+    case 3: return set_lds_limit_w<3, GS, ADJ>(ctx, lds);
+    case 4: return set_lds_limit_w<4, GS, ADJ>(ctx, lds);
+    case 5: return set_lds_limit_w<5, GS, ADJ>(ctx, lds);
+    case 6: return set_lds_limit_w<6, GS, ADJ>(ctx, lds);
+    case 7: return set_lds_limit_w<7, GS, ADJ>(ctx, lds);
+    case 8: return set_lds_limit_w<8, GS, ADJ>(ctx, lds);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", W);
     }
 }
 int set_lds_limit(cse_ctx* ctx, const LaunchGroup& G) {
     if (G.lds <= 65536) return CSE_OK;
-    return G.gs ? set_lds_limit_gs<true>(ctx, G.W, G.lds) : set_lds_limit_gs<false>(ctx, G.W, G.lds);
+    if (G.gs) return G.adj ? set_lds_limit_gs<true, true>(ctx, G.W, G.lds) : set_lds_limit_gs<true, false>(ctx, G.W, G.lds);
+    return G.adj ? set_lds_limit_gs<false, true>(ctx, G.W, G.lds) : set_lds_limit_gs<false, false>(ctx, G.W, G.lds);
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -609,12 +611,13 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
     B.seg_job.clear();
     B.groups.clear();
     B.pools.clear();
-    for (int cls = 0; cls < 16; ++cls) {
-        const int W = 1 + (cls >> 1);
-        const bool gs = cls & 1;
+    for (int cls = 0; cls < 32; ++cls) {
+        const int W = 1 + (cls >> 2);
+        const bool gs = cls & 1, adj = (cls >> 1) & 1;
         LaunchGroup G;
         G.W = W;
         G.gs = gs;
+        G.adj = adj;
         G.seg_begin = (int)B.segs.size();
         uint32_t unit = 0;
         for (int jid : B.jobs) {
@@ -623,7 +626,7 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             const SchemeRec& sc = ctx->schemes[J.scheme];
             for (int c = 0; c < J.n_comp; ++c) {
                 const DevComp& dc = sc.comp[c];
-                if (dc.W != W || dc.gs != gs) continue;
+                if (dc.W != W || dc.gs != gs || dc.adj != adj) continue;
                 csek::Segment s{};
                 s.C = comp_args(dc, c, J.cfg.count_path == CSE_COUNT_MFMA);
                 s.R = run_args(ctx, J);
@@ -745,37 +748,42 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
     return CSE_OK;
 }
 
-template <int W, bool GS>
+template <int W, bool GS, bool ADJ>
 int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                    int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    hipLaunchKernelGGL((csek::step_kernel<W, GS>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
                        d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;
 }
 
-template <bool GS>
+template <bool GS, bool ADJ>
 int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                     int* d_err, hipStream_t s) {
     switch (G.W) {
-    case 1: return launch_group_w<1, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 2: return launch_group_w<2, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 3: return launch_group_w<3, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 4: return launch_group_w<4, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 5: return launch_group_w<5, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 6: return launch_group_w<6, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 7: return launch_group_w<7, GS>(ctx, G, d_segs, d_order, d_err, s);
-    case 8: return launch_group_w<8, GS>(ctx, G, d_segs, d_order, d_err, s);
+    case 1: return launch_group_w<1, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 2: return launch_group_w<2, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 3: return launch_group_w<3, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 4: return launch_group_w<4, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 5: return launch_group_w<5, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 6: return launch_group_w<6, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 7: return launch_group_w<7, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 8: return launch_group_w<8, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
     }
 }
 
 int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
     for (const LaunchGroup& G : B.groups) {
-        int rc = G.gs ? launch_group_gs<true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                      : launch_group_gs<false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        int rc;
+        if (G.gs)
+            rc = G.adj ? launch_group_gs<true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                       : launch_group_gs<true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        else
+            rc = G.adj ? launch_group_gs<false, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                       : launch_group_gs<false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         if (rc) return rc;
     }
     return CSE_OK;

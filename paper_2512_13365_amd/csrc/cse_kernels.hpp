@@ -77,6 +77,10 @@ __device__ __forceinline__ uint32_t scale_u32(uint32_t u, uint32_t n) {
 // use the device library's DPP sequences; call them in uniform control flow.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+// A pointer known to address global memory (HBM): its accesses compile to
+// global loads and stores, counted by the vector-memory counter alone,
+// instead of generic ones that also wait on the LDS counter.
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -857,18 +861,23 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             int I = 0, X = 0, j = 0;
             // 1. (x, a) and (x, b), x < a: every (x, a) entry, and the (x, b)
             //    entries before (a, b).
+            // Each stream keeps its head and the entry after it, so the load
+            // issued when a stream advances is needed one advance later.
             int ia = ra.z, ib = rb.z;
             uint32_t ea = ia < ra.w ? tp[ia] : kEnd;
+            uint32_t ea1 = ia + 1 < ra.w ? tp[ia + 1] : kEnd;
             uint32_t eb = ib < rb.w ? tp[ib] : kEnd;
-            uint32_t qa = ea == kEnd ? kEnd : (ea & kQ);
-            uint32_t qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
+            uint32_t eb1 = ib + 1 < rb.w ? tp[ib + 1] : kEnd;
             uint32_t cw = co.word(0);
             int left = 32;
-            while ((qa & qb) != kEnd) {
+            for (;;) {
+                const uint32_t qa = ea == kEnd ? kEnd : (ea & kQ);
+                const uint32_t qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
+                if ((qa & qb) == kEnd) break;
                 const bool ta = qa < qb;
-                const int w = (int)((ta ? ea : eb) >> 23);
-                I += w;
-                X += w & -(int)(cw & 1u);
+                const uint32_t w = (ta ? ea : eb) >> 23;
+                I += (int)w;
+                X += (int)((cw & 1u) * w);
                 cw >>= 1;
                 ++j;
                 if (--left == 0) {
@@ -877,12 +886,12 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
                 }
                 if (ta) {
                     ++ia;
-                    ea = ia < ra.w ? tp[ia] : kEnd;
-                    qa = ea == kEnd ? kEnd : (ea & kQ);
+                    ea = ea1;
+                    ea1 = ia + 1 < ra.w ? tp[ia + 1] : kEnd;
                 } else {
                     ++ib;
-                    eb = ib < rb.w ? tp[ib] : kEnd;
-                    qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
+                    eb = eb1;
+                    eb1 = ib + 1 < rb.w ? tp[ib + 1] : kEnd;
                 }
             }
             // 2. (a, y): the canonical range of a without p.
@@ -1061,7 +1070,10 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // step_cap.  Grid unit g maps to segment s and process g - unit_begin; block
 // b runs grid unit order[b].
 // ---------------------------------------------------------------------------
-template <int W, bool GS>
+// W: row words; GS: bulk state in HBM slots; ADJ: gi over per-variable
+// ranges (large candidate sets) instead of masks.  Each combination is its
+// own kernel, so a launch carries only the code its units run.
+template <int W, bool GS, bool ADJ>
 __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ order, uint32_t n_grid,
                                                      int* err) {
@@ -1078,8 +1090,13 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, C.adj, C.kbits);
-    char* bulk = GS ? S.gs_base + (size_t)proc * S.gs_stride : (char*)smem;
+    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, ADJ ? 1 : 0, C.kbits);
+    // HBM slots are addressed from a kernel argument (which the compiler
+    // knows to be global memory) plus a byte offset, so every access to them
+    // compiles to global rather than generic loads and stores.
+    char* const garg = (char*)segs;
+    char* bulk = GS ? garg + ((uintptr_t)(S.gs_base + (size_t)proc * S.gs_stride) - (uintptr_t)garg)
+                    : (char*)smem;
     char* lists = GS ? (char*)smem : (char*)smem + BL.bytes;
     uint64_t* colP = (uint64_t*)(bulk + BL.colP);
     uint64_t* colN = (uint64_t*)(bulk + BL.colN);
@@ -1108,7 +1125,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     const uint32_t alpha_q = pu.y >> 17;
     const uint32_t beta_q = 32768u + (pu.z >> 17);
     // The second candidate ordering is kept only where gi walks ranges.
-    const bool need_tl = C.adj && (strat == S_GI || strat == S_MIX);
+    const bool need_tl = ADJ && (strat == S_GI || strat == S_MIX);
 
     for (int i = l; i < n_vmax * W; i += kWave) {
         const bool in = i < C.n_x * W;
@@ -1198,7 +1215,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
             pick = select_wr(cand, m, su.z);
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
-            if (C.adj) {
+            if constexpr (ADJ) {
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tp, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tp, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
                                         dw, &n_int, &n_blk);
@@ -1224,7 +1241,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         cost -= c - 1;
         ++executed;
         ops += step_ops(s, m, n_int, n_blk, C.n_e, n_live);
-        if (C.adj) {
+        if constexpr (ADJ) {
             int n_new = 0;
             const int m_old = m;
             m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
