@@ -77,6 +77,13 @@ __device__ __forceinline__ uint32_t scale_u32(uint32_t u, uint32_t n) {
 // use the device library's DPP sequences; call them in uniform control flow.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+// c + a * b on 24-bit operands in one instruction (the compiler turns a
+// multiply by a 0/1 value into a compare and a select).
+__device__ __forceinline__ int mad_u24(uint32_t a, uint32_t b, int c) {
+    int r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 // A pointer known to address global memory (HBM): its accesses compile to
 // global loads and stores, counted by the vector-memory counter alone,
 // instead of generic ones that also wait on the LDS counter.
@@ -1024,7 +1031,7 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
                     u &= u - 1u;
                     const uint32_t wq = wrow[bit];
                     I += (int)wq;
-                    X += (int)((cw & 1u) * wq);
+                    X = mad_u24(cw & 1u, wq, X);
                     cw >>= 1;
                 } while (u);
             }
