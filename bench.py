@@ -147,7 +147,7 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
         pcie_inclusive={"readback_ms": readback_s * 1e3,
                         "steps_per_s": subs / (per_step + readback_s),
                         "note": "job plus host copy of all unit results and programs"},
-        roofline={"kernel": "step_kernel<1, false>", "bound": "alu", "achieved": achieved / 1e12,
+        roofline={"kernel": "step_kernel<1, false, false>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
                   "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
                   "algorithmic_ops_per_launch": ops / launches,

@@ -171,13 +171,16 @@ int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done, int32_t best_cost[
 /* Block until the job is done.  CSE_ECANCELED if it was cancelled (its
  * results are still readable). */
 int32_t cse_wait(cse_ctx* ctx, int32_t job_id);
-/* Stop a job early.  A running launch checks the request every 32
- * selection steps of each unit; a unit that stops keeps a consistent state
- * whose program is a prefix of the one it would have built.  A queued server
+/* Stop a job early.  A running launch checks the request every 256
+ * selection steps of each unit (shorter units run to their end); a unit
+ * that stops keeps a consistent state whose program is a prefix of the one
+ * it would have built.  A queued server
  * job leaves the queue; a running server job stops after the current round.
  * A job whose device work already completed is left as it is.  Returns
  * CSE_OK once the request is recorded; cse_wait then returns CSE_ECANCELED.
- * A relaunch clears the request. */
+ * A relaunch clears the request.  This is the one call that may run on
+ * another thread while cse_wait blocks on the same job; otherwise a context
+ * is used by one thread at a time. */
 int32_t cse_cancel(cse_ctx* ctx, int32_t job_id);
 
 /* Per-unit results of component `comp` for processes 0..n-1 (n = n_proc);

@@ -451,3 +451,44 @@ def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
     cse.cse_job_release(ctx, job)
     assert_same(got, ref, f"autotuned layout {chosen[0]} {rows}x{cols}")
     cse.cse_scheme_free(ctx, sid)
+
+
+def test_server_cancel_queued_and_running(gpu, oracle):
+    """A queued server job cancelled before admission never runs; a running
+    one stops at the end of its round and keeps prefixes of the oracle's runs;
+    cse_wait reports both as cancelled."""
+    from cse_helpers import naive_count, replay
+    cse, ctx, torch = gpu
+    A = workloads.random_system(6060, 49, 16, 0.3, 1, 8)
+    kw = dict(seed=21, n_proc=128, weights=dict(ALL_W), proc0_greedy=True)
+    sid = cse.cse_system_load(ctx, A)
+    info = cse.cse_scheme_info(ctx, sid)
+    srv = cse.cse_server_create(ctx, max_state_bytes=64 << 20, round_steps=2, stream=torch.cuda.current_stream())
+    ja = cse.cse_server_submit(srv, sid, cse.cse_run_cfg(**kw))
+    jb = cse.cse_server_submit(srv, sid, cse.cse_run_cfg(**dict(kw, seed=22)))
+    say("[gpu] server cancel: one queued, one running")
+    cse.cse_cancel(ctx, jb)
+    assert cse.cse_server_job_info(srv, jb)[0] == cse.CSE_JOB_DONE
+    with pytest.raises(cse.CseError, match="CSE_ECANCELED"):
+        cse.cse_wait(ctx, jb)
+    running, queued = cse.cse_server_tick(srv)
+    assert (running, queued) == (1, 0)
+    cse.cse_cancel(ctx, ja)
+    running, queued = cse.cse_server_tick(srv)
+    assert (running, queued) == (0, 0)
+    assert cse.cse_server_job_info(srv, ja)[0] == cse.CSE_JOB_DONE
+    with pytest.raises(cse.CseError, match="CSE_ECANCELED"):
+        cse.cse_wait(ctx, ja)
+    got = cse.cse_get_unit_results(ctx, ja, 0, kw["n_proc"])
+    prog = cse.cse_get_programs(ctx, ja, 0, kw["n_proc"], max(1, info[0][2]))
+    ref = oracle.run_pool(A, oracle.make_cfg(**kw), n_threads=THREADS)
+    assert (got["steps"] <= 4).all() and (got["steps"] < ref["steps"]).any()
+    for u in range(kw["n_proc"]):
+        t = int(got["steps"][u])
+        assert (prog[u][:t] == ref["prog"][u][:t]).all(), f"unit {u}: not a prefix"
+        _, cs = replay(A, prog[u][:t])
+        assert int(got["cost"][u]) == naive_count(A) - sum(c - 1 for c in cs)
+    cse.cse_server_release(srv, ja)
+    cse.cse_server_release(srv, jb)
+    cse.cse_server_destroy(srv)
+    cse.cse_scheme_free(ctx, sid)
