@@ -196,7 +196,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
         // The fresh-variable pairs (update) and the gi masks and weights
         // (selection) are never live at the same time: one region.
         const size_t gi = (size_t)m_words * 8 + (((size_t)m_cap * 2 + 7) & ~size_t(7));
-        const size_t up = (size_t)newc_cap * 8;
+        const size_t up = (size_t)newc_cap * 8 + (size_t)((n_vmax + 63) / 64) * 24;
         L.newc = o;
         L.M = o;
         L.wt = o + (size_t)m_words * 8;
@@ -355,10 +355,14 @@ __device__ int analyse_full(const uint64_t* colP, const uint64_t* colN, const ui
 // old pair whose first variable is <= x (k is the largest id), so the new
 // list is an ordered merge of the filtered old list and the new pairs.
 template <int W>
-__device__ int update_candidates(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
-                                 uint64_t* cand, int m, uint64_t* newc, int newc_cap, int m_cap, int a, int b,
-                                 int k, int* err_flags) {
+__device__ int update_candidates(const uint64_t* colP, const uint64_t* colN, const uint32_t* live,
+                                 const int32_t* vpos, int n_live, uint64_t* cand, int m, uint64_t* newc,
+                                 int newc_cap, int m_cap, int a, int b, int k, int* err_flags) {
     const int l = lane_id();
+    // Per 64 live positions: which have a new '+' / '-' pair with k, and the
+    // number of new pairs before them (stored after the new pairs).
+    uint64_t* nmask = newc + newc_cap;
+    int32_t* nbefore = (int32_t*)(nmask + 2 * ((n_live + kWave - 1) / kWave));
     // 1. Recount the pairs touching a or b; compact in place.
     int mf = 0;
     for (int base = 0; base < m; base += kWave) {
@@ -390,6 +394,11 @@ __device__ int update_candidates(const uint64_t* colP, const uint64_t* colN, con
         const int2 c = valid ? pair_counts<W>(colP, colN, x - 1, k - 1) : make_int2(0, 0);
         const bool hp = c.x >= 2, hm = c.y >= 2;
         const uint64_t bp = ballot(hp), bm = ballot(hm);
+        if (l == 0) {
+            nmask[2 * (base / kWave)] = bp;
+            nmask[2 * (base / kWave) + 1] = bm;
+            nbefore[base / kWave] = n_new;
+        }
         const int pos = n_new + lanes_below(bp) + lanes_below(bm);
         if (hp) {
             if (pos < newc_cap) newc[pos] = pair_key(x, k, 0) | ((uint64_t)c.x << 32);
@@ -424,19 +433,18 @@ __device__ int update_candidates(const uint64_t* colP, const uint64_t* colN, con
     __syncthreads();
     // 3b. Move old pairs up by the number of new pairs with a smaller first
     // variable, last chunk first (destinations are increasing in the index).
+    // New pairs (x, k) come from the live positions below the old pair's
+    // first variable: a prefix of the step-2 ballots.
     for (int base = ((mf - 1) / kWave) * kWave; base >= 0; base -= kWave) {
         const int i = base + l;
         const bool valid = i < mf;
         const uint64_t v = valid ? cand[i] : 0ull;
         int shift = 0;
         if (valid) {
-            const int qa = key_a((uint32_t)v);
-            int lo = 0, hi = n_new;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (key_a((uint32_t)newc[mid]) < qa) lo = mid + 1; else hi = mid;
-            }
-            shift = lo;
+            const int pv = vpos[key_a((uint32_t)v) - 1];
+            const int cw = pv / kWave;
+            const uint64_t below = (1ull << (pv % kWave)) - 1ull;
+            shift = nbefore[cw] + popc64(nmask[2 * cw] & below) + popc64(nmask[2 * cw + 1] & below);
         }
         __syncthreads();
         if (valid) cand[i + shift] = v;
@@ -1258,7 +1266,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
             cand2 = sw;
             if (need_tl) update_tl(tl, m_old, remap, newc, n_new);
         } else {
-            m = update_candidates<W>(colP, colN, live, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
+            m = update_candidates<W>(colP, colN, live, vpos, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
                                      key_b(key), k, &err_flags);
         }
     }
