@@ -146,8 +146,10 @@ def test_sharing_dense_targets(gpu, oracle):
 
 def test_invalid_inputs_rejected(gpu):
     cse, ctx, torch = gpu
+    many = np.zeros((2, 40000), np.int8)
+    many[:, :30000] = 1  # 40000 columns + 29999 fresh variables exceed the 15-bit variable ids
     bad = [np.array([[1, 0], [0, 0]], np.int8), np.array([[1, 2]], np.int8), np.zeros((0, 3), np.int8),
-           np.ones((513, 2), np.int8)]
+           np.zeros((3, 0), np.int8), np.ones((513, 2), np.int8), many]
     for A in bad:
         with pytest.raises(cse.CseError) as e:
             cse.cse_system_load(ctx, A)
@@ -233,10 +235,11 @@ def test_batch_equals_separate_jobs(gpu, oracle):
         cse.cse_scheme_free(ctx, sid)
 
 
-@pytest.mark.parametrize("rows,cols,p,cap", [(42, 197, 0.2, 40), (331, 64, 0.12, 25)])
+@pytest.mark.parametrize("rows,cols,p,cap", [(42, 197, 0.2, 40), (331, 64, 0.12, 25), (64, 331, 0.12, 12)])
 def test_hbm_state_large_systems(gpu, oracle, rows, cols, p, cap):
     """Systems whose state exceeds the LDS budget keep it in HBM slots
-    (shapes of the 7x7x4-r197 W^T and the 8x8x8-r331 U components)."""
+    (shapes of the 7x7x4-r197 W^T and the 8x8x8-r331 U and W^T components,
+    the largest of the serving stream)."""
     A = workloads.random_system(rows + 7 * cols, rows, cols, p)
     kw = dict(seed=3, n_proc=12, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True, step_cap=cap)
     check_workload(gpu, oracle, [A], kw, f"hbm-state {rows}x{cols}")
