@@ -352,8 +352,9 @@ def main():
                     help="first run a plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the CSE processes need no collective, and this build "
-              "runs on a single MI355X (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the CSE processes of a pool are independent; across GPUs a pool "
+              "would shard by process index with one small all-gather of sharing keys per round",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -22,8 +22,8 @@
  *     (Algorithm 1, Substitution; Sec. 3.2.1).
  *
  * Points the paper leaves open (random generator, tie-breaks, fixed-point
- * score, coin indexing, sharing schedule) are fixed by the readings listed in
- * the design notes; each is restated where it is used below.
+ * score, coin indexing, sharing schedule) are fixed by explicit readings;
+ * each is stated where it is used below.
  */
 #include <stdint.h>
 #include <stdlib.h>

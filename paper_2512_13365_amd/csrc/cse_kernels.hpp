@@ -5,7 +5,9 @@
 // component reduced by one process.  A launch covers a table of segments;
 // a segment is a contiguous range of units that share one system and one run
 // configuration, so one launch can hold the three components of a scheme or
-// the components of many schemes.  The unit's state lives in LDS:
+// the components of many schemes.  The step kernel is specialised on the row
+// words W, on where the unit's state lives and on the form of gi.  A unit's
+// state:
 //   colP[v][w], colN[v][w]  pos / neg bitsets of variable v over the rows,
 //                           W 64-bit words per column (rows <= 64 W);
 //   live[], vpos[]          ids of the variables with a nonzero column,
@@ -14,8 +16,17 @@
 //   cand[]                  the pairs occurring at least twice, in canonical
 //                           order, one 64-bit entry each: key | c << 32 with
 //                           key = a << 16 | b << 1 | (s < 0);
-//   newc[], M[]             scratch for the pairs of a fresh variable and for
-//                           the per-variable candidate masks of gi.
+//   newc[]                  the pairs of the fresh variable (update scratch);
+//   M[], wt[]               per-variable candidate masks and weights (the
+//                           mask form of gi; they share newc's region);
+//   cand2[], tl[], tp[], pl[], rng[], remap[], kpre[]
+//                           for large candidate sets (the range form of gi):
+//                           a second candidate buffer, the second ordering
+//                           (by second variable) plain and packed with
+//                           weights, weight bit-planes, per-variable ranges
+//                           and the index map of the update.
+// The lists live in LDS; the rest lives in LDS too, or, for systems whose
+// state exceeds the LDS budget, in a per-unit slot in HBM.
 // The pair count of (a, b, +) is popc(Pa & Pb) + popc(Na & Nb) and of
 // (a, b, -) popc(Pa & Nb) + popc(Na & Pb), summed over the row words.
 // Every random draw is a Philox4x32-10 block of a counter that names the
