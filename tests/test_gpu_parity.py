@@ -495,3 +495,40 @@ def test_server_cancel_queued_and_running(gpu, oracle):
     cse.cse_server_release(srv, jb)
     cse.cse_server_destroy(srv)
     cse.cse_scheme_free(ctx, sid)
+
+
+def test_randomized_configurations(gpu, oracle):
+    """A seeded sweep over shapes (1..8 row words), densities, strategy
+    mixes, step caps, gr probabilities, sharing schedules, count paths and
+    layouts: every unit equals the oracle's."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(2512)
+    names = ["g", "ga", "wr", "gr", "gi", "mix"]
+    for case in range(16):
+        rows = int(rng.choice([3, 17, 40, 64, 65, 100, 130, 250, 380, 511]))
+        cols = int(rng.integers(4, 48 if rows <= 100 else 20))
+        p = float(rng.uniform(0.08, 0.45 if rows <= 100 else 0.3))
+        A = workloads.random_system(int(rng.integers(1 << 30)), rows, cols, p)
+        weights = {n: int(w) for n, w in zip(names, rng.integers(0, 4, len(names))) if w}
+        weights = weights or {"gi": 1}
+        kw = dict(seed=int(rng.integers(1 << 62)), n_proc=int(rng.integers(1, 97)), weights=weights,
+                  mix_weights=tuple(int(x) for x in rng.integers(1, 9, 4)), proc0_greedy=bool(rng.integers(2)),
+                  gr_p_q16=int(rng.integers(0, 65537)),
+                  step_cap=int(rng.choice([0, 0, 3, 11])) if rows <= 100 else int(rng.choice([3, 11, 30])))
+        if rng.integers(2):
+            kw.update(share_every=int(rng.integers(1, 9)), share_src_pm=int(rng.integers(1, 300)),
+                      share_dst_pm=int(rng.integers(0, 1001)), share_max_rounds=int(rng.integers(1, 20)))
+        path = int(rng.choice([cse.CSE_COUNT_POPCOUNT, cse.CSE_COUNT_MFMA]))
+        ref = compare(oracle, [A], kw, "random")[0]
+        sid = cse.cse_system_load(ctx, A)
+        lay = int(rng.integers(0, 4))
+        try:
+            cse.cse_scheme_layout(ctx, sid, 0, lay)
+        except cse.CseError as e:
+            assert "CSE_ENOMEM" in str(e)
+            lay = cse.cse_scheme_layout(ctx, sid, 0)
+        say(f"[gpu] random case {case}: {rows}x{cols} p={p:.2f} n_proc={kw['n_proc']} layout {lay} path {path}")
+        job, got = run_loaded(gpu, sid, dict(kw, count_path=path))
+        cse.cse_job_release(ctx, job)
+        cse.cse_scheme_free(ctx, sid)
+        assert_same(got, ref, f"random case {case} ({rows}x{cols}, layout {lay})")
