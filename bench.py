@@ -238,6 +238,12 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
     sid = cse.cse_scheme_load(ctx, *sc.systems)
     info = cse.cse_scheme_info(ctx, sid)
     cfg = cse.cse_run_cfg(**rs.as_kwargs(), count_path=COUNT_PATHS[args.count_path])
+    tuning = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        layouts = cse.cse_autotune(ctx, sid, cfg, stream)
+        tuning = {"seconds": time.perf_counter() - t0, "layouts": layouts}
+        log(f"[bench] autotune: layouts {layouts} in {tuning['seconds']:.1f} s")
     job = cse.cse_launch(ctx, sid, cfg, stream)
     cse.cse_wait(ctx, job)
     gpu_s = timed_relaunch(cse, ctx, job, stream, torch, args.steps, args.warmup)
@@ -252,7 +258,8 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
         ms_per_step=gpu_s / args.steps * 1e3,
         config={"workload": "plain-6x6x6-r160: U,V 160x36, W^T 36x160, p=0.15, row nnz in [1,12]; 16384 "
                             "processes, paper weights, proc0 = g; sharing every 32 steps, 1% -> 10%",
-                "n_proc": rs.n_proc, "substitutions_per_step": subs, "count_path": args.count_path},
+                "n_proc": rs.n_proc, "substitutions_per_step": subs, "count_path": args.count_path,
+                "autotune": tuning},
         time_to_best_ms={"U": ttb[0][1] * 1e3, "V": ttb[1][1] * 1e3, "Wt": ttb[2][1] * 1e3,
                          "scheme": max(t for _, t in ttb) * 1e3},
         best_additions={"U": ttb[0][0], "V": ttb[1][0], "Wt": ttb[2][0], "scheme": sum(b for b, _ in ttb),
@@ -343,7 +350,8 @@ def main():
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
-    ap.add_argument("--autotune", action="store_true", help="batch: pick component layouts with cse_autotune first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch / 6x6x6: pick component layouts with cse_autotune first")
     ap.add_argument("--count-path", default="auto", choices=list(COUNT_PATHS),
                     help="4x4x4 / 6x6x6: how the input's pair counts are computed (same results)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")

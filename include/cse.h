@@ -127,8 +127,9 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
 
 /* Query (layout < 0) or set the layout (CSE_LAYOUT_* bits) of component
  * `comp`; *current (may be NULL) receives the layout in effect before the
- * call.  Loading picks a layout from the system's size (state in HBM when it
- * exceeds 64 KB of LDS, range form of gi for large candidate sets).
+ * call.  Loading picks a layout from the system's size: the range form of gi
+ * for large candidate sets, and state in HBM with the range form when the
+ * state would leave room in a CU's 160 KB of LDS for fewer than four units.
  * CSE_EBUSY while a job of the scheme exists; CSE_ENOMEM if the state does not
  * fit in LDS for an LDS layout.  Unit results are the same in every layout. */
 int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t layout, int32_t* current);

@@ -34,9 +34,11 @@ namespace {
 constexpr int kMaxRows = 512;          // W <= 8 row words
 constexpr int kMaxVars = 32767;        // 15-bit variable ids
 constexpr int kMaskBudgetWords = 1024; // gi masks: at most 8 KB per unit (64-bit words)
-// Units whose state exceeds this many bytes of LDS keep the bulk of it in
-// HBM (one slot per unit) and only the variable lists in LDS.
-constexpr size_t kLdsUnitBudget = 64 * 1024;
+// LDS of one gfx950 CU.  A unit (one wave) whose state would let fewer than
+// four units share a CU, one per SIMD, keeps the bulk of it in HBM (one slot
+// per unit) and only the variable lists in LDS.
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int kMinUnitsPerCu = 4;
 // Cancellation flags (pinned host memory read by the kernels): jobs alive at once.
 constexpr int kCancelSlots = 1 << 16;
 
@@ -357,7 +359,9 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     const long long want32 = std::max<long long>(2ll * cols * ((c.m0 + 31) / 32), 256);
     const long long words32 = std::min<long long>({full32, want32, 2ll * kMaskBudgetWords});
     c.m_words = (int)std::max<long long>(1, (words32 + 1) / 2);
-    c.gs = bulk_bytes(c) + csek::list_bytes(n_vmax) > kLdsUnitBudget;
+    // Too large for four units per CU: state in HBM, and gi over ranges, which
+    // touches far less of that state per step than building masks does.
+    if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
     *out = c;
     return CSE_OK;
 }
