@@ -38,8 +38,9 @@
 /* Strategy ids (Sec. 3.4.1, 3.4.2, 3.4.3; gp of Sec. 3.5.1 is not built). */
 enum { S_G = 0, S_GA = 1, S_WR = 2, S_GR = 3, S_GI = 4, S_MIX = 5, S_GP = 6, N_STRAT = 7 };
 
-/* Random-stream tags placed in the top nibble of counter word 1. */
-enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4 };
+/* Random-stream tags placed in the top nibble of counter word 1 (REINIT is
+ * drawn by the outer-iteration driver, which composes pool runs). */
+enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4, TAG_REINIT = 5 };
 
 /* ------------------------------------------------------------------------
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
@@ -497,7 +498,7 @@ static int cmp_rank(const void* x, const void* y)
 /* One sharing event (Sec. 3.5.2, periodic variant): rank all units of the
  * pool by (current cost, process); the first ceil(N src_pm / 1000) are the
  * sources.  Each active non-source unit draws one Philox block keyed by
- * (process, SHARE|comp|0|0, round, 0): word 0 makes it a target with
+ * (process, SHARE|comp|iteration|0, round, 0): word 0 makes it a target with
  * probability dst_pm / 1000, word 1 picks its source among the sources in
  * rank order, word 2 picks k uniformly in [1, max(1, floor(3 L / 4))] with L
  * the source's program length.  A target restarts from the first k
@@ -524,7 +525,7 @@ static int share_round(const oc_problem* P, oc_unit* units, int n_units, uint32_
         oc_unit* U = &units[i];
         if (!U->active || is_src[i]) continue;
         uint32_t u[4];
-        draw(cfg->seed, U->proc, oc_domain_word(TAG_SHARE, P->comp, 0, 0), round, 0, u);
+        draw(cfg->seed, U->proc, oc_domain_word(TAG_SHARE, P->comp, cfg->iteration, 0), round, 0, u);
         if (scale_index(u[0], 1000) >= cfg->share_dst_pm) continue;
         const oc_unit* S = &units[order[scale_index(u[1], (uint64_t)n_src)]];
         int L = S->t;

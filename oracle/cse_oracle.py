@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcse_oracle.so")
 
 STRATEGIES = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
 COMPONENTS = ("U", "V", "Wt")
+TAG_REINIT = 5  # random-stream tag of the driver's restart draws
 
 
 class OracleCfg(ctypes.Structure):
@@ -254,3 +255,82 @@ def run_pool(A, cfg, comp=0, procs=None, init_prog=None, init_len=None, init_epo
         raise ValueError(f"oracle run_pool failed with status {rc}")
     out["n_fmax"] = n_fmax
     return out
+
+
+def _scale(u, n):
+    """floor(u n / 2^32): an index in [0, n) from a 32-bit word."""
+    return (int(u) * int(n)) >> 32
+
+
+def run_driver(systems, cfg, reinit_pm=400, patience=10, max_iterations=100, n_threads=1):
+    """The tool's outer iterations (Sec. 3.5.1, 3.5.2), run until the best
+    total addition count has not changed for `patience` consecutive
+    iterations (the convergence rule of Sec. 4) or `max_iterations` ran.
+
+    Iteration i runs every process on every component: run_pool with
+    cfg.iteration = i, so strategy, alpha and beta are drawn afresh and
+    process 0 is greedy only in iteration 0.  Each component keeps its best
+    program so far: a strictly lower cost replaces it; within an iteration
+    the lowest (cost, process) wins.  Before iteration i >= 1 every unit draws
+    Philox(process, REINIT|comp|i|0, 0, 0): with probability reinit_pm / 1000
+    (word 0) it restarts from the first k = 1 + floor(u1 max(1, floor(3 L / 4))
+    / 2^32) substitutions of that best program (word 1; L its length, no copy
+    when L = 0), otherwise from the input system; either way its epoch goes
+    up by one, so its step and coin draws are new.
+
+    Returns a dict: iterations; totals, the best total after each iteration;
+    best[c] = dict(cost, prog (L x 3 int32), iteration, proc); last[c] = the
+    final iteration's run_pool output, with executed and ops summed over all
+    iterations."""
+    if not 1 <= max_iterations <= 1024:
+        raise ValueError("max_iterations must be in 1..1024 (10-bit iteration field)")
+    n = cfg.n_proc
+    key = (cfg.seed & 0xFFFFFFFF, cfg.seed >> 32)
+    best = [None] * len(systems)
+    starts = [None] * len(systems)
+    executed = [np.zeros(n, np.int64) for _ in systems]
+    ops = [np.zeros(n, np.int64) for _ in systems]
+    last = [None] * len(systems)
+    totals = []
+    unchanged = 0
+    it = 0
+    while True:
+        cfg.iteration = it
+        for c, A in enumerate(systems):
+            if starts[c] is None:
+                r = run_pool(A, cfg, comp=c, n_threads=n_threads)
+            else:
+                ip, il, ie = starts[c]
+                r = run_pool(A, cfg, comp=c, init_prog=ip, init_len=il, init_epoch=ie, n_threads=n_threads)
+            executed[c] += r["executed"]
+            ops[c] += r["ops"]
+            u = int(np.lexsort((np.arange(n), r["cost"]))[0])
+            if best[c] is None or int(r["cost"][u]) < best[c]["cost"]:
+                L = int(r["steps"][u])
+                best[c] = dict(cost=int(r["cost"][u]), prog=r["prog"][u, :L].copy(), iteration=it, proc=u)
+            last[c] = r
+        total = sum(b["cost"] for b in best)
+        unchanged = unchanged + 1 if totals and total == totals[-1] else 0
+        totals.append(total)
+        it += 1
+        if unchanged >= patience or it >= max_iterations:
+            break
+        for c in range(len(systems)):
+            r = last[c]
+            cap = r["prog"].shape[1]
+            ip = np.zeros((n, cap, 3), np.int32)
+            il = np.zeros(n, np.int32)
+            ie = (r["epoch"] + 1).astype(np.int32)
+            bp = best[c]["prog"]
+            L = len(bp)
+            for p in range(n):
+                w = philox4x32_10((p, domain_word(TAG_REINIT, c, it, 0), 0, 0), key)
+                if L > 0 and _scale(w[0], 1000) < reinit_pm:
+                    k = 1 + _scale(w[1], max(1, (3 * L) // 4))
+                    ip[p, :k] = bp[:k]
+                    il[p] = k
+            starts[c] = (ip, il, ie)
+    for c in range(len(systems)):
+        last[c] = dict(last[c], executed=executed[c], ops=ops[c])
+    return dict(iterations=it, totals=totals, best=best, last=last)
+
