@@ -163,6 +163,49 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
  * allocation in between; on the same stream the call does not block. */
 int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void* stream);
 
+/* The tool's outer iterations (Sec. 3.5.1, 3.5.2) and its convergence rule
+ * (Sec. 4).  Zero-initialise and set the three fields. */
+typedef struct {
+    uint32_t reinit_pm;       /* processes restarted from the best prefix, per mille (paper: 400) */
+    uint32_t patience;        /* stop once the best total is unchanged this many iterations (paper: 10) */
+    uint32_t max_iterations;  /* at most this many iterations, 1..1024 */
+    uint32_t reserved;        /* must be 0 */
+} cse_driver_cfg;
+
+/* Run a job of `cfg` (cfg->iteration must be 0) for iterations i = 0, 1, ...
+ * Iteration i runs every unit to completion, with cfg's sharing rounds if
+ * any, its strategy, alpha and beta drawn for iteration i (process 0 runs g
+ * in iteration 0 only, when proc0_greedy is set).  After each iteration each
+ * component keeps its best program so far: the lowest (cost, process) of
+ * the iteration replaces it when its cost is strictly lower.  Before
+ * iteration i >= 1 every unit restarts, with its epoch advanced: with
+ * probability reinit_pm / 1000 (Philox word 0 of (process,
+ * REINIT|comp|i|0, 0, 0)) from the first k = 1 + floor(u1 max(1,
+ * floor(3 L / 4)) / 2^32) substitutions of that best program (L its length;
+ * none when L = 0), otherwise from the input.  The run stops when the sum of
+ * the component bests has not changed for `patience` iterations (0: after
+ * the first), or after max_iterations.  Blocking.  *job_id receives the
+ * job (release it with cse_job_release); its unit results are those of the
+ * last iteration, with executed and ops summed over all iterations, and
+ * finish times counted from the start of iteration 0.  *iterations (may be
+ * NULL) receives the number of iterations run.  cse_cancel from another
+ * thread stops the run after the current iteration: CSE_ECANCELED, with
+ * the job and its bests kept.  Errors after the job was created leave
+ * *job_id set. */
+int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, const cse_driver_cfg* dcfg,
+                       void* stream, int32_t* job_id, int32_t* iterations);
+
+/* The best program so far of component `comp` of a driver job: triples
+ * (cap x 3 int32, as in cse_get_program), its length, cost, and the
+ * iteration and process that found it; CSE_ERANGE with *needed set when
+ * cap is too small. */
+int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* triples, int32_t cap,
+                        int32_t* n_fresh, int32_t* cost, int32_t* iteration, int32_t* proc, int32_t* needed);
+
+/* The best total (sum of the component bests) after each iteration of a
+ * driver job: *n receives the count; CSE_ERANGE when cap < *n. */
+int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, int32_t cap, int32_t* n);
+
 /* Non-blocking: *done = 1 when the job's device work has completed, else 0.
  * best_cost (3 entries, may be NULL) receives, once done, the lowest cost
  * over the units of each component (the best of each pool, Sec. 3.5, and

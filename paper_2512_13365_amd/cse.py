@@ -33,7 +33,8 @@ EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error",
            "cse_launch", "cse_launch_batch",
            "cse_relaunch", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results", "cse_get_programs",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
-           "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy")
+           "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
+           "cse_run_driver", "cse_driver_best", "cse_driver_totals")
 CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE = 0, 1, 2
 
 
@@ -59,6 +60,15 @@ class CseRunCfg(ctypes.Structure):
         ("iteration", ctypes.c_uint32),
         ("count_path", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32 * 3),
+    ]
+
+
+class CseDriverCfg(ctypes.Structure):
+    _fields_ = [
+        ("reinit_pm", ctypes.c_uint32),
+        ("patience", ctypes.c_uint32),
+        ("max_iterations", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -130,6 +140,12 @@ def load_library(path: str = LIB_PATH):
     L.cse_server_release.restype = i32
     L.cse_server_destroy.argtypes = [vp]
     L.cse_server_destroy.restype = None
+    L.cse_run_driver.argtypes = [vp, i32, P(CseRunCfg), P(CseDriverCfg), vp, P(i32), P(i32)]
+    L.cse_run_driver.restype = i32
+    L.cse_driver_best.argtypes = [vp, i32, i32, P(i32), i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    L.cse_driver_best.restype = i32
+    L.cse_driver_totals.argtypes = [vp, i32, P(i32), i32, P(i32)]
+    L.cse_driver_totals.restype = i32
     _lib = L
     return L
 
@@ -329,6 +345,50 @@ def cse_job_timing(ctx, job_id):
 
 def cse_job_release(ctx, job_id):
     _check(ctx, load_library().cse_job_release(ctx, job_id))
+
+
+def cse_run_driver(ctx, scheme_id, cfg: CseRunCfg, stream=None, reinit_pm=400, patience=10, max_iterations=100):
+    """Outer iterations until convergence (blocking).  Returns (job, iterations).
+    On an error after the job was created the raised CseError carries
+    job_id (release it) and iterations."""
+    d = CseDriverCfg()
+    d.reinit_pm, d.patience, d.max_iterations = reinit_pm, patience, max_iterations
+    job, its = ctypes.c_int32(-1), ctypes.c_int32(0)
+    rc = load_library().cse_run_driver(ctx, scheme_id, ctypes.byref(cfg), ctypes.byref(d), _stream_ptr(stream),
+                                       ctypes.byref(job), ctypes.byref(its))
+    if rc != 0:
+        err = CseError(rc, load_library().cse_last_error(ctx).decode())
+        err.job_id = job.value if job.value > 0 else None
+        err.iterations = its.value
+        raise err
+    return job.value, its.value
+
+
+def cse_driver_best(ctx, job_id, comp):
+    """Best program so far of a component of a driver job:
+    dict(prog (L x 3 int32), cost, iteration, proc)."""
+    L = load_library()
+    nf, cost, it, proc, need = (ctypes.c_int32() for _ in range(5))
+    rc = L.cse_driver_best(ctx, job_id, comp, None, 0, ctypes.byref(nf), ctypes.byref(cost), ctypes.byref(it),
+                           ctypes.byref(proc), ctypes.byref(need))
+    if rc not in (0, -3):
+        _check(ctx, rc)
+    tri = np.zeros((max(1, need.value), 3), np.int32)
+    _check(ctx, L.cse_driver_best(ctx, job_id, comp, _p(tri, ctypes.c_int32), need.value, ctypes.byref(nf),
+                                  ctypes.byref(cost), ctypes.byref(it), ctypes.byref(proc), ctypes.byref(need)))
+    return dict(prog=tri[:nf.value], cost=cost.value, iteration=it.value, proc=proc.value)
+
+
+def cse_driver_totals(ctx, job_id):
+    """Best total after each iteration of a driver job (list of int)."""
+    L = load_library()
+    n = ctypes.c_int32()
+    rc = L.cse_driver_totals(ctx, job_id, None, 0, ctypes.byref(n))
+    if rc not in (0, -3):
+        _check(ctx, rc)
+    out = np.zeros(max(1, n.value), np.int32)
+    _check(ctx, L.cse_driver_totals(ctx, job_id, _p(out, ctypes.c_int32), n.value, ctypes.byref(n)))
+    return [int(x) for x in out[:n.value]]
 
 
 # Servers report errors through the context they were created on.

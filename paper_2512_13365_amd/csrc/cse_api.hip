@@ -92,6 +92,14 @@ struct JobRec {
     int32_t* d_best = nullptr;           // per-component best cost (cse_poll)
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     size_t bytes = 0;                    // device footprint
+    // Outer iterations (cse_run_driver): each component's best program so far.
+    bool driver = false;
+    bool driver_running = false;
+    uint32_t* d_bestprog = nullptr;          // per component max(1, n_fmax) keys
+    unsigned long long* d_key = nullptr;     // per component argmin key
+    int32_t best_cost[3] = {-1, -1, -1}, best_iter[3] = {0, 0, 0}, best_proc[3] = {0, 0, 0};
+    std::vector<uint32_t> best_keys[3];
+    std::vector<int32_t> totals;             // best total after each iteration
 };
 
 struct LaunchGroup {
@@ -508,9 +516,13 @@ void free_job_device(cse_ctx* ctx, JobRec& J) {
     if (J.d_t0) (void)hipFree(J.d_t0);
     if (J.d_share) (void)hipFree(J.d_share);
     if (J.d_best) (void)hipFree(J.d_best);
+    if (J.d_bestprog) (void)hipFree(J.d_bestprog);
+    if (J.d_key) (void)hipFree(J.d_key);
     J.d_t0 = nullptr;
     J.d_share = nullptr;
     J.d_best = nullptr;
+    J.d_bestprog = nullptr;
+    J.d_key = nullptr;
     if (J.cancel_slot >= 0) ctx->free_slots.push_back(J.cancel_slot);
     J.cancel_slot = -1;
     J.allocated = false;
@@ -705,6 +717,7 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             d.shares = P.shares ? 1u : 0u;
             d.n_fmax = ctx->schemes[J.scheme].comp[P.comp].n_fmax;
             d.first_of_job = P.comp == 0 ? 1u : 0u;
+            d.iteration = J.cfg.iteration;
             pd.push_back(d);
             nmax = std::max(nmax, P.n);
         }
@@ -888,14 +901,23 @@ int round_once(cse_ctx* ctx, BatchRec& B) {
 
 // Enqueue a batch's run on its stream.  Without sharing one launch per group
 // runs every unit to completion asynchronously; with sharing the host runs
-// rounds until no job has an active unit.
-int run_batch(cse_ctx* ctx, BatchRec& B) {
+// rounds until no job has an active unit.  fresh = false continues the units
+// as they are (the driver's later iterations): only the round counters
+// restart.
+int run_batch(cse_ctx* ctx, BatchRec& B, bool fresh = true) {
     hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B.stream, B.d_err, 1, 0);
     for (int jid : B.jobs) {
         JobRec& J = ctx->jobs[jid];
         J.budget = shares(J.cfg) ? (int)J.cfg.share_every : -1;
-        int rc = init_job(ctx, J, B.stream);
-        if (rc) return rc;
+        if (fresh) {
+            int rc = init_job(ctx, J, B.stream);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, B.stream, J.cj[0].st.round, 1, 0);
+            HIP_TRY(ctx, hipGetLastError());
+            J.round = 0;
+            J.done = false;
+        }
     }
     int rc = B.built ? CSE_OK : build_segments(ctx, B);
     if (rc) return rc;
@@ -1224,6 +1246,7 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (B->is_server) return fail(ctx, CSE_EINVAL, "server jobs cannot be relaunched");
+    if (J->driver) return fail(ctx, CSE_EINVAL, "driver jobs cannot be relaunched");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // On the batch's own stream the earlier run is ordered before the new
     // one; elsewhere, and whenever the host drives rounds, wait for it.
@@ -1314,6 +1337,12 @@ int32_t cse_cancel(cse_ctx* ctx, int32_t job_id) {
             J->t_done = now_ns();
         }
         return CSE_OK;  // a running server job stops at the end of the current round
+    }
+    if (__atomic_load_n(&J->driver_running, __ATOMIC_SEQ_CST)) {
+        // The driver stops after the running iteration, whose units stop early.
+        if (J->cancel_slot >= 0) __atomic_store_n(&ctx->h_cancel[J->cancel_slot], 1, __ATOMIC_SEQ_CST);
+        __atomic_store_n(&J->cancelled, true, __ATOMIC_SEQ_CST);
+        return CSE_OK;
     }
     if (B->finished) return CSE_OK;
     hipError_t e = hipEventQuery(B->ev_done);
@@ -1422,6 +1451,157 @@ int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* 
     }
     if (ticks) *ticks = last;
     if (tick_hz) *tick_hz = ctx->tick_hz;
+    return CSE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Offset of component c's best program in a driver job's buffer.
+size_t best_offset(const SchemeRec& sc, int c) {
+    size_t o = 0;
+    for (int i = 0; i < c; ++i) o += (size_t)std::max(1, sc.comp[i].n_fmax);
+    return o;
+}
+
+// After an iteration of a driver job: each component's best unit (lowest
+// cost, then process) replaces the best program so far when its cost is
+// strictly lower.  Returns the best total.
+int driver_update_best(cse_ctx* ctx, JobRec& J, hipStream_t s, int32_t* total) {
+    const SchemeRec& sc = ctx->schemes[J.scheme];
+    const uint32_t n = J.cfg.n_proc;
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)J.d_key, 2 * J.n_comp, -1);
+    for (int c = 0; c < J.n_comp; ++c)
+        hipLaunchKernelGGL(csek::driver_argmin_kernel, dim3((n + 255) / 256), dim3(256), 0, s, J.cj[c].st.cost, n,
+                           J.d_key + c);
+    HIP_TRY(ctx, hipGetLastError());
+    unsigned long long key[3];
+    HIP_TRY(ctx, hipMemcpyAsync(key, J.d_key, sizeof(unsigned long long) * J.n_comp, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int it = (int)J.cfg.iteration;
+    int32_t sum = 0;
+    for (int c = 0; c < J.n_comp; ++c) {
+        const int32_t cost = (int32_t)(key[c] >> 32);
+        const int32_t proc = (int32_t)(key[c] & 0xFFFFFFFFu);
+        if (J.best_cost[c] < 0 || cost < J.best_cost[c]) {
+            const int nf = std::max(1, sc.comp[c].n_fmax);
+            int32_t len = 0;
+            HIP_TRY(ctx, hipMemcpy(&len, J.cj[c].st.t + proc, 4, hipMemcpyDeviceToHost));
+            if (len < 0 || len > sc.comp[c].n_fmax) return fail(ctx, CSE_EHIP, "program length %d out of range", len);
+            uint32_t* dst = J.d_bestprog + best_offset(sc, c);
+            const uint32_t* src = J.cj[c].st.prog + (size_t)proc * nf;
+            J.best_keys[c].assign((size_t)len, 0u);
+            if (len > 0) {
+                HIP_TRY(ctx, hipMemcpy(dst, src, (size_t)len * 4, hipMemcpyDeviceToDevice));
+                HIP_TRY(ctx, hipMemcpy(J.best_keys[c].data(), src, (size_t)len * 4, hipMemcpyDeviceToHost));
+            }
+            J.best_cost[c] = cost;
+            J.best_iter[c] = it;
+            J.best_proc[c] = proc;
+        }
+        sum += J.best_cost[c];
+    }
+    *total = sum;
+    return CSE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, const cse_driver_cfg* dcfg,
+                       void* stream, int32_t* job_id, int32_t* iterations) {
+    if (!ctx || !cfg || !dcfg || !job_id) return CSE_EINVAL;
+    if (dcfg->reinit_pm > 1000 || dcfg->max_iterations < 1 || dcfg->max_iterations > 1024 || dcfg->reserved)
+        return fail(ctx, CSE_EINVAL, "driver configuration out of range");
+    if (cfg->iteration != 0) return fail(ctx, CSE_EINVAL, "the driver starts at iteration 0");
+    if (iterations) *iterations = 0;
+    int32_t jid = -1;
+    int rc = cse_launch(ctx, scheme_id, cfg, stream, &jid);  // iteration 0
+    if (rc) return rc;
+    *job_id = jid;
+    JobRec& J = ctx->jobs[jid];
+    BatchRec& B = ctx->batches[J.batch];
+    const SchemeRec& sc = ctx->schemes[J.scheme];
+    J.driver = true;
+    __atomic_store_n(&J.driver_running, true, __ATOMIC_SEQ_CST);
+    hipError_t e = hipMalloc((void**)&J.d_bestprog, 4 * best_offset(sc, sc.n_comp));
+    if (e == hipSuccess) e = hipMalloc((void**)&J.d_key, sizeof(unsigned long long) * 3);
+    if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipMalloc: %s", hipGetErrorString(e));
+    int it = 0, unchanged = 0;
+    while (rc == CSE_OK) {
+        rc = wait_batch(ctx, B);
+        if (rc) break;
+        int32_t total = 0;
+        rc = driver_update_best(ctx, J, B.stream, &total);
+        if (rc) break;
+        unchanged = (!J.totals.empty() && total == J.totals.back()) ? unchanged + 1 : 0;
+        J.totals.push_back(total);
+        ++it;
+        if (__atomic_load_n(&J.cancelled, __ATOMIC_SEQ_CST)) {
+            rc = fail(ctx, CSE_ECANCELED, "job %d was cancelled", jid);
+            break;
+        }
+        if (unchanged >= (int)dcfg->patience || it >= (int)dcfg->max_iterations) break;
+        // Restart every unit, then run iteration `it` with its own draws.
+        for (int c = 0; c < J.n_comp; ++c)
+            hipLaunchKernelGGL(csek::driver_reinit_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0, B.stream,
+                               J.cj[c].st, J.cfg.n_proc, J.cfg.seed, (uint32_t)c, (uint32_t)it, dcfg->reinit_pm,
+                               J.d_bestprog + best_offset(sc, c), (int)J.best_keys[c].size(),
+                               std::max(1, sc.comp[c].n_fmax));
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            rc = fail(ctx, CSE_EHIP, "driver_reinit_kernel: %s", hipGetErrorString(e));
+            break;
+        }
+        J.cfg.iteration = (uint32_t)it;
+        B.built = false;
+        B.finished = false;
+        rc = run_batch(ctx, B, false);
+        if (rc) break;
+        e = hipEventRecord(B.ev_done, B.stream);
+        if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+    if (!B.finished) (void)hipStreamSynchronize(B.stream);
+    B.finished = true;
+    __atomic_store_n(&J.driver_running, false, __ATOMIC_SEQ_CST);
+    if (iterations) *iterations = it;
+    return rc;
+}
+
+int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* triples, int32_t cap,
+                        int32_t* n_fresh, int32_t* cost, int32_t* iteration, int32_t* proc, int32_t* needed) {
+    if (!ctx) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    int rc = readable(ctx, job_id, &J, comp);
+    if (rc) return rc;
+    if (!J->driver) return fail(ctx, CSE_EINVAL, "job %d did not run the driver", job_id);
+    if (comp < 0) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    if (J->best_cost[comp] < 0) return fail(ctx, CSE_ENOENT, "job %d has no completed iteration", job_id);
+    const std::vector<uint32_t>& k = J->best_keys[comp];
+    const int len = (int)k.size();
+    if (n_fresh) *n_fresh = len;
+    if (cost) *cost = J->best_cost[comp];
+    if (iteration) *iteration = J->best_iter[comp];
+    if (proc) *proc = J->best_proc[comp];
+    if (needed) *needed = len;
+    if (cap < len || (!triples && len > 0)) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, len);
+    for (int i = 0; i < len; ++i) {
+        triples[3 * i + 0] = (int32_t)(k[i] >> 16);
+        triples[3 * i + 1] = (int32_t)((k[i] >> 1) & 0x7FFFu);
+        triples[3 * i + 2] = (k[i] & 1u) ? -1 : 1;
+    }
+    return CSE_OK;
+}
+
+int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, int32_t cap, int32_t* n) {
+    if (!ctx || !n) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    int rc = readable(ctx, job_id, &J, -1);
+    if (rc) return rc;
+    if (!J->driver) return fail(ctx, CSE_EINVAL, "job %d did not run the driver", job_id);
+    *n = (int32_t)J->totals.size();
+    if (cap < *n || (!totals && *n > 0)) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, *n);
+    for (int32_t i = 0; i < *n; ++i) totals[i] = J->totals[(size_t)i];
     return CSE_OK;
 }
 

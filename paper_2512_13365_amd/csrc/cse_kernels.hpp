@@ -46,7 +46,7 @@ namespace csek {
 
 constexpr int kWave = 64;
 enum { S_G = 0, S_GA = 1, S_WR = 2, S_GR = 3, S_GI = 4, S_MIX = 5, S_GP = 6, N_STRAT = 7 };
-enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4 };
+enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4, TAG_REINIT = 5 };
 
 // Device consistency flags (host reports them as an error).
 enum { ERR_CAND_OVERFLOW = 1, ERR_BAD_PICK = 2, ERR_COUNT_MISMATCH = 4, ERR_NEW_OVERFLOW = 8 };

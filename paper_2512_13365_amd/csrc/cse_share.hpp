@@ -46,6 +46,7 @@ struct PoolDev {
     uint32_t n, n_src, comp, dst_pm, max_rounds, shares;
     int32_t n_fmax;
     uint32_t first_of_job;  // advances the job's round counter
+    uint32_t iteration;     // the job's outer iteration (keys the draws)
 };
 
 // Active units per pool (counts[p] starts at 0).
@@ -86,7 +87,7 @@ __global__ void pools_target_kernel(const PoolDev* __restrict__ pools) {
     if (round >= P.max_rounds) return;
     const UnitState& S = P.S;
     if (!S.active[u] || P.sc.is_src[u]) return;
-    const U4 r = philox10(u, domain(TAG_SHARE, P.comp, 0, 0), round, 0u, (uint32_t)P.seed,
+    const U4 r = philox10(u, domain(TAG_SHARE, P.comp, P.iteration, 0), round, 0u, (uint32_t)P.seed,
                           (uint32_t)(P.seed >> 32));
     if (scale_u32(r.x, 1000u) >= P.dst_pm) return;
     const int src = P.sc.src_list[scale_u32(r.y, P.n_src)];
@@ -102,6 +103,42 @@ __global__ void pools_target_kernel(const PoolDev* __restrict__ pools) {
     S.t[u] = k;
     S.epoch[u] += 1;
     S.k0[u] = k;
+}
+
+// Outer iterations (Sec. 3.5.1, 3.5.2).  *key becomes the minimum over the
+// units of cost << 32 | process: the pool's best unit, ties to the lowest
+// process (*key starts at all ones).
+__global__ void driver_argmin_kernel(const int32_t* __restrict__ cost, uint32_t n, unsigned long long* key) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long k = u < n ? ((unsigned long long)(uint32_t)cost[u] << 32) | u : ~0ull;
+    const unsigned long long m = ~wave_max_u64(~k);
+    if ((threadIdx.x & 63) == 0) atomicMin(key, m);
+}
+
+// Restart of every unit before iteration `iteration` >= 1: Philox block
+// (process, REINIT|comp|iteration|0, 0, 0); with probability reinit_pm/1000
+// (word 0) the unit starts from the first k = 1 + floor(u1 max(1, floor(3 L
+// / 4)) / 2^32) substitutions of the component's best program (word 1; L its
+// length, L = 0: no copy), otherwise from the input.  Its epoch advances, so
+// its step and coin draws are new; the step kernel replays the prefix.
+__global__ void driver_reinit_kernel(UnitState S, uint32_t n, uint64_t seed, uint32_t comp, uint32_t iteration,
+                                     uint32_t reinit_pm, const uint32_t* __restrict__ best, int L, int stride) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const U4 r = philox10(u, domain(TAG_REINIT, comp, iteration, 0), 0u, 0u, (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+    int k = 0;
+    if (L > 0 && scale_u32(r.x, 1000u) < reinit_pm) {
+        int kmax = (3 * L) / 4;
+        if (kmax < 1) kmax = 1;
+        k = 1 + (int)scale_u32(r.y, (uint32_t)kmax);
+        uint32_t* to = S.prog + (size_t)u * stride;
+        for (int i = 0; i < k; ++i) to[i] = best[i];
+    }
+    S.t[u] = k;
+    S.k0[u] = k;
+    S.epoch[u] += 1;
+    S.active[u] = 1;
 }
 
 // End of a round: every job's round counter advances once.

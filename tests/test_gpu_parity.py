@@ -532,3 +532,102 @@ def test_randomized_configurations(gpu, oracle):
         cse.cse_job_release(ctx, job)
         cse.cse_scheme_free(ctx, sid)
         assert_same(got, ref, f"random case {case} ({rows}x{cols}, layout {lay})")
+
+
+def run_driver_gpu(gpu, systems, kw, layouts=None, **dkw):
+    cse, ctx, torch = gpu
+    sid = cse.cse_scheme_load(ctx, *systems) if len(systems) == 3 else cse.cse_system_load(ctx, systems[0])
+    info = cse.cse_scheme_info(ctx, sid)
+    for c, lay in enumerate(layouts or []):
+        cse.cse_scheme_layout(ctx, sid, c, lay)
+    job, its = cse.cse_run_driver(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream(), **dkw)
+    out = dict(iterations=its, totals=cse.cse_driver_totals(ctx, job),
+               best=[cse.cse_driver_best(ctx, job, c) for c in range(len(systems))], last=[])
+    for c in range(len(systems)):
+        r = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+        r["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+        out["last"].append(r)
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    return out
+
+
+def check_driver(gpu, oracle, systems, kw, label, layouts=None, **dkw):
+    say(f"[gpu] driver {label}: shapes {[A.shape for A in systems]} n_proc {kw['n_proc']} {dkw}")
+    got = run_driver_gpu(gpu, systems, kw, layouts, **dkw)
+    ref = oracle.run_driver(systems, oracle.make_cfg(**kw), n_threads=THREADS, **dkw)
+    assert got["iterations"] == ref["iterations"], label
+    assert got["totals"] == ref["totals"], label
+    for c in range(len(systems)):
+        g, r = got["best"][c], ref["best"][c]
+        assert (g["cost"], g["iteration"], g["proc"]) == (r["cost"], r["iteration"], r["proc"]), f"{label} comp {c}"
+        assert np.array_equal(g["prog"], r["prog"]), f"{label} comp {c}: best programs differ"
+        check_program(systems[c], g["prog"], g["cost"])
+        assert_same(got["last"][c], ref["last"][c], f"{label} comp {c} last iteration")
+    return got
+
+
+def test_driver_converges_like_oracle(gpu, oracle):
+    """Outer iterations (Sec. 3.5.1-3.5.2, Sec. 4 rule): improvements after
+    the first iteration, restarts from best prefixes, the same stop."""
+    S = [workloads.random_system(61 + i, 49, 16, 0.3, 1, 8) for i in range(3)]
+    kw = dict(seed=3, n_proc=16, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True)
+    got = check_driver(gpu, oracle, S, kw, "49x16 x3", patience=3, max_iterations=40)
+    assert got["iterations"] > 4 and got["totals"][-1] < got["totals"][0]
+
+
+def test_driver_with_sharing_rounds_and_layouts(gpu, oracle):
+    """Sharing rounds inside every iteration (their draws keyed by the
+    iteration), in LDS and in HBM slots with the range form of gi."""
+    wl = workloads.plain_4x4x4()
+    S = wl.schemes[0].systems
+    kw = dict(seed=7, n_proc=64, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True,
+              share_every=4, share_src_pm=50, share_dst_pm=300, share_max_rounds=64)
+    check_driver(gpu, oracle, S, kw, "4x4x4 sharing", patience=2, max_iterations=5)
+    check_driver(gpu, oracle, S, kw, "4x4x4 sharing hbm+range", layouts=[3, 1, 2], patience=2, max_iterations=5)
+
+
+def test_driver_tiny_and_edge_settings(gpu, oracle):
+    """gi only on the tiny system; every process restarts from a prefix;
+    no restarts; a single iteration."""
+    wl = workloads.tiny_2x2x2()
+    S = wl.schemes[0].systems
+    kw = wl.runs[0].as_kwargs()
+    check_driver(gpu, oracle, S, kw, "tiny", patience=2, max_iterations=10)
+    check_driver(gpu, oracle, S, dict(kw, n_proc=32), "tiny all restart", reinit_pm=1000, patience=1,
+                 max_iterations=4)
+    A = workloads.random_system(77, 40, 14, 0.3, 1, 8)
+    kw2 = dict(seed=5, n_proc=48, weights=dict(ALL_W), proc0_greedy=True)
+    check_driver(gpu, oracle, [A], kw2, "no restarts", reinit_pm=0, patience=100, max_iterations=3)
+    got = check_driver(gpu, oracle, [A], kw2, "one iteration", patience=0, max_iterations=10)
+    assert got["iterations"] == 1
+
+
+def test_driver_rejects_bad_use(gpu):
+    cse, ctx, torch = gpu
+    A = workloads.random_system(78, 20, 8, 0.3, 1, 6)
+    sid = cse.cse_system_load(ctx, A)
+    st = torch.cuda.current_stream()
+    cfg = cse.cse_run_cfg(n_proc=8, weights={"gi": 1})
+    for bad in (dict(max_iterations=0), dict(max_iterations=1025), dict(reinit_pm=1001)):
+        with pytest.raises(cse.CseError) as e:
+            cse.cse_run_driver(ctx, sid, cfg, st, **bad)
+        assert e.value.status == -1 and e.value.job_id is None
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_run_driver(ctx, sid, cse.cse_run_cfg(n_proc=8, weights={"gi": 1}, iteration=1), st)
+    assert e.value.status == -1
+    job = cse.cse_launch(ctx, sid, cfg, st)
+    cse.cse_wait(ctx, job)
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_driver_best(ctx, job, 0)
+    assert e.value.status == -1
+    cse.cse_job_release(ctx, job)
+    job, its = cse.cse_run_driver(ctx, sid, cfg, st, patience=1, max_iterations=3)
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_relaunch(ctx, job)
+    assert e.value.status == -1
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_driver_best(ctx, job, 1)
+    assert e.value.status == -1
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
