@@ -266,6 +266,42 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
                         "naive": sum(i[3] for i in info)})
 
 
+def run_driver(args, cse, workloads, torch, ctx, stream):
+    """The tool's outer iterations on the 4x4x4 systems until the best total
+    is unchanged for `patience` iterations (Sec. 3.5.1-3.5.2, Sec. 4)."""
+    wl = workloads.plain_4x4x4()
+    sc = wl.schemes[0]
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    info = cse.cse_scheme_info(ctx, sid)
+    cfg = cse.cse_run_cfg(seed=0, n_proc=4096, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job, its = cse.cse_run_driver(ctx, sid, cfg, stream, reinit_pm=400, patience=args.patience,
+                                  max_iterations=100)
+    wall = time.perf_counter() - t0
+    totals, ns = cse.cse_driver_totals(ctx, job, elapsed=True)
+    best = [cse.cse_driver_best(ctx, job, c) for c in range(3)]
+    res = job_results(cse, ctx, job, 4096)
+    subs = sum(int(r["executed"].sum()) for r in res)
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    first_best = totals.index(totals[-1])
+    log(f"[bench] driver: {its} iterations in {wall:.2f} s, totals {totals}")
+    return base_line(
+        args, value=subs / wall, unit="substitution steps/s", ms_per_step=None,
+        config={"workload": "driver-4x4x4-r49: U,V 49x16, W^T 16x49 as plain-4x4x4; 4096 processes, paper "
+                            "weights, proc0 = g; iterations until the best total is unchanged for "
+                            f"{args.patience}, best-prefix restarts of 40%",
+                "n_proc": 4096, "reinit_pm": 400, "patience": args.patience},
+        driver={"iterations": its, "wall_s": wall, "ms_per_iteration": wall / its * 1e3,
+                "substitutions": subs, "totals": totals,
+                "time_to_best_ms": ns[first_best] / 1e6, "best_found_at_iteration": first_best,
+                "first_iteration_total": totals[0], "final_total": totals[-1],
+                "naive": sum(i[3] for i in info),
+                "best_additions": {n: b["cost"] for n, b in zip(("U", "V", "Wt"), best)},
+                "best_iteration": {n: b["iteration"] for n, b in zip(("U", "V", "Wt"), best)}})
+
+
 def run_serve(args, cse, workloads, torch, ctx, stream):
     """Poisson stream of jobs: a continuous-batching server vs one plain
     launch per job in arrival order; latency = completion - arrival."""
@@ -345,7 +381,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve"])
+    ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve", "driver"])
+    ap.add_argument("--patience", type=int, default=10, help="driver: iterations without improvement to stop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
@@ -388,6 +425,8 @@ def main():
                 out["batched_vs_plain"] = batch_vs_plain(cse, workloads, torch, ctx, stream)
         elif args.workload == "6x6x6":
             out = run_6x6x6(args, cse, workloads, torch, ctx, stream)
+        elif args.workload == "driver":
+            out = run_driver(args, cse, workloads, torch, ctx, stream)
         elif args.workload == "batch":
             bp = batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2, autotune=args.autotune)
             out = base_line(args, value=bp["batched"]["steps_per_s"], unit="substitution steps/s",

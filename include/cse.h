@@ -202,9 +202,13 @@ int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, 
 int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* triples, int32_t cap,
                         int32_t* n_fresh, int32_t* cost, int32_t* iteration, int32_t* proc, int32_t* needed);
 
-/* The best total (sum of the component bests) after each iteration of a
- * driver job: *n receives the count; CSE_ERANGE when cap < *n. */
-int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, int32_t cap, int32_t* n);
+/* Per iteration of a driver job: the best total (sum of the component
+ * bests) after it, and the host time in ns from the start of
+ * cse_run_driver to its end.  *n receives the iteration count; totals and
+ * elapsed_ns (either may be NULL; both NULL only counts) receive *n
+ * entries; CSE_ERANGE when cap < *n. */
+int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, uint64_t* elapsed_ns, int32_t cap,
+                          int32_t* n);
 
 /* Non-blocking: *done = 1 when the job's device work has completed, else 0.
  * best_cost (3 entries, may be NULL) receives, once done, the lowest cost

@@ -144,7 +144,7 @@ def load_library(path: str = LIB_PATH):
     L.cse_run_driver.restype = i32
     L.cse_driver_best.argtypes = [vp, i32, i32, P(i32), i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
     L.cse_driver_best.restype = i32
-    L.cse_driver_totals.argtypes = [vp, i32, P(i32), i32, P(i32)]
+    L.cse_driver_totals.argtypes = [vp, i32, P(i32), P(ctypes.c_uint64), i32, P(i32)]
     L.cse_driver_totals.restype = i32
     _lib = L
     return L
@@ -379,16 +379,18 @@ def cse_driver_best(ctx, job_id, comp):
     return dict(prog=tri[:nf.value], cost=cost.value, iteration=it.value, proc=proc.value)
 
 
-def cse_driver_totals(ctx, job_id):
-    """Best total after each iteration of a driver job (list of int)."""
+def cse_driver_totals(ctx, job_id, elapsed=False):
+    """Best total after each iteration of a driver job (list of int); with
+    elapsed=True also the host ns from the driver start to each iteration's end."""
     L = load_library()
     n = ctypes.c_int32()
-    rc = L.cse_driver_totals(ctx, job_id, None, 0, ctypes.byref(n))
-    if rc not in (0, -3):
-        _check(ctx, rc)
+    _check(ctx, L.cse_driver_totals(ctx, job_id, None, None, 0, ctypes.byref(n)))
     out = np.zeros(max(1, n.value), np.int32)
-    _check(ctx, L.cse_driver_totals(ctx, job_id, _p(out, ctypes.c_int32), n.value, ctypes.byref(n)))
-    return [int(x) for x in out[:n.value]]
+    ns = np.zeros(max(1, n.value), np.uint64)
+    _check(ctx, L.cse_driver_totals(ctx, job_id, _p(out, ctypes.c_int32), _p(ns, ctypes.c_uint64), n.value,
+                                    ctypes.byref(n)))
+    totals = [int(x) for x in out[:n.value]]
+    return (totals, [int(x) for x in ns[:n.value]]) if elapsed else totals
 
 
 # Servers report errors through the context they were created on.

@@ -100,6 +100,7 @@ struct JobRec {
     int32_t best_cost[3] = {-1, -1, -1}, best_iter[3] = {0, 0, 0}, best_proc[3] = {0, 0, 0};
     std::vector<uint32_t> best_keys[3];
     std::vector<int32_t> totals;             // best total after each iteration
+    std::vector<uint64_t> iter_ns;           // host time from the driver start to each iteration's end
 };
 
 struct LaunchGroup {
@@ -145,6 +146,7 @@ struct BatchRec {
     // launch, the pool kernels, the count copy) captured as a graph and
     // replayed on an internal stream.
     csek::PoolDev* d_pools = nullptr;
+    std::vector<csek::PoolDev> hpools;  // host copy of the pools' table
     size_t dpools_cap = 0;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_order = nullptr;
@@ -728,8 +730,9 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             B.dpools_cap = std::max(pd.size(), 2 * B.dpools_cap);
             HIP_TRY(ctx, hipMalloc((void**)&B.d_pools, sizeof(csek::PoolDev) * B.dpools_cap));
         }
+        B.hpools = pd;
         if (!pd.empty())
-            HIP_TRY(ctx, hipMemcpyAsync(B.d_pools, pd.data(), sizeof(csek::PoolDev) * pd.size(),
+            HIP_TRY(ctx, hipMemcpyAsync(B.d_pools, B.hpools.data(), sizeof(csek::PoolDev) * pd.size(),
                                         hipMemcpyHostToDevice, B.stream));
         if (B.gexec) HIP_TRY(ctx, hipGraphExecDestroy(B.gexec));
         B.gexec = nullptr;  // the captured round no longer matches
@@ -762,6 +765,22 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
         HIP_TRY(ctx, hipMemcpyAsync(B.d_order, B.order.data(), sizeof(uint32_t) * B.order.size(),
                                     hipMemcpyHostToDevice, B.stream));
     B.built = true;
+    return CSE_OK;
+}
+
+// Move a built single-job batch to outer iteration `it`: only the run
+// arguments' and pools' iteration fields change, in place in device memory,
+// so the dispatch order and a captured round stay valid (the order only
+// affects timing; the draws are keyed by the iteration).
+int set_iteration(cse_ctx* ctx, BatchRec& B, uint32_t it) {
+    for (csek::Segment& sg : B.segs) sg.R.iteration = it;
+    for (csek::PoolDev& pd : B.hpools) pd.iteration = it;
+    if (!B.segs.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(B.d_segs, B.segs.data(), sizeof(csek::Segment) * B.segs.size(),
+                                    hipMemcpyHostToDevice, B.stream));
+    if (B.rounds && !B.hpools.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(B.d_pools, B.hpools.data(), sizeof(csek::PoolDev) * B.hpools.size(),
+                                    hipMemcpyHostToDevice, B.stream));
     return CSE_OK;
 }
 
@@ -1515,6 +1534,7 @@ int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, 
         return fail(ctx, CSE_EINVAL, "driver configuration out of range");
     if (cfg->iteration != 0) return fail(ctx, CSE_EINVAL, "the driver starts at iteration 0");
     if (iterations) *iterations = 0;
+    const uint64_t t_start = now_ns();
     int32_t jid = -1;
     int rc = cse_launch(ctx, scheme_id, cfg, stream, &jid);  // iteration 0
     if (rc) return rc;
@@ -1536,6 +1556,7 @@ int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, 
         if (rc) break;
         unchanged = (!J.totals.empty() && total == J.totals.back()) ? unchanged + 1 : 0;
         J.totals.push_back(total);
+        J.iter_ns.push_back(now_ns() - t_start);
         ++it;
         if (__atomic_load_n(&J.cancelled, __ATOMIC_SEQ_CST)) {
             rc = fail(ctx, CSE_ECANCELED, "job %d was cancelled", jid);
@@ -1554,7 +1575,8 @@ int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, 
             break;
         }
         J.cfg.iteration = (uint32_t)it;
-        B.built = false;
+        rc = B.built ? set_iteration(ctx, B, (uint32_t)it) : CSE_OK;
+        if (rc) break;
         B.finished = false;
         rc = run_batch(ctx, B, false);
         if (rc) break;
@@ -1593,15 +1615,20 @@ int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* tri
     return CSE_OK;
 }
 
-int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, int32_t cap, int32_t* n) {
+int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, uint64_t* elapsed_ns, int32_t cap,
+                          int32_t* n) {
     if (!ctx || !n) return CSE_EINVAL;
     JobRec* J = nullptr;
     int rc = readable(ctx, job_id, &J, -1);
     if (rc) return rc;
     if (!J->driver) return fail(ctx, CSE_EINVAL, "job %d did not run the driver", job_id);
     *n = (int32_t)J->totals.size();
-    if (cap < *n || (!totals && *n > 0)) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, *n);
-    for (int32_t i = 0; i < *n; ++i) totals[i] = J->totals[(size_t)i];
+    if (!totals && !elapsed_ns) return CSE_OK;
+    if (cap < *n) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, *n);
+    for (int32_t i = 0; i < *n; ++i) {
+        if (totals) totals[i] = J->totals[(size_t)i];
+        if (elapsed_ns) elapsed_ns[i] = J->iter_ns[(size_t)i];
+    }
     return CSE_OK;
 }
 
