@@ -267,13 +267,23 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
 
 
 def run_driver(args, cse, workloads, torch, ctx, stream):
-    """The tool's outer iterations on the 4x4x4 systems until the best total
-    is unchanged for `patience` iterations (Sec. 3.5.1-3.5.2, Sec. 4)."""
-    wl = workloads.plain_4x4x4()
+    """The tool's outer iterations on the 4x4x4 (or 6x6x6) systems until the
+    best total is unchanged for `patience` iterations (Sec. 3.5.1-3.5.2,
+    Sec. 4)."""
+    if args.driver_scheme == "6x6x6":
+        wl = workloads.plain_6x6x6()
+        kw = wl.runs[0].as_kwargs()
+        name = ("driver-6x6x6-r160: U,V 160x36, W^T 36x160 as plain-6x6x6; 16384 processes, paper weights, "
+                "proc0 = g, sharing every 32 steps 1% -> 10% inside each iteration")
+    else:
+        wl = workloads.plain_4x4x4()
+        kw = dict(seed=0, n_proc=4096, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+        name = "driver-4x4x4-r49: U,V 49x16, W^T 16x49 as plain-4x4x4; 4096 processes, paper weights, proc0 = g"
+    n_proc = kw["n_proc"]
     sc = wl.schemes[0]
     sid = cse.cse_scheme_load(ctx, *sc.systems)
     info = cse.cse_scheme_info(ctx, sid)
-    cfg = cse.cse_run_cfg(seed=0, n_proc=4096, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+    cfg = cse.cse_run_cfg(**kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     job, its = cse.cse_run_driver(ctx, sid, cfg, stream, reinit_pm=400, patience=args.patience,
@@ -281,7 +291,7 @@ def run_driver(args, cse, workloads, torch, ctx, stream):
     wall = time.perf_counter() - t0
     totals, ns = cse.cse_driver_totals(ctx, job, elapsed=True)
     best = [cse.cse_driver_best(ctx, job, c) for c in range(3)]
-    res = job_results(cse, ctx, job, 4096)
+    res = job_results(cse, ctx, job, n_proc)
     subs = sum(int(r["executed"].sum()) for r in res)
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
@@ -289,10 +299,9 @@ def run_driver(args, cse, workloads, torch, ctx, stream):
     log(f"[bench] driver: {its} iterations in {wall:.2f} s, totals {totals}")
     return base_line(
         args, value=subs / wall, unit="substitution steps/s", ms_per_step=None,
-        config={"workload": "driver-4x4x4-r49: U,V 49x16, W^T 16x49 as plain-4x4x4; 4096 processes, paper "
-                            "weights, proc0 = g; iterations until the best total is unchanged for "
-                            f"{args.patience}, best-prefix restarts of 40%",
-                "n_proc": 4096, "reinit_pm": 400, "patience": args.patience},
+        config={"workload": f"{name}; iterations until the best total is unchanged for {args.patience}, "
+                            "best-prefix restarts of 40%",
+                "n_proc": n_proc, "reinit_pm": 400, "patience": args.patience},
         driver={"iterations": its, "wall_s": wall, "ms_per_iteration": wall / its * 1e3,
                 "substitutions": subs, "totals": totals,
                 "time_to_best_ms": ns[first_best] / 1e6, "best_found_at_iteration": first_best,
@@ -383,6 +392,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve", "driver"])
     ap.add_argument("--patience", type=int, default=10, help="driver: iterations without improvement to stop")
+    ap.add_argument("--driver-scheme", default="4x4x4", choices=["4x4x4", "6x6x6"], help="driver: which systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")

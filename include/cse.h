@@ -188,10 +188,11 @@ typedef struct {
  * job (release it with cse_job_release); its unit results are those of the
  * last iteration, with executed and ops summed over all iterations, and
  * finish times counted from the start of iteration 0.  *iterations (may be
- * NULL) receives the number of iterations run.  cse_cancel from another
- * thread stops the run after the current iteration: CSE_ECANCELED, with
- * the job and its bests kept.  Errors after the job was created leave
- * *job_id set. */
+ * NULL) receives the number of iterations run.  *job_id is written as soon
+ * as the job exists, before iteration 0 completes, so another thread may
+ * read it and call cse_cancel, which stops the run after the current
+ * iteration: CSE_ECANCELED, with the job and its bests kept.  Errors after
+ * the job was created leave *job_id set. */
 int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, const cse_driver_cfg* dcfg,
                        void* stream, int32_t* job_id, int32_t* iterations);
 

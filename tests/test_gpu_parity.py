@@ -631,3 +631,45 @@ def test_driver_rejects_bad_use(gpu):
     assert e.value.status == -1
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
+
+
+def test_driver_cancel_from_another_thread(gpu):
+    """cse_cancel on another thread stops a long driver run after the
+    current iteration; the bests of the completed iterations stay readable."""
+    import ctypes
+    import threading
+    import time
+    cse, ctx, torch = gpu
+    wl = workloads.plain_4x4x4()
+    sid = cse.cse_scheme_load(ctx, *wl.schemes[0].systems)
+    cfg = cse.cse_run_cfg(seed=1, n_proc=4096, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+    d = cse.CseDriverCfg()
+    d.reinit_pm, d.patience, d.max_iterations = 400, 1024, 1024
+    job, its, rc = ctypes.c_int32(-1), ctypes.c_int32(0), []
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = cse.load_library()
+
+    def run():
+        rc.append(L.cse_run_driver(ctx, sid, ctypes.byref(cfg), ctypes.byref(d), stream, ctypes.byref(job),
+                                   ctypes.byref(its)))
+
+    th = threading.Thread(target=run)
+    th.start()
+    t0 = time.time()
+    while job.value <= 0 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    assert job.value > 0
+    time.sleep(0.1)
+    cse.cse_cancel(ctx, job.value)
+    th.join(60)
+    assert not th.is_alive()
+    assert rc == [-7], rc
+    assert 1 <= its.value < 1024
+    totals = cse.cse_driver_totals(ctx, job.value)
+    assert len(totals) == its.value
+    best = [cse.cse_driver_best(ctx, job.value, c) for c in range(3)]
+    assert sum(b["cost"] for b in best) == totals[-1]
+    for c, A in enumerate(wl.schemes[0].systems):
+        check_program(A, best[c]["prog"], best[c]["cost"])
+    cse.cse_job_release(ctx, job.value)
+    cse.cse_scheme_free(ctx, sid)
