@@ -6,9 +6,8 @@
 // a source it picks, k uniform in [1, max(1, floor(3 L / 4))].
 //
 // Ranking needs no sort: a unit's rank is the number of units whose
-// (cost, process) key is smaller, and a unit can stop counting as soon as it
-// has seen n_src smaller keys, since it is then not a source.  Only the few
-// best units scan the whole pool.
+// (cost, process) key is smaller, and a unit is not a source once it has
+// seen n_src smaller keys.  Keys are compared tile by tile from LDS.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -59,18 +58,30 @@ __global__ void pools_count_kernel(const PoolDev* __restrict__ pools, int32_t* c
 }
 
 // Sources of every sharing pool below its round limit: rank by (cost,
-// process), mark the first n_src and list them in rank order.
-__global__ void pools_rank_kernel(const PoolDev* __restrict__ pools) {
+// process), mark the first n_src and list them in rank order.  A block of
+// kRankBlock units counts the smaller keys tile by tile, each tile of keys
+// staged in LDS, and stops once every one of its units has seen n_src of
+// them (such a unit is not a source; the others end with exact ranks).
+constexpr int kRankBlock = 256;
+__global__ __launch_bounds__(kRankBlock) void pools_rank_kernel(const PoolDev* __restrict__ pools) {
+    __shared__ unsigned long long tile[kRankBlock];
     const PoolDev& P = pools[blockIdx.y];
-    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!P.shares || (uint32_t)*P.S.round >= P.max_rounds || u >= P.n) return;
+    if (!P.shares || (uint32_t)*P.S.round >= P.max_rounds || blockIdx.x * kRankBlock >= P.n) return;
+    const uint32_t u = blockIdx.x * kRankBlock + threadIdx.x;
     const int32_t* cost = P.S.cost;
-    const unsigned long long mine = ((unsigned long long)(uint32_t)cost[u] << 32) | u;
+    const bool in = u < P.n;
+    const unsigned long long mine = in ? ((unsigned long long)(uint32_t)cost[u] << 32) | u : ~0ull;
     uint32_t below = 0;
-    for (uint32_t v = 0; v < P.n && below < P.n_src; ++v) {
-        const unsigned long long kv = ((unsigned long long)(uint32_t)cost[v] << 32) | v;
-        below += kv < mine ? 1u : 0u;
+    for (uint32_t t0 = 0; t0 < P.n; t0 += kRankBlock) {
+        const uint32_t v = t0 + threadIdx.x;
+        tile[threadIdx.x] = v < P.n ? ((unsigned long long)(uint32_t)cost[v] << 32) | v : ~0ull;
+        __syncthreads();
+        const int cnt = P.n - t0 < (uint32_t)kRankBlock ? (int)(P.n - t0) : kRankBlock;
+        for (int i = 0; i < cnt; ++i) below += tile[i] < mine ? 1u : 0u;
+        // Also the barrier before the next tile overwrites this one.
+        if (__syncthreads_and(!in || below >= P.n_src)) break;
     }
+    if (!in) return;
     const bool src = below < P.n_src;
     P.sc.is_src[u] = src ? 1 : 0;
     if (src) P.sc.src_list[below] = (int32_t)u;
