@@ -467,9 +467,13 @@ csek::CompArgs comp_args(const DevComp& c, int comp, bool gram) {
     return C;
 }
 
+// An HBM slot holds a unit's bulk state and, in its last 16 bytes, the
+// record of which state that is (256 bytes keep slots aligned).
+size_t slot_bytes(const DevComp& c) { return bulk_bytes(c) + 256; }
+
 size_t comp_job_bytes(const DevComp& c, uint32_t n) {
     const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
-    const size_t gs = c.gs ? (size_t)n * bulk_bytes(c) : 0;
+    const size_t gs = c.gs ? (size_t)n * slot_bytes(c) : 0;
     return gs + prog + 7 * (size_t)n * 4 + 2 * (size_t)n * 8 + 64 * 11;
 }
 
@@ -487,7 +491,7 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     const size_t prog = (size_t)n * std::max(1, c.n_fmax) * 4;
     const size_t i32 = (size_t)n * 4;
     const size_t u64 = (size_t)n * 8;
-    const size_t gs = c.gs ? (size_t)n * bulk_bytes(c) : 0;
+    const size_t gs = c.gs ? (size_t)n * slot_bytes(c) : 0;
     const size_t total = comp_job_bytes(c, n);
     char* base = nullptr;
     HIP_TRY(ctx, hipMalloc((void**)&base, total));
@@ -496,7 +500,7 @@ int alloc_comp_job(cse_ctx* ctx, const DevComp& c, uint32_t n, CompJob* cj) {
     auto take = [&](size_t bytes) { char* p = base; base += (bytes + 63) & ~size_t(63); return p; };
     csek::UnitState& S = cj->st;
     S.gs_base = c.gs ? take(gs) : nullptr;
-    S.gs_stride = c.gs ? bulk_bytes(c) : 0;
+    S.gs_stride = c.gs ? slot_bytes(c) : 0;
     S.ops = (unsigned long long*)take(u64);
     S.finish = (unsigned long long*)take(u64);
     S.prog = (uint32_t*)take(prog);

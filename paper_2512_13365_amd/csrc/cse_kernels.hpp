@@ -1153,12 +1153,14 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     // The second candidate ordering is kept only where gi walks ranges.
     const bool need_tl = ADJ && (strat == S_GI || strat == S_MIX);
 
-    for (int i = l; i < n_vmax * W; i += kWave) {
-        const bool in = i < C.n_x * W;
-        colP[i] = in ? C.P0[i] : 0ull;
-        colN[i] = in ? C.N0[i] : 0ull;
+    if constexpr (!GS) {
+        for (int i = l; i < n_vmax * W; i += kWave) {
+            const bool in = i < C.n_x * W;
+            colP[i] = in ? C.P0[i] : 0ull;
+            colN[i] = in ? C.N0[i] : 0ull;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     int t = S.t[proc];
     const int epoch = S.epoch[proc];
@@ -1167,11 +1169,46 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     int cost = C.naive0;
     uint32_t* prog = S.prog + (size_t)proc * C.prog_stride;
 
+    // A unit whose state lives in an HBM slot resumes from it when the slot
+    // holds the state after its current program (same length and epoch: no
+    // restart since its last launch); the state is the one a replay would
+    // rebuild.  Otherwise the unit replays its program (a shared prefix or an
+    // earlier round) from the input.  The last 16 bytes of a slot record
+    // (t, epoch, m, current candidate buffer) of the state it holds; t = -1:
+    // none.
+    bool resumed = false;
+    int4 rs = make_int4(-1, 0, 0, 0);
+    int4* rec = nullptr;
+    if constexpr (GS) {
+        rec = (int4*)(bulk + S.gs_stride - 16);
+        rs = *rec;
+        resumed = t > 0 && rs.x == t && rs.y == epoch;
+        if (resumed) {
+            cost = S.cost[proc];
+            if constexpr (ADJ) {
+                if (rs.w) {
+                    uint64_t* sw = cand;
+                    cand = cand2;
+                    cand2 = sw;
+                }
+            }
+        } else {
+            for (int i = l; i < n_vmax * W; i += kWave) {
+                const bool in = i < C.n_x * W;
+                colP[i] = in ? C.P0[i] : 0ull;
+                colN[i] = in ? C.N0[i] : 0ull;
+            }
+            __syncthreads();
+        }
+    }
+
     // Replay the unit's program (a shared prefix or an earlier round).
-    for (int i = 0; i < t; ++i) {
-        int dead;
-        const int c = substitute<W>(colP, colN, prog[i], C.n_x + i, &dead);
-        cost -= c - 1;
+    if (!resumed) {
+        for (int i = 0; i < t; ++i) {
+            int dead;
+            const int c = substitute<W>(colP, colN, prog[i], C.n_x + i, &dead);
+            cost -= c - 1;
+        }
     }
 
     // Live list: variables with a nonzero column, ascending.
@@ -1198,7 +1235,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
 
     int err_flags = 0;
     int m;
-    if (t == 0) {
+    if (resumed) {
+        m = rs.z;
+    } else if (t == 0) {
         // Every unit of a component starts from the same input: its
         // candidates (and second ordering) were counted once, on load.
         m = C.m0;
@@ -1285,6 +1324,10 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     if (any_err && l == 0) atomicOr(err, (int)any_err);
 
     if (l == 0) {
+        if constexpr (GS) {
+            const int cur = (ADJ && cand != (uint64_t*)(bulk + BL.cand)) ? 1 : 0;
+            *rec = make_int4(t, epoch, m, cur);
+        }
         S.t[proc] = t;
         S.cost[proc] = cost;
         S.executed[proc] = executed;
@@ -1318,6 +1361,7 @@ __global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp) {
     S.strat[i] = -1;
     S.ops[i] = 0;
     S.finish[i] = 0;
+    if (S.gs_base) *(int4*)(S.gs_base + (size_t)i * S.gs_stride + S.gs_stride - 16) = make_int4(-1, 0, 0, 0);
 }
 
 }  // namespace csek
