@@ -673,3 +673,24 @@ def test_driver_cancel_from_another_thread(gpu):
         check_program(A, best[c]["prog"], best[c]["cost"])
     cse.cse_job_release(ctx, job.value)
     cse.cse_scheme_free(ctx, sid)
+
+
+@pytest.mark.parametrize("rows,cols,p,every", [(60, 18, 0.3, 1), (160, 36, 0.15, 3), (42, 120, 0.2, 6)])
+def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
+    """Units with state in HBM slots resume from the slot between sharing
+    rounds unless they were restarted; with rounds every few steps and many
+    targets, resumed and replayed units alternate, in both HBM layouts."""
+    cse, ctx, torch = gpu
+    A = workloads.random_system(rows * 7 + cols, rows, cols, p)
+    kw = dict(seed=rows + every, n_proc=48, weights=dict(ALL_W), proc0_greedy=True, share_every=every,
+              share_src_pm=60, share_dst_pm=400, share_max_rounds=1000)
+    ref = compare(oracle, [A], kw, "resume")[0]
+    assert ref["epoch"].max() > 1
+    for lay in (cse.CSE_LAYOUT_HBM, cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE):
+        sid = cse.cse_system_load(ctx, A)
+        cse.cse_scheme_layout(ctx, sid, 0, lay)
+        say(f"[gpu] resume: system {rows}x{cols} every {every} layout {lay}")
+        job, got = run_loaded(gpu, sid, kw)
+        cse.cse_job_release(ctx, job)
+        cse.cse_scheme_free(ctx, sid)
+        assert_same(got, ref, f"resume {rows}x{cols} layout {lay}")
