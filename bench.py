@@ -250,12 +250,20 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
     res = job_results(cse, ctx, job, rs.n_proc)
     _, tick_hz = cse.cse_job_timing(ctx, job)
     subs = sum(int(r["executed"].sum()) for r in res)
+    ops = sum(int(r["ops"].sum()) for r in res)
     ttb = time_to_best(res, tick_hz)
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
+    per_job = gpu_s / args.steps
+    achieved = ops / per_job
     return base_line(
         args, value=subs * args.steps / gpu_s, unit="substitution steps/s",
-        ms_per_step=gpu_s / args.steps * 1e3,
+        ms_per_step=per_job * 1e3,
+        roofline={"kernel": "step_kernel<3, true, true> (U, V) and step_kernel<1, false, false> (W^T); "
+                            "achieved over the whole job, sharing rounds included",
+                  "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,
+                  "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS, "traffic": None,
+                  "algorithmic_ops_per_job": ops, "job_ms": per_job * 1e3},
         config={"workload": "plain-6x6x6-r160: U,V 160x36, W^T 36x160, p=0.15, row nnz in [1,12]; 16384 "
                             "processes, paper weights, proc0 = g; sharing every 32 steps, 1% -> 10%",
                 "n_proc": rs.n_proc, "substitutions_per_step": subs, "count_path": args.count_path,
