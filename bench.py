@@ -147,7 +147,7 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
         pcie_inclusive={"readback_ms": readback_s * 1e3,
                         "steps_per_s": subs / (per_step + readback_s),
                         "note": "job plus host copy of all unit results and programs"},
-        roofline={"kernel": "step_kernel<1, false, false>", "bound": "alu", "achieved": achieved / 1e12,
+        roofline={"kernel": "step_kernel<1, false, false, false>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
                   "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
                   "algorithmic_ops_per_launch": ops / launches,
@@ -259,7 +259,7 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
     return base_line(
         args, value=subs * args.steps / gpu_s, unit="substitution steps/s",
         ms_per_step=per_job * 1e3,
-        roofline={"kernel": "step_kernel<3, true, true> (U, V) and step_kernel<1, false, false> (W^T); "
+        roofline={"kernel": "step_kernel<3, true, true, false> (U, V) and step_kernel<1, false, false, false> (W^T); "
                             "achieved over the whole job, sharing rounds included",
                   "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,
                   "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS, "traffic": None,

@@ -51,6 +51,7 @@ struct DevComp {
     int n_e = 0, n_x = 0, n_fmax = 0, W = 0, m_cap = 0, naive0 = 0, newc_cap = 0, m_words = 0, m0 = 0;
     bool gs = false;   // bulk state in HBM
     bool adj = false;  // gi over per-variable ranges (large candidate sets)
+    bool tl = false;   // with gs and adj: the range tables in LDS
     int kbits = 1;     // weight bit-planes per ordering
     long long occ0 = 0;
     int8_t* d_A = nullptr;        // the input, rows x cols row-major
@@ -107,6 +108,7 @@ struct LaunchGroup {
     int W = 0;
     bool gs = false;
     bool adj = false;
+    bool tl = false;
     uint32_t n_grid = 0;
     size_t lds = 0;
     int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
@@ -203,6 +205,7 @@ size_t bulk_bytes(const DevComp& c) {
     return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0, c.kbits).bytes;
 }
 size_t lds_bytes(const DevComp& c) {
+    if (c.gs && c.tl) return csek::table_layout(c.n_x + c.n_fmax, c.m_cap, c.kbits).bytes;
     return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
 }
 
@@ -300,10 +303,21 @@ int ensure_gram_lists(cse_ctx* ctx, DevComp& c) {
 // Layout of a component (CSE_LAYOUT_*): bulk state in HBM slots instead of
 // LDS, and gi over per-variable ranges instead of masks.  Results do not
 // depend on it.
-int layout_code(const DevComp& c) { return (c.gs ? CSE_LAYOUT_HBM : 0) | (c.adj ? CSE_LAYOUT_RANGE : 0); }
+// Layouts: LDS or HBM state, masks or ranges, and for HBM state with ranges
+// the range tables in LDS.
+constexpr int kLayoutMax = CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE | CSE_LAYOUT_LDS_TABLES;
+bool layout_valid(int layout) {
+    if (layout < 0 || layout > kLayoutMax) return false;
+    return !(layout & CSE_LAYOUT_LDS_TABLES) || (layout & (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE)) ==
+                                                      (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE);
+}
+int layout_code(const DevComp& c) {
+    return (c.gs ? CSE_LAYOUT_HBM : 0) | (c.adj ? CSE_LAYOUT_RANGE : 0) | (c.tl ? CSE_LAYOUT_LDS_TABLES : 0);
+}
 void set_layout(DevComp& c, int layout) {
     c.gs = (layout & CSE_LAYOUT_HBM) != 0;
     c.adj = (layout & CSE_LAYOUT_RANGE) != 0;
+    c.tl = (layout & CSE_LAYOUT_LDS_TABLES) != 0;
 }
 
 int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
@@ -590,30 +604,34 @@ void free_batch_device(BatchRec& B) {
 
 // Dynamic LDS above 64 KB must be allowed per kernel before launches (and
 // before a launch is captured into a graph).
-template <int W, bool GS, bool ADJ>
+template <int W, bool GS, bool ADJ, bool TL>
 int set_lds_limit_w(cse_ctx* ctx, size_t lds) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS, ADJ>,
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS, ADJ, TL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return CSE_OK;
 }
-template <bool GS, bool ADJ>
+template <bool GS, bool ADJ, bool TL>
 int set_lds_limit_gs(cse_ctx* ctx, int W, size_t lds) {
     switch (W) {
-    case 1: return set_lds_limit_w<1, GS, ADJ>(ctx, lds);
-    case 2: return set_lds_limit_w<2, GS, ADJ>(ctx, lds);
-    case 3: return set_lds_limit_w<3, GS, ADJ>(ctx, lds);
-    case 4: return set_lds_limit_w<4, GS, ADJ>(ctx, lds);
-    case 5: return set_lds_limit_w<5, GS, ADJ>(ctx, lds);
-    case 6: return set_lds_limit_w<6, GS, ADJ>(ctx, lds);
-    case 7: return set_lds_limit_w<7, GS, ADJ>(ctx, lds);
-    case 8: return set_lds_limit_w<8, GS, ADJ>(ctx, lds);
+    case 1: return set_lds_limit_w<1, GS, ADJ, TL>(ctx, lds);
+    case 2: return set_lds_limit_w<2, GS, ADJ, TL>(ctx, lds);
+    case 3: return set_lds_limit_w<3, GS, ADJ, TL>(ctx, lds);
+    case 4: return set_lds_limit_w<4, GS, ADJ, TL>(ctx, lds);
+    case 5: return set_lds_limit_w<5, GS, ADJ, TL>(ctx, lds);
+    case 6: return set_lds_limit_w<6, GS, ADJ, TL>(ctx, lds);
+    case 7: return set_lds_limit_w<7, GS, ADJ, TL>(ctx, lds);
+    case 8: return set_lds_limit_w<8, GS, ADJ, TL>(ctx, lds);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", W);
     }
 }
 int set_lds_limit(cse_ctx* ctx, const LaunchGroup& G) {
     if (G.lds <= 65536) return CSE_OK;
-    if (G.gs) return G.adj ? set_lds_limit_gs<true, true>(ctx, G.W, G.lds) : set_lds_limit_gs<true, false>(ctx, G.W, G.lds);
-    return G.adj ? set_lds_limit_gs<false, true>(ctx, G.W, G.lds) : set_lds_limit_gs<false, false>(ctx, G.W, G.lds);
+    if (G.gs && G.adj)
+        return G.tl ? set_lds_limit_gs<true, true, true>(ctx, G.W, G.lds)
+                    : set_lds_limit_gs<true, true, false>(ctx, G.W, G.lds);
+    if (G.gs) return set_lds_limit_gs<true, false, false>(ctx, G.W, G.lds);
+    return G.adj ? set_lds_limit_gs<false, true, false>(ctx, G.W, G.lds)
+                 : set_lds_limit_gs<false, false, false>(ctx, G.W, G.lds);
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -633,13 +651,15 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
     B.seg_job.clear();
     B.groups.clear();
     B.pools.clear();
-    for (int cls = 0; cls < 32; ++cls) {
-        const int W = 1 + (cls >> 2);
-        const bool gs = cls & 1, adj = (cls >> 1) & 1;
+    // Classes (W, placement, gi form, tables): the kernel is specialised on each.
+    for (int cls = 0; cls < 40; ++cls) {
+        const int W = 1 + cls / 5, k = cls % 5;
+        const bool gs = k == 1 || k >= 3, adj = k >= 2, tl = k == 4;
         LaunchGroup G;
         G.W = W;
         G.gs = gs;
         G.adj = adj;
+        G.tl = tl;
         G.seg_begin = (int)B.segs.size();
         uint32_t unit = 0;
         for (int jid : B.jobs) {
@@ -648,7 +668,7 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             const SchemeRec& sc = ctx->schemes[J.scheme];
             for (int c = 0; c < J.n_comp; ++c) {
                 const DevComp& dc = sc.comp[c];
-                if (dc.W != W || dc.gs != gs || dc.adj != adj) continue;
+                if (dc.W != W || dc.gs != gs || dc.adj != adj || dc.tl != tl) continue;
                 csek::Segment s{};
                 s.C = comp_args(dc, c, J.cfg.count_path == CSE_COUNT_MFMA);
                 s.R = run_args(ctx, J);
@@ -788,29 +808,29 @@ int set_iteration(cse_ctx* ctx, BatchRec& B, uint32_t it) {
     return CSE_OK;
 }
 
-template <int W, bool GS, bool ADJ>
+template <int W, bool GS, bool ADJ, bool TL>
 int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                    int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
                        d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;
 }
 
-template <bool GS, bool ADJ>
+template <bool GS, bool ADJ, bool TL>
 int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                     int* d_err, hipStream_t s) {
     switch (G.W) {
-    case 1: return launch_group_w<1, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 2: return launch_group_w<2, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 3: return launch_group_w<3, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 4: return launch_group_w<4, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 5: return launch_group_w<5, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 6: return launch_group_w<6, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 7: return launch_group_w<7, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
-    case 8: return launch_group_w<8, GS, ADJ>(ctx, G, d_segs, d_order, d_err, s);
+    case 1: return launch_group_w<1, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 2: return launch_group_w<2, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 3: return launch_group_w<3, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 4: return launch_group_w<4, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 5: return launch_group_w<5, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 6: return launch_group_w<6, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 7: return launch_group_w<7, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 8: return launch_group_w<8, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
     }
 }
@@ -818,12 +838,14 @@ int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_s
 int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
     for (const LaunchGroup& G : B.groups) {
         int rc;
-        if (G.gs)
-            rc = G.adj ? launch_group_gs<true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                       : launch_group_gs<true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        if (G.gs && G.adj)
+            rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                      : launch_group_gs<true, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        else if (G.gs)
+            rc = launch_group_gs<true, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         else
-            rc = G.adj ? launch_group_gs<false, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                       : launch_group_gs<false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+            rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                       : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         if (rc) return rc;
     }
     return CSE_OK;
@@ -1170,11 +1192,11 @@ int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t
     DevComp& dc = it->second.comp[comp];
     if (current) *current = layout_code(dc);
     if (layout < 0) return CSE_OK;
-    if (layout > (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE)) return fail(ctx, CSE_EINVAL, "unknown layout %d", layout);
+    if (!layout_valid(layout)) return fail(ctx, CSE_EINVAL, "unknown layout %d", layout);
     if (scheme_busy(ctx, scheme_id)) return fail(ctx, CSE_EBUSY, "scheme %d has jobs; release them first", scheme_id);
     DevComp probe = dc;
     set_layout(probe, layout);
-    if (!probe.gs && lds_bytes(probe) > ctx->lds_max)
+    if ((!probe.gs || probe.tl) && lds_bytes(probe) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "layout %d needs %zu B of LDS per unit (max %zu)", layout, lds_bytes(probe),
                     ctx->lds_max);
     set_layout(dc, layout);
@@ -1202,10 +1224,13 @@ int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, vo
         // The mask form of gi is skipped where the input's masks already
         // exceed their capacity (its steps would take the O(m^2) form).
         const bool masks_fit = (long long)dc.n_x * ((dc.m0 + 31) / 32) <= 2ll * dc.m_words;
+        // Range tables in LDS are not probed: a one-component probe cannot
+        // show what their LDS footprint costs when the components of a job
+        // share the CUs (on 6x6x6 it would pick them and lose 3%).
         for (int lay = 0; lay <= (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE); ++lay) {
             DevComp probe = dc;
             set_layout(probe, lay);
-            if (!probe.gs && lds_bytes(probe) > ctx->lds_max) continue;
+            if ((!probe.gs || probe.tl) && lds_bytes(probe) > ctx->lds_max) continue;
             if (!probe.adj && !masks_fit) continue;
             float ms = 0.f;
             rc = probe_layout(ctx, probe, pc, (hipStream_t)stream, best_ms, &ms);

@@ -232,6 +232,23 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
 // live and vpos: n_vmax int32 each.
 __host__ __device__ inline size_t list_bytes(int n_vmax) { return ((size_t)n_vmax * 8 + 15) & ~size_t(15); }
 
+// Units with state in HBM slots may keep the per-step tables of the range
+// form of gi (ranges, second ordering with weights, weight bit-planes) in
+// LDS after their lists instead of in the slot: offsets in LDS, and bytes
+// of LDS in all.
+struct TableLayout {
+    size_t rng, tp, pl, bytes;
+};
+__host__ __device__ inline TableLayout table_layout(int n_vmax, int m_cap, int kbits) {
+    TableLayout T;
+    size_t o = list_bytes(n_vmax);
+    T.rng = o;  o += (size_t)n_vmax * 16;
+    T.tp = o;   o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
+    T.pl = o;   o += (size_t)2 * kbits * plane_words(m_cap) * 4;
+    T.bytes = (o + 15) & ~size_t(15);
+    return T;
+}
+
 __device__ __forceinline__ int weighted_pick(const uint32_t* w, int n, uint32_t u) {
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += w[i];
@@ -1097,9 +1114,10 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // b runs grid unit order[b].
 // ---------------------------------------------------------------------------
 // W: row words; GS: bulk state in HBM slots; ADJ: gi over per-variable
-// ranges (large candidate sets) instead of masks.  Each combination is its
-// own kernel, so a launch carries only the code its units run.
-template <int W, bool GS, bool ADJ>
+// ranges (large candidate sets) instead of masks; TL (with GS and ADJ): the
+// range tables in LDS.  Each combination is its own kernel, so a launch
+// carries only the code its units run and every pointer's memory is known.
+template <int W, bool GS, bool ADJ, bool TL>
 __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ order, uint32_t n_grid,
                                                      int* err) {
@@ -1134,9 +1152,10 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     uint32_t* tl = (uint32_t*)(bulk + BL.tl);
     int32_t* remap = (int32_t*)(bulk + BL.remap);
     int32_t* kpre = (int32_t*)(bulk + BL.kpre);
-    int32_t* rng = (int32_t*)(bulk + BL.rng);
-    uint32_t* tp = (uint32_t*)(bulk + BL.tp);
-    uint32_t* pl = (uint32_t*)(bulk + BL.pl);
+    const TableLayout TB = table_layout(n_vmax, C.m_cap, C.kbits);
+    int32_t* rng = TL ? (int32_t*)((char*)smem + TB.rng) : (int32_t*)(bulk + BL.rng);
+    uint32_t* tp = TL ? (uint32_t*)((char*)smem + TB.tp) : (uint32_t*)(bulk + BL.tp);
+    uint32_t* pl = TL ? (uint32_t*)((char*)smem + TB.pl) : (uint32_t*)(bulk + BL.pl);
     const int pw = plane_words(C.m_cap);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);

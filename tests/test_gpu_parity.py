@@ -432,21 +432,24 @@ def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
     ref = compare(oracle, [A], kw, "layouts")[0]
     sid = cse.cse_system_load(ctx, A)
     tried = 0
-    for lay in range(4):
+    for lay in (0, 1, 2, 3, 7):
         try:
             cse.cse_scheme_layout(ctx, sid, 0, lay)
         except cse.CseError as e:
-            assert "CSE_ENOMEM" in str(e) and not lay & cse.CSE_LAYOUT_HBM
+            assert "CSE_ENOMEM" in str(e) and (not lay & cse.CSE_LAYOUT_HBM or lay & cse.CSE_LAYOUT_LDS_TABLES)
             continue
         assert cse.cse_scheme_layout(ctx, sid, 0) == lay
         say(f"[gpu] layout {lay}: system {rows}x{cols}")
         job, got = run_loaded(gpu, sid, kw)
         with pytest.raises(cse.CseError, match="CSE_EBUSY"):
-            cse.cse_scheme_layout(ctx, sid, 0, lay ^ cse.CSE_LAYOUT_RANGE)
+            cse.cse_scheme_layout(ctx, sid, 0, (lay + 1) % 4)
         cse.cse_job_release(ctx, job)
         assert_same(got, ref, f"layout {lay} {rows}x{cols}")
         tried += 1
-    assert tried >= 2
+    assert tried >= 3
+    for bad in (4, 5, 6, 8):
+        with pytest.raises(cse.CseError, match="CSE_EINVAL"):
+            cse.cse_scheme_layout(ctx, sid, 0, bad)
     say(f"[gpu] autotune: system {rows}x{cols}")
     chosen = cse.cse_autotune(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
     assert chosen[0] == cse.cse_scheme_layout(ctx, sid, 0) and chosen[1:] == [-1, -1]
@@ -522,6 +525,8 @@ def test_randomized_configurations(gpu, oracle):
         ref = compare(oracle, [A], kw, "random")[0]
         sid = cse.cse_system_load(ctx, A)
         lay = int(rng.integers(0, 4))
+        if lay == 3 and case % 2:
+            lay = 7
         try:
             cse.cse_scheme_layout(ctx, sid, 0, lay)
         except cse.CseError as e:
@@ -686,7 +691,8 @@ def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
               share_src_pm=60, share_dst_pm=400, share_max_rounds=1000)
     ref = compare(oracle, [A], kw, "resume")[0]
     assert ref["epoch"].max() > 1
-    for lay in (cse.CSE_LAYOUT_HBM, cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE):
+    for lay in (cse.CSE_LAYOUT_HBM, cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE,
+                cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_LDS_TABLES):
         sid = cse.cse_system_load(ctx, A)
         cse.cse_scheme_layout(ctx, sid, 0, lay)
         say(f"[gpu] resume: system {rows}x{cols} every {every} layout {lay}")
