@@ -680,7 +680,7 @@ def test_driver_cancel_from_another_thread(gpu):
     cse.cse_scheme_free(ctx, sid)
 
 
-@pytest.mark.parametrize("rows,cols,p,every", [(60, 18, 0.3, 1), (160, 36, 0.15, 3), (42, 120, 0.2, 6)])
+@pytest.mark.parametrize("rows,cols,p,every", [(60, 18, 0.3, 1), (160, 36, 0.15, 3), (24, 80, 0.2, 4)])
 def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
     """Units with state in HBM slots resume from the slot between sharing
     rounds unless they were restarted; with rounds every few steps and many
