@@ -214,6 +214,17 @@ int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* tri
 int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, uint64_t* elapsed_ns, int32_t cap,
                           int32_t* n);
 
+/* The component-wise hybrid over several finished jobs of schemes with the
+ * same number of components (Sec. 4: the best U, V and W^T may come from
+ * different runs or strategy mixes): for each component, the lowest cost
+ * over the jobs, the job and the process holding it (ties: the earlier job
+ * in the list, then the lower process).  A driver job counts with its best
+ * program so far (read it with cse_driver_best), any other job with its
+ * best unit (cse_get_program with that process).  Absent components: -1.
+ * best_job and best_proc may be NULL.  Blocking. */
+int32_t cse_hybrid_best(cse_ctx* ctx, const int32_t* job_ids, int32_t n, int32_t best_cost[3], int32_t best_job[3],
+                        int32_t best_proc[3]);
+
 /* Non-blocking: *done = 1 when the job's device work has completed, else 0.
  * best_cost (3 entries, may be NULL) receives, once done, the lowest cost
  * over the units of each component (the best of each pool, Sec. 3.5, and

@@ -34,7 +34,7 @@ EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error",
            "cse_relaunch", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results", "cse_get_programs",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
-           "cse_run_driver", "cse_driver_best", "cse_driver_totals")
+           "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best")
 CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE = 0, 1, 2
 
 
@@ -146,6 +146,8 @@ def load_library(path: str = LIB_PATH):
     L.cse_driver_best.restype = i32
     L.cse_driver_totals.argtypes = [vp, i32, P(i32), P(ctypes.c_uint64), i32, P(i32)]
     L.cse_driver_totals.restype = i32
+    L.cse_hybrid_best.argtypes = [vp, P(i32), i32, P(i32), P(i32), P(i32)]
+    L.cse_hybrid_best.restype = i32
     _lib = L
     return L
 
@@ -391,6 +393,14 @@ def cse_driver_totals(ctx, job_id, elapsed=False):
                                     ctypes.byref(n)))
     totals = [int(x) for x in out[:n.value]]
     return (totals, [int(x) for x in ns[:n.value]]) if elapsed else totals
+
+
+def cse_hybrid_best(ctx, job_ids):
+    """Per component over several jobs: [(cost, job, proc)] of the best (Sec. 4 hybrid)."""
+    ids = np.ascontiguousarray(job_ids, dtype=np.int32)
+    cost, job, proc = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)()
+    _check(ctx, load_library().cse_hybrid_best(ctx, _p(ids, ctypes.c_int32), len(ids), cost, job, proc))
+    return [(cost[c], job[c], proc[c]) for c in range(3) if cost[c] >= 0]
 
 
 # Servers report errors through the context they were created on.

@@ -1644,6 +1644,60 @@ int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* tri
     return CSE_OK;
 }
 
+int32_t cse_hybrid_best(cse_ctx* ctx, const int32_t* job_ids, int32_t n, int32_t best_cost[3], int32_t best_job[3],
+                        int32_t best_proc[3]) {
+    if (!ctx || !job_ids || n < 1 || !best_cost) return CSE_EINVAL;
+    int n_comp = -1;
+    for (int i = 0; i < n; ++i) {
+        JobRec* J = nullptr;
+        int rc = readable(ctx, job_ids[i], &J, -1);
+        if (rc) return rc;
+        if (n_comp >= 0 && J->n_comp != n_comp)
+            return fail(ctx, CSE_EINVAL, "jobs have different numbers of components");
+        n_comp = J->n_comp;
+    }
+    for (int c = 0; c < 3; ++c) {
+        best_cost[c] = -1;
+        if (best_job) best_job[c] = -1;
+        if (best_proc) best_proc[c] = -1;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    for (int i = 0; i < n; ++i) {
+        JobRec& J = ctx->jobs[job_ids[i]];
+        int32_t cost[3], proc[3];
+        if (J.driver && J.best_cost[0] >= 0) {
+            for (int c = 0; c < n_comp; ++c) {
+                cost[c] = J.best_cost[c];
+                proc[c] = J.best_proc[c];
+            }
+        } else {
+            // The best unit of each component: a device argmin over (cost, process).
+            unsigned long long* d_key = nullptr;
+            HIP_TRY(ctx, hipMalloc((void**)&d_key, sizeof(unsigned long long) * 3));
+            hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, nullptr, (int32_t*)d_key, 6, -1);
+            for (int c = 0; c < n_comp; ++c)
+                hipLaunchKernelGGL(csek::driver_argmin_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0,
+                                   nullptr, J.cj[c].st.cost, J.cfg.n_proc, d_key + c);
+            unsigned long long key[3];
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpy(key, d_key, sizeof key, hipMemcpyDeviceToHost);
+            (void)hipFree(d_key);
+            if (e != hipSuccess) return fail(ctx, CSE_EHIP, "best units: %s", hipGetErrorString(e));
+            for (int c = 0; c < n_comp; ++c) {
+                cost[c] = (int32_t)(key[c] >> 32);
+                proc[c] = (int32_t)(key[c] & 0xFFFFFFFFu);
+            }
+        }
+        for (int c = 0; c < n_comp; ++c) {
+            if (best_cost[c] >= 0 && cost[c] >= best_cost[c]) continue;
+            best_cost[c] = cost[c];
+            if (best_job) best_job[c] = job_ids[i];
+            if (best_proc) best_proc[c] = proc[c];
+        }
+    }
+    return CSE_OK;
+}
+
 int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, uint64_t* elapsed_ns, int32_t cap,
                           int32_t* n) {
     if (!ctx || !n) return CSE_EINVAL;

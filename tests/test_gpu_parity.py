@@ -700,3 +700,46 @@ def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
         cse.cse_job_release(ctx, job)
         cse.cse_scheme_free(ctx, sid)
         assert_same(got, ref, f"resume {rows}x{cols} layout {lay}")
+
+
+def test_hybrid_best_over_jobs(gpu):
+    """Component-wise hybrid (Sec. 4): per component, the lowest cost over a
+    gi-only job, a ga-only job and a driver job, with the job and process that
+    hold it; each chosen program re-expands exactly."""
+    cse, ctx, torch = gpu
+    wl = workloads.plain_4x4x4(n_proc=256)
+    S = wl.schemes[0].systems
+    sid = cse.cse_scheme_load(ctx, *S)
+    st = torch.cuda.current_stream()
+    jobs = []
+    for w in ({"gi": 1}, {"ga": 1}):
+        j = cse.cse_launch(ctx, sid, cse.cse_run_cfg(seed=4, n_proc=256, weights=w), st)
+        cse.cse_wait(ctx, j)
+        jobs.append(j)
+    dj, _ = cse.cse_run_driver(ctx, sid, cse.cse_run_cfg(seed=5, n_proc=256, weights=dict(workloads.PAPER_WEIGHTS)),
+                               st, patience=2, max_iterations=6)
+    jobs.append(dj)
+    hyb = cse.cse_hybrid_best(ctx, jobs)
+    assert len(hyb) == 3
+    for c in range(3):
+        per_job = []
+        for j in jobs:
+            if j == dj:
+                b = cse.cse_driver_best(ctx, j, c)
+                per_job.append((b["cost"], j, b["proc"]))
+            else:
+                cost = cse.cse_get_unit_results(ctx, j, c, 256)["cost"]
+                u = int(np.argmin(cost))
+                per_job.append((int(cost[u]), j, u))
+        want = min(per_job, key=lambda x: x[0])
+        assert hyb[c] == want, (c, hyb[c], per_job)
+        cost, j, u = hyb[c]
+        if j == dj:
+            prog = cse.cse_driver_best(ctx, j, c)["prog"]
+        else:
+            prog, pc = cse.cse_get_program(ctx, j, c, proc=u)
+            assert pc == cost
+        check_program(S[c], prog, cost)
+    for j in jobs:
+        cse.cse_job_release(ctx, j)
+    cse.cse_scheme_free(ctx, sid)
