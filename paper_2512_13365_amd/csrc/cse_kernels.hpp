@@ -26,7 +26,10 @@
 //                           weights, weight bit-planes, per-variable ranges
 //                           and the index map of the update.
 // The lists live in LDS; the rest lives in LDS too, or, for systems whose
-// state exceeds the LDS budget, in a per-unit slot in HBM.
+// state would leave fewer than four units per CU, in a per-unit slot in HBM
+// (optionally with tp, pl and rng in LDS).  A slot also records which state
+// it holds, so a unit that was not restarted resumes from it at its next
+// launch instead of replaying its program.
 // The pair count of (a, b, +) is popc(Pa & Pb) + popc(Na & Nb) and of
 // (a, b, -) popc(Pa & Nb) + popc(Na & Pb), summed over the row words.
 // Every random draw is a Philox4x32-10 block of a counter that names the
