@@ -242,8 +242,9 @@ int32_t cse_wait(cse_ctx* ctx, int32_t job_id);
  * A job whose device work already completed is left as it is.  Returns
  * CSE_OK once the request is recorded; cse_wait then returns CSE_ECANCELED.
  * A relaunch clears the request.  This is the one call that may run on
- * another thread while cse_wait blocks on the same job; otherwise a context
- * is used by one thread at a time. */
+ * another thread while cse_wait or cse_run_driver blocks on the same job
+ * (a driver run stops after its current iteration); otherwise a context is
+ * used by one thread at a time. */
 int32_t cse_cancel(cse_ctx* ctx, int32_t job_id);
 
 /* Per-unit results of component `comp` for processes 0..n-1 (n = n_proc);
