@@ -606,6 +606,12 @@ def test_driver_tiny_and_edge_settings(gpu, oracle):
     check_driver(gpu, oracle, [A], kw2, "no restarts", reinit_pm=0, patience=100, max_iterations=3)
     got = check_driver(gpu, oracle, [A], kw2, "one iteration", patience=0, max_iterations=10)
     assert got["iterations"] == 1
+    kw3 = dict(kw2, step_cap=7)
+    ref3 = oracle.run_driver([A], oracle.make_cfg(**kw3), n_threads=THREADS, patience=2, max_iterations=5)
+    got3 = run_driver_gpu(gpu, [A], dict(kw3, count_path=2), patience=2, max_iterations=5)
+    assert got3["iterations"] == ref3["iterations"] and got3["totals"] == ref3["totals"]
+    assert_same(got3["last"][0], ref3["last"][0], "driver step cap, MFMA count path")
+    assert int(got3["last"][0]["steps"].max()) <= 7
 
 
 def test_driver_rejects_bad_use(gpu):
