@@ -63,3 +63,48 @@ def test_binding_fails_loudly_without_library(tmp_path):
             cse.load_library(str(tmp_path / "missing.so"))
     finally:
         cse._lib = saved
+
+
+def test_driver_cfg_struct_layout_matches_header(tmp_path):
+    """The binding's cse_driver_cfg has the C compiler's size and offsets."""
+    import subprocess
+
+    from paper_2512_13365_amd import cse
+    fields = [f[0] for f in cse.CseDriverCfg._fields_]
+    src = tmp_path / "dlayout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cse.h"\nint main(void){\n'
+                   '  printf("%zu\\n", sizeof(cse_driver_cfg));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(cse_driver_cfg, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "dlayout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cse.CseDriverCfg) == 16
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cse.CseDriverCfg, f).offset == off, f
+
+
+def test_binding_constants_match_header():
+    """CSE_LAYOUT_*, CSE_COUNT_* and CSE_JOB_* of the binding equal the header's."""
+    from paper_2512_13365_amd import cse
+    defs = dict(re.findall(r"#define\s+(CSE_[A-Z_]+)\s+(-?\d+)", open(HEADER).read()))
+    names = [n for n in defs if n.startswith(("CSE_LAYOUT_", "CSE_COUNT_", "CSE_JOB_"))]
+    assert len(names) >= 9
+    for n in names:
+        assert getattr(cse, n) == int(defs[n]), n
+    codes = dict(re.findall(r"#define\s+(CSE_OK|CSE_E[A-Z]+)\s+\(?(-?\d+)\)?", open(HEADER).read()))
+    assert len(codes) == 8
+    assert {int(v): k for k, v in codes.items()} == cse.STATUS
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
