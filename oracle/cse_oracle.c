@@ -35,7 +35,7 @@
 #define OC_ENOMEM (-2)
 #define OC_ERANGE (-3)
 
-/* Strategy ids (Sec. 3.4.1, 3.4.2, 3.4.3; gp of Sec. 3.5.1 is not built). */
+/* Strategy ids (Sec. 3.4.1, 3.4.2, 3.4.3; gp of Sec. 2 and 3.4, read as below). */
 enum { S_G = 0, S_GA = 1, S_WR = 2, S_GR = 3, S_GI = 4, S_MIX = 5, S_GP = 6, N_STRAT = 7 };
 
 /* Random-stream tags placed in the top nibble of counter word 1 (REINIT is
@@ -268,6 +268,57 @@ int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
     return best;
 }
 
+int oc_substitute(int8_t* A, int n_e, int stride, int a, int b, int s, int k);
+
+/* Greedy-Potential (gp), Sec. 2 and 3.4: a candidate's potential is the
+ * number of new substitution possibilities a trial substitution creates.
+ * Counts of old pairs can only fall, so the new possibilities are the pairs
+ * (x, k, s) of the fresh variable k that occur at least twice.  Reading:
+ *     2^16 H(p) = (c_p - 1) 2^16 + alpha_q N_new(p),
+ * alpha_q the process's alpha (alpha = alpha_q / 2^16 in [0, 0.5), as for
+ * gi), evaluated exactly; ties go to the first in canonical order.  For each
+ * candidate the oracle substitutes on a copy of the n_e x n_v system and
+ * counts the fresh variable's pairs row by row.  n_cols (optional) receives
+ * the number of (candidate, live column other than a and b) pairs counted,
+ * for the algorithmic work tally. */
+int oc_select_gp(const int8_t* A, int n_e, int n_v, int stride, const oc_cand* C, int m, uint32_t alpha_q,
+                 int64_t* n_cols)
+{
+    int8_t* T = (int8_t*)malloc((size_t)n_e * stride);
+    int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * 2 * ((size_t)n_v + 1));
+    if (!T || !cnt) { free(T); free(cnt); return -1; }
+    int live = 0;
+    for (int j = 0; j < n_v; j++) {
+        for (int i = 0; i < n_e; i++)
+            if (A[(size_t)i * stride + j]) { live++; break; }
+    }
+    int best = -1;
+    int64_t best_h = 0;
+    for (int p = 0; p < m; p++) {
+        int a = key_a(C[p].key), b = key_b(C[p].key), s = key_s(C[p].key);
+        memcpy(T, A, (size_t)n_e * stride);
+        int k = n_v + 1;
+        oc_substitute(T, n_e, stride, a, b, s, k);
+        memset(cnt, 0, sizeof(int32_t) * 2 * ((size_t)n_v + 1));
+        for (int i = 0; i < n_e; i++) {
+            int8_t ak = T[(size_t)i * stride + (k - 1)];
+            if (!ak) continue;
+            for (int x = 1; x <= n_v; x++) {
+                int8_t ax = T[(size_t)i * stride + (x - 1)];
+                if (ax) cnt[2 * x + (ax * ak < 0)]++;
+            }
+        }
+        int64_t n_new = 0;
+        for (int x = 1; x <= n_v; x++) n_new += (cnt[2 * x] >= 2) + (cnt[2 * x + 1] >= 2);
+        int64_t h = ((int64_t)(C[p].c - 1) << 16) + (int64_t)alpha_q * n_new;
+        if (best < 0 || h > best_h) { best = p; best_h = h; }
+    }
+    if (n_cols) *n_cols = (int64_t)m * (live > 2 ? live - 2 : 0);
+    free(T);
+    free(cnt);
+    return best;
+}
+
 /* ------------------------------------------------------------------------
  * Substitution (Algorithm 1; Sec. 3.2.1): fresh x_k = x_a + s x_b replaces
  * the pair in every row where both occur with relative sign s; the row keeps
@@ -367,6 +418,9 @@ static int live_columns(const int8_t* A, int n_e, int n_v, int stride)
  *   98                       one Philox4x32-10 block for the step draw
  *   gi:  2 n_int + 98 n_blk + 10 m   coin tests and masked adds, coin blocks,
  *                                    disjoint sums, score and argmax
+ *   gp:  10 w m + 8 w n_cols + 2 m   trial substitutions, the fresh column's
+ *                                    pair counts against n_cols live columns
+ *                                    (four sign pairs: AND + POPC), argmax
  *   other strategies: 2 m             one scan plus one pick pass
  *   10 w                              substitution over w 32-bit row words
  *   24 w (n_live - 1)                 recount of the three changed columns
@@ -375,7 +429,8 @@ static int live_columns(const int8_t* A, int n_e, int n_v, int stride)
 static int64_t step_ops(int strat, int m, int64_t n_int, int64_t n_blk, int n_e, int n_live)
 {
     int64_t w = (n_e + 31) / 32;
-    int64_t sel = (strat == S_GI) ? (2 * n_int + 98 * n_blk + 10 * (int64_t)m) : (2 * (int64_t)m);
+    int64_t sel = (strat == S_GI) ? (2 * n_int + 98 * n_blk + 10 * (int64_t)m)
+                : (strat == S_GP) ? (10 * w * (int64_t)m + 8 * w * n_int + 2 * (int64_t)m) : (2 * (int64_t)m);
     return 98 + sel + 10 * w + 24 * w * (int64_t)(n_live - 1);
 }
 
@@ -432,6 +487,8 @@ static void unit_run(const oc_problem* P, oc_unit* U, int budget)
         case S_WR: pick = oc_select_wr(U->cand, m, u[2]); break;
         case S_GI: pick = oc_select_gi(U->cand, m, U->alpha_q, U->beta_q, cfg->seed, U->proc, P->comp,
                                        (uint32_t)U->epoch, (uint32_t)U->t, &n_int, &n_blk); break;
+        case S_GP: pick = oc_select_gp(U->A, P->n_e, P->n_x + U->t, P->n_vmax, U->cand, m, U->alpha_q, &n_int);
+                   break;
         default:   pick = -1; break;
         }
         if (pick < 0) { U->active = 0; break; }
@@ -566,7 +623,6 @@ int oc_run_pool(const int8_t* A0, int n_e, int n_x, int comp, const oc_cfg* cfg,
         for (int j = 0; j < n_x; j++) nnz += A0[(size_t)i * n_x + j] != 0;
         if (nnz == 0) return OC_EINVAL;
     }
-    if (cfg->weights[S_GP] != 0) return OC_EINVAL;
     if (cfg->share_every && procs) return OC_EINVAL;
 
     oc_problem P;

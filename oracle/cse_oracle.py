@@ -74,6 +74,9 @@ def lib():
                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                    ctypes.c_uint32, P(ctypes.c_int64), P(ctypes.c_int64)]
         L.oc_select_gi.restype = ctypes.c_int
+        L.oc_select_gp.argtypes = [P(ctypes.c_int8), ctypes.c_int, ctypes.c_int, ctypes.c_int, P(OracleCand),
+                                   ctypes.c_int, ctypes.c_uint32, P(ctypes.c_int64)]
+        L.oc_select_gp.restype = ctypes.c_int
         L.oc_substitute.argtypes = [P(ctypes.c_int8), ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oc_substitute.restype = ctypes.c_int
@@ -183,6 +186,20 @@ def select_gi(cands, alpha_q, beta_q, seed=0, proc=0, comp=0, epoch=0, step=0):
     i = lib().oc_select_gi(_cands(cands), len(cands), alpha_q, beta_q, seed, proc, comp, epoch, step,
                            ctypes.byref(n_int), ctypes.byref(n_blk))
     return int(i), int(n_int.value), int(n_blk.value)
+
+
+def select_gp(A, alpha_q):
+    """Greedy-Potential pick on system A (n_e x n_v, all columns current
+    variables): (index into analyse(A), n_cols)."""
+    A = np.ascontiguousarray(A, dtype=np.int8)
+    n_e, n_v = A.shape
+    W = np.zeros((n_e, n_v + 1), np.int8)
+    W[:, :n_v] = A
+    cands = analyse(A)
+    n_cols = ctypes.c_int64()
+    i = lib().oc_select_gp(_ptr(W, ctypes.c_int8), n_e, n_v, n_v + 1, _cands(cands), len(cands), alpha_q,
+                           ctypes.byref(n_cols))
+    return int(i), int(n_cols.value)
 
 
 def substitute(A, a, b, s, k):

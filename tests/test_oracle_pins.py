@@ -13,7 +13,7 @@ from cse_helpers import (brute_force_optimum, check_program, is_terminal, naive_
                          pair_counts, read_golden, replay)
 from paper_2512_13365_amd.workloads import random_system
 
-ALL = ("g", "ga", "wr", "gr", "gi", "mix")
+ALL = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
 
 
 def _golden_matrix(rows):
@@ -358,3 +358,36 @@ def test_sharing_rounds(oracle):
                            init_epoch=r["epoch"][idx])
     assert np.array_equal(cont["prog"], r["prog"][idx])
     assert np.array_equal(cont["cost"], r["cost"][idx])
+
+
+def _gp_reference(A, alpha_q):
+    """Independent Greedy-Potential pick: symbolic replay of each trial
+    substitution and a dictionary count of the fresh variable's pairs."""
+    cands = sorted(((a, b, s, c) for (a, b, s), c in pair_counts(A).items() if c >= 2),
+                   key=lambda t: (t[0], t[1], t[2] < 0))
+    k = A.shape[1] + 1
+    best, best_h = -1, None
+    for i, (a, b, s, c) in enumerate(cands):
+        F, _ = replay(A, [(a, b, s)])
+        n_new = sum(1 for (x, y, _), cnt in pair_counts(F).items() if cnt >= 2 and k in (x, y))
+        h = ((c - 1) << 16) + alpha_q * n_new
+        if best_h is None or h > best_h:
+            best, best_h = i, h
+    return best
+
+
+def test_gp_matches_independent_potential(oracle):
+    """Greedy-Potential (Sec. 2, 3.4; reading R21): the oracle's pick equals
+    one computed from an independent replay and pair count, for several
+    alphas, and alpha = 0 is greedy."""
+    rng = np.random.default_rng(17)
+    for case in range(12):
+        rows, cols = int(rng.integers(6, 30)), int(rng.integers(4, 12))
+        A = random_system(int(rng.integers(1 << 30)), rows, cols, float(rng.uniform(0.25, 0.6)))
+        if not oracle.analyse(A):
+            continue
+        for alpha_q in (0, 1, 4096, 32767):
+            got, n_cols = oracle.select_gp(A, alpha_q)
+            assert got == _gp_reference(A, alpha_q), (case, alpha_q)
+        assert oracle.select_gp(A, 0)[0] == oracle.select_g(oracle.analyse(A))
+
