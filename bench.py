@@ -408,7 +408,7 @@ def main():
     ap.add_argument("--patience", type=int, default=10, help="driver: iterations without improvement to stop")
     ap.add_argument("--driver-scheme", default="4x4x4", choices=["4x4x4", "6x6x6"], help="driver: which systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix"],
+    ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix", "gp"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
     ap.add_argument("--autotune", action="store_true",

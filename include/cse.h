@@ -50,14 +50,14 @@ extern "C" {
 #define CSE_ECANCELED (-7)  /* job was cancelled */
 
 /* Strategy ids, the index into cse_run_cfg.weights (Sec. 3.4.1-3.4.3,
- * 3.5.1).  Greedy-Potential (gp) is reserved: its weight must be 0. */
+ * 3.5.1; Greedy-Potential of Sec. 2 and 3.4). */
 #define CSE_STRAT_G   0   /* greedy: highest frequency */
 #define CSE_STRAT_GA  1   /* greedy-alternative: uniform among maximal */
 #define CSE_STRAT_WR  2   /* weighted-random: probability ~ c - 1 */
 #define CSE_STRAT_GR  3   /* greedy-random: ga with prob gr_p, else wr */
 #define CSE_STRAT_GI  4   /* greedy-intersections (Sec. 3.4.2) */
 #define CSE_STRAT_MIX 5   /* per step one of gi/ga/gr/wr by mix_weights */
-#define CSE_STRAT_GP  6   /* reserved */
+#define CSE_STRAT_GP  6   /* greedy-potential: c - 1 plus alpha x new pairs after a trial */
 
 /* Counting paths for the pair counts of the Analysis step (Algorithm 1).
  * All paths give identical results. */

@@ -1087,15 +1087,74 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
     return gi_argmax(best_h, best_p);
 }
 
+// Greedy-Potential (Sec. 2 and 3.4, potential as new pairs): for each candidate
+// (a, b, s), the column the fresh variable would get (rows of a and b with
+// relative sign s, carrying a's sign) is counted against every other live
+// column; N_new is the number of its pairs (x, +/-) with count >= 2.  The
+// score 2^16 (c - 1) + alpha_q N_new is maximal, ties to the first candidate.
+// One lane per candidate holds the trial column in registers; the loop over
+// the live list is uniform across the wave, so each column word is one
+// broadcast read.  The columns of a and b lose exactly the rewritten rows,
+// so they share none with the fresh column and are skipped.  *n_cols
+// receives m (n_live - 2), the columns counted.
+template <int W>
+__device__ int select_gp(const uint64_t* cand, int m, const uint64_t* colP, const uint64_t* colN,
+                         const uint32_t* live, int n_live, uint32_t alpha_q, long long* n_cols) {
+    const int l = lane_id();
+    long long best_h = -1;
+    int best_p = 0x7FFFFFFF;
+    for (int base = 0; base < m; base += kWave) {
+        const int q = base + l;
+        const uint64_t e = cand[q < m ? q : 0];
+        const uint32_t key = (uint32_t)e;
+        const int a = key_a(key), b = key_b(key);
+        const bool neg = key & 1u;
+        uint64_t Pk[W], Nk[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t Pa = colP[(a - 1) * W + w], Na = colN[(a - 1) * W + w];
+            const uint64_t Pb = colP[(b - 1) * W + w], Nb = colN[(b - 1) * W + w];
+            const uint64_t R = neg ? ((Pa & Nb) | (Na & Pb)) : ((Pa & Pb) | (Na & Nb));
+            Pk[w] = Pa & R;
+            Nk[w] = Na & R;
+        }
+        int n_new = 0;
+        for (int i = 0; i < n_live; ++i) {
+            const int x = (int)live[i];
+            int same = 0, opp = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t Px = colP[(x - 1) * W + w], Nx = colN[(x - 1) * W + w];
+                same += popc64(Px & Pk[w]) + popc64(Nx & Nk[w]);
+                opp += popc64(Px & Nk[w]) + popc64(Nx & Pk[w]);
+            }
+            n_new += (x == a || x == b) ? 0 : (same >= 2) + (opp >= 2);
+        }
+        if (q < m) {
+            const long long h = ((long long)(entry_c(e) - 1) << 16) + (long long)alpha_q * n_new;
+            if (h > best_h) {
+                best_h = h;
+                best_p = q;
+            }
+        }
+    }
+    *n_cols = (long long)m * (n_live > 2 ? n_live - 2 : 0);
+    return gi_argmax(best_h, best_p);
+}
+
 // Algorithmic work of a step in 32-bit integer lane operations (the same
 // cost model the oracle tallies): 98 per Philox block of the step draw;
-// selection 2 n_int + 98 n_blk + 10 m for gi, 2 m otherwise; 10 w for the
-// substitution and 24 w (n_live - 1) for recounting the three changed
-// columns, w = ceil(n_e / 32).
+// selection 2 n_int + 98 n_blk + 10 m for gi, 10 w m + 8 w n_cols + 2 m for
+// gp (trial columns, their counts against n_cols columns, argmax), 2 m
+// otherwise; 10 w for the substitution and 24 w (n_live - 1) for recounting
+// the three changed columns, w = ceil(n_e / 32).
+template <bool GP>
 __device__ __forceinline__ unsigned long long step_ops(int strat, int m, long long n_int, long long n_blk,
                                                        int n_e, int n_live) {
     const long long w = (n_e + 31) / 32;
-    const long long sel = strat == S_GI ? (2 * n_int + 98 * n_blk + 10 * (long long)m) : 2 * (long long)m;
+    const long long sel = GP               ? (10 * w * m + 8 * w * n_int + 2 * (long long)m)
+                          : strat == S_GI ? (2 * n_int + 98 * n_blk + 10 * (long long)m)
+                                          : 2 * (long long)m;
     return (unsigned long long)(98 + sel + 10 * w + 24 * w * (long long)(n_live - 1));
 }
 
@@ -1118,12 +1177,13 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // ---------------------------------------------------------------------------
 // W: row words; GS: bulk state in HBM slots; ADJ: gi over per-variable
 // ranges (large candidate sets) instead of masks; TL (with GS and ADJ): the
-// range tables in LDS.  Each combination is its own kernel, so a launch
-// carries only the code its units run and every pointer's memory is known.
-template <int W, bool GS, bool ADJ, bool TL>
-__global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
-                                                     const uint32_t* __restrict__ order, uint32_t n_grid,
-                                                     int* err) {
+// range tables in LDS; GP: the kernel of the Greedy-Potential units (every
+// other unit runs in the kernel without it).  Each combination is its own
+// kernel, so a launch carries only the code its units run and every
+// pointer's memory is known.
+template <int W, bool GS, bool ADJ, bool TL, bool GP>
+__device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int n_segs,
+                                          const uint32_t* __restrict__ order, uint32_t n_grid, int* err) {
     extern __shared__ uint64_t smem[];
     const int l = lane_id();
     if (blockIdx.x >= n_grid) return;
@@ -1172,6 +1232,8 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
     else strat = weighted_pick(R.weights, N_STRAT, pu.x);
     const uint32_t alpha_q = pu.y >> 17;
     const uint32_t beta_q = 32768u + (pu.z >> 17);
+    // Each unit runs in exactly one of the two kernels of its class.
+    if ((strat == S_GP) != GP) return;
     // The second candidate ordering is kept only where gi walks ranges.
     const bool need_tl = ADJ && (strat == S_GI || strat == S_MIX);
 
@@ -1283,7 +1345,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
 
         // The step draw is consumed by ga, wr, gr and mix only.
         U4 su = {0u, 0u, 0u, 0u};
-        if (strat != S_G && strat != S_GI)
+        if (!GP && strat != S_G && strat != S_GI)
             su = philox10(proc, domain(TAG_STEP, C.comp, (uint32_t)epoch, (uint32_t)t), 0u, 0u, k0, k1);
         int s = strat;
         if (s == S_MIX) {
@@ -1294,7 +1356,9 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
 
         long long n_int = 0, n_blk = 0;
         int pick;
-        if (s == S_G) {
+        if constexpr (GP) {
+            pick = select_gp<W>(cand, m, colP, colN, live, n_live, alpha_q, &n_int);
+        } else if (s == S_G) {
             pick = select_g(cand, m);
         } else if (s == S_GA) {
             pick = select_ga(cand, m, su.z);
@@ -1327,7 +1391,7 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         ++t;
         cost -= c - 1;
         ++executed;
-        ops += step_ops(s, m, n_int, n_blk, C.n_e, n_live);
+        ops += step_ops<GP>(s, m, n_int, n_blk, C.n_e, n_live);
         if constexpr (ADJ) {
             int n_new = 0;
             const int m_old = m;
@@ -1358,6 +1422,20 @@ __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__
         S.active[proc] = active;
         if (!active) S.finish[proc] = wall_clock64() - *S.t0;
     }
+}
+
+template <int W, bool GS, bool ADJ, bool TL>
+__global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
+                                                     const uint32_t* __restrict__ order, uint32_t n_grid,
+                                                     int* err) {
+    step_body<W, GS, ADJ, TL, false>(segs, n_segs, order, n_grid, err);
+}
+
+template <int W, bool GS, bool ADJ, bool TL>
+__global__ __launch_bounds__(kWave) void step_kernel_gp(const Segment* __restrict__ segs, int n_segs,
+                                                        const uint32_t* __restrict__ order, uint32_t n_grid,
+                                                        int* err) {
+    step_body<W, GS, ADJ, TL, true>(segs, n_segs, order, n_grid, err);
 }
 
 // Lowest cost over a component's units (out starts at INT_MAX).

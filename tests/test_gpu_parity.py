@@ -156,7 +156,7 @@ def test_invalid_inputs_rejected(gpu):
         assert e.value.status == -1
     sid = cse.cse_system_load(ctx, np.array([[1, 1], [1, 1]], np.int8))
     with pytest.raises(cse.CseError):
-        cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=4, weights={"gp": 1}))
+        cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=4, weights={"mix": 1}, mix_weights=(0, 0, 0, 0)))
     with pytest.raises(cse.CseError):
         cse.cse_launch(ctx, sid, cse.cse_run_cfg(n_proc=0))
     with pytest.raises(cse.CseError) as e:
@@ -749,3 +749,57 @@ def test_hybrid_best_over_jobs(gpu):
     for j in jobs:
         cse.cse_job_release(ctx, j)
     cse.cse_scheme_free(ctx, sid)
+
+
+GP_W = {"gp": 4, "gi": 2, "ga": 1, "wr": 1, "mix": 1}
+
+
+@pytest.mark.parametrize("rows,cols,p,hi,cap", [
+    (9, 5, 0.5, None, 0), (40, 16, 0.3, 8, 0), (65, 24, 0.25, 8, 40), (130, 30, 0.2, 10, 30),
+    (200, 24, 0.12, 12, 24), (300, 20, 0.2, 8, 20), (330, 16, 0.25, 8, 16), (420, 14, 0.3, 8, 14),
+    (511, 10, 0.4, 6, 12)])
+def test_greedy_potential_shapes(gpu, oracle, rows, cols, p, hi, cap):
+    """Greedy-Potential units (the trial substitution score) over 1..8 row
+    words with ragged tails: gp alone, then beside the other strategies."""
+    A = workloads.random_system(rows * 977 + cols, rows, cols, p, 1, hi)
+    kw = dict(seed=rows * 3 + cols, n_proc=96, weights={"gp": 1}, step_cap=cap)
+    got, _ = check_workload(gpu, oracle, [A], kw, f"gp {rows}x{cols}")
+    assert (got[0]["strat"] == 6).all()
+    kw = dict(kw, seed=kw["seed"] + 1, weights=GP_W, proc0_greedy=True)
+    check_workload(gpu, oracle, [A], kw, f"gp mixed {rows}x{cols}")
+
+
+def test_greedy_potential_6x6x6_and_large_candidate_set(gpu, oracle):
+    """gp on the three 6x6x6 components at full size (no step cap) and on a
+    42 x 197 system whose candidate set exceeds 2000 pairs."""
+    wl = workloads.plain_6x6x6(n_proc=16)
+    check_workload(gpu, oracle, wl.schemes[0].systems, dict(seed=5, n_proc=16, weights={"gp": 3, "gi": 1}, step_cap=0),
+                   "gp 6x6x6")
+    A = workloads.random_system(42 * 31 + 197, 42, 197, 0.2)
+    check_workload(gpu, oracle, [A], dict(seed=6, n_proc=12, weights={"gp": 1}, step_cap=12), "gp 42x197")
+
+
+def test_greedy_potential_layouts_sharing_driver(gpu, oracle):
+    """gp units in every layout of the unit state, with sharing rounds, and
+    under the outer-iteration driver."""
+    cse, ctx, torch = gpu
+    for rows, cols, p, cap in ((60, 18, 0.3, 0), (160, 36, 0.15, 25)):
+        A = workloads.random_system(rows * 131 + cols, rows, cols, p)
+        kw = dict(seed=rows + 9, n_proc=64, weights=GP_W, proc0_greedy=True, step_cap=cap,
+                  share_every=3, share_src_pm=150, share_dst_pm=500, share_max_rounds=6)
+        ref = compare(oracle, [A], kw, "gp layouts")[0]
+        sid = cse.cse_system_load(ctx, A)
+        for lay in (0, 1, 2, 3, 7):
+            try:
+                cse.cse_scheme_layout(ctx, sid, 0, lay)
+            except cse.CseError as e:
+                assert "CSE_ENOMEM" in str(e)
+                continue
+            say(f"[gpu] gp layout {lay}: system {rows}x{cols}")
+            job, got = run_loaded(gpu, sid, kw)
+            cse.cse_job_release(ctx, job)
+            assert_same(got, ref, f"gp layout {lay} {rows}x{cols}")
+        cse.cse_scheme_free(ctx, sid)
+    S = [workloads.random_system(71 + i, 30, 12, 0.3, 1, 8) for i in range(3)]
+    check_driver(gpu, oracle, S, dict(seed=8, n_proc=48, weights=GP_W, proc0_greedy=True), "gp driver",
+                 patience=2, max_iterations=6)

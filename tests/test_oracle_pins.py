@@ -377,9 +377,10 @@ def _gp_reference(A, alpha_q):
 
 
 def test_gp_matches_independent_potential(oracle):
-    """Greedy-Potential (Sec. 2, 3.4; reading R21): the oracle's pick equals
-    one computed from an independent replay and pair count, for several
-    alphas, and alpha = 0 is greedy."""
+    """Greedy-Potential (Sec. 2, 3.4; the potential read as the number of the
+    fresh variable's pairs that occur at least twice after the trial
+    substitution): the oracle's pick equals one computed from an independent
+    replay and pair count, for several alphas, and alpha = 0 is greedy."""
     rng = np.random.default_rng(17)
     for case in range(12):
         rows, cols = int(rng.integers(6, 30)), int(rng.integers(4, 12))
