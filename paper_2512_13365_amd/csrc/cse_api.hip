@@ -5,9 +5,7 @@
 // jobs that share launches).  A batch is executed by launch groups: one
 // step-kernel launch per (row-word count W, state placement) covering the
 // units of all its jobs' components, described by a segment table in device
-// memory, plus, where a job gives Greedy-Potential a weight, a launch of the
-// gp kernel over the same units (each unit runs in the one kernel of its
-// strategy).  With sharing (Sec. 3.5.2) the host runs rounds: every group
+// memory.  With sharing (Sec. 3.5.2) the host runs rounds: every group
 // advances its units by at most share_every steps, each component pool
 // counts its active units, ranks them and copies prefixes, and the host
 // reads the counts.  A server is a batch whose job set changes between
@@ -111,7 +109,7 @@ struct LaunchGroup {
     bool gs = false;
     bool adj = false;
     bool tl = false;
-    bool gp = false;                // the kernel of the Greedy-Potential units
+    bool gp = false;                // some job gives Greedy-Potential a weight
     uint32_t n_grid = 0;
     size_t lds = 0;
     int seg_begin = 0, n_segs = 0;  // slice of the batch's segment table
@@ -607,38 +605,34 @@ void free_batch_device(BatchRec& B) {
 
 // Dynamic LDS above 64 KB must be allowed per kernel before launches (and
 // before a launch is captured into a graph).
-template <int W, bool GS, bool ADJ, bool TL, bool GP>
+template <int W, bool GS, bool ADJ, bool TL>
 int set_lds_limit_w(cse_ctx* ctx, size_t lds) {
-    const void* k = GP ? (const void*)csek::step_kernel_gp<W, GS, ADJ, TL> : (const void*)csek::step_kernel<W, GS, ADJ, TL>;
-    HIP_TRY(ctx, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS, ADJ, TL>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return CSE_OK;
 }
-template <bool GS, bool ADJ, bool TL, bool GP>
+template <bool GS, bool ADJ, bool TL>
 int set_lds_limit_gs(cse_ctx* ctx, int W, size_t lds) {
     switch (W) {
-    case 1: return set_lds_limit_w<1, GS, ADJ, TL, GP>(ctx, lds);
-    case 2: return set_lds_limit_w<2, GS, ADJ, TL, GP>(ctx, lds);
-    case 3: return set_lds_limit_w<3, GS, ADJ, TL, GP>(ctx, lds);
-    case 4: return set_lds_limit_w<4, GS, ADJ, TL, GP>(ctx, lds);
-    case 5: return set_lds_limit_w<5, GS, ADJ, TL, GP>(ctx, lds);
-    case 6: return set_lds_limit_w<6, GS, ADJ, TL, GP>(ctx, lds);
-    case 7: return set_lds_limit_w<7, GS, ADJ, TL, GP>(ctx, lds);
-    case 8: return set_lds_limit_w<8, GS, ADJ, TL, GP>(ctx, lds);
+    case 1: return set_lds_limit_w<1, GS, ADJ, TL>(ctx, lds);
+    case 2: return set_lds_limit_w<2, GS, ADJ, TL>(ctx, lds);
+    case 3: return set_lds_limit_w<3, GS, ADJ, TL>(ctx, lds);
+    case 4: return set_lds_limit_w<4, GS, ADJ, TL>(ctx, lds);
+    case 5: return set_lds_limit_w<5, GS, ADJ, TL>(ctx, lds);
+    case 6: return set_lds_limit_w<6, GS, ADJ, TL>(ctx, lds);
+    case 7: return set_lds_limit_w<7, GS, ADJ, TL>(ctx, lds);
+    case 8: return set_lds_limit_w<8, GS, ADJ, TL>(ctx, lds);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", W);
     }
 }
-template <bool GP>
-int set_lds_limit_g(cse_ctx* ctx, const LaunchGroup& G) {
-    if (G.gs && G.adj)
-        return G.tl ? set_lds_limit_gs<true, true, true, GP>(ctx, G.W, G.lds)
-                    : set_lds_limit_gs<true, true, false, GP>(ctx, G.W, G.lds);
-    if (G.gs) return set_lds_limit_gs<true, false, false, GP>(ctx, G.W, G.lds);
-    return G.adj ? set_lds_limit_gs<false, true, false, GP>(ctx, G.W, G.lds)
-                 : set_lds_limit_gs<false, false, false, GP>(ctx, G.W, G.lds);
-}
 int set_lds_limit(cse_ctx* ctx, const LaunchGroup& G) {
     if (G.lds <= 65536) return CSE_OK;
-    return G.gp ? set_lds_limit_g<true>(ctx, G) : set_lds_limit_g<false>(ctx, G);
+    if (G.gs && G.adj)
+        return G.tl ? set_lds_limit_gs<true, true, true>(ctx, G.W, G.lds)
+                    : set_lds_limit_gs<true, true, false>(ctx, G.W, G.lds);
+    if (G.gs) return set_lds_limit_gs<true, false, false>(ctx, G.W, G.lds);
+    return G.adj ? set_lds_limit_gs<false, true, false>(ctx, G.W, G.lds)
+                 : set_lds_limit_gs<false, false, false>(ctx, G.W, G.lds);
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -690,16 +684,11 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
         G.n_segs = (int)B.segs.size() - G.seg_begin;
         G.n_grid = unit;
         if (!G.n_segs) continue;
-        B.groups.push_back(G);
-        // Greedy-Potential units run in a kernel of their own over the same
-        // segments; it is launched only where a job gives gp a weight.
-        bool any_gp = false;
+        // The kernel's Greedy-Potential body is entered only where a job
+        // gives gp a weight.
         for (int si = G.seg_begin; si < G.seg_begin + G.n_segs; ++si)
-            any_gp |= ctx->jobs[B.seg_job[si]].cfg.weights[CSE_STRAT_GP] != 0;
-        if (any_gp) {
-            G.gp = true;
-            B.groups.push_back(G);
-        }
+            G.gp |= ctx->jobs[B.seg_job[si]].cfg.weights[CSE_STRAT_GP] != 0;
+        B.groups.push_back(G);
     }
     // Longest expected work first, so that the long units do not form the
     // tail of the launch (unit results do not depend on the order).
@@ -825,50 +814,44 @@ int set_iteration(cse_ctx* ctx, BatchRec& B, uint32_t it) {
     return CSE_OK;
 }
 
-template <int W, bool GS, bool ADJ, bool TL, bool GP>
+template <int W, bool GS, bool ADJ, bool TL>
 int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                    int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    if constexpr (GP)
-        hipLaunchKernelGGL((csek::step_kernel_gp<W, GS, ADJ, TL>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
-                           d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
-    else
-        hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
-                           d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err);
+    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+                       d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err, G.gp ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;
 }
 
-template <bool GS, bool ADJ, bool TL, bool GP>
+template <bool GS, bool ADJ, bool TL>
 int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
                     int* d_err, hipStream_t s) {
     switch (G.W) {
-    case 1: return launch_group_w<1, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 2: return launch_group_w<2, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 3: return launch_group_w<3, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 4: return launch_group_w<4, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 5: return launch_group_w<5, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 6: return launch_group_w<6, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 7: return launch_group_w<7, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
-    case 8: return launch_group_w<8, GS, ADJ, TL, GP>(ctx, G, d_segs, d_order, d_err, s);
+    case 1: return launch_group_w<1, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 2: return launch_group_w<2, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 3: return launch_group_w<3, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 4: return launch_group_w<4, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 5: return launch_group_w<5, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 6: return launch_group_w<6, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 7: return launch_group_w<7, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
+    case 8: return launch_group_w<8, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
     default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
     }
 }
 
-template <bool GP>
-int launch_group(cse_ctx* ctx, const LaunchGroup& G, BatchRec& B, hipStream_t s) {
-    if (G.gs && G.adj)
-        return G.tl ? launch_group_gs<true, true, true, GP>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                    : launch_group_gs<true, true, false, GP>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
-    if (G.gs) return launch_group_gs<true, false, false, GP>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
-    return G.adj ? launch_group_gs<false, true, false, GP>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                 : launch_group_gs<false, false, false, GP>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
-}
-
 int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
     for (const LaunchGroup& G : B.groups) {
-        const int rc = G.gp ? launch_group<true>(ctx, G, B, s) : launch_group<false>(ctx, G, B, s);
+        int rc;
+        if (G.gs && G.adj)
+            rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                      : launch_group_gs<true, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        else if (G.gs)
+            rc = launch_group_gs<true, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+        else
+            rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
+                       : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         if (rc) return rc;
     }
     return CSE_OK;

@@ -1177,8 +1177,8 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // ---------------------------------------------------------------------------
 // W: row words; GS: bulk state in HBM slots; ADJ: gi over per-variable
 // ranges (large candidate sets) instead of masks; TL (with GS and ADJ): the
-// range tables in LDS; GP: the kernel of the Greedy-Potential units (every
-// other unit runs in the kernel without it).  Each combination is its own
+// range tables in LDS; GP: the body of the Greedy-Potential units (every
+// other unit runs in the body without it).  Each (W, GS, ADJ, TL) is its own
 // kernel, so a launch carries only the code its units run and every
 // pointer's memory is known.
 template <int W, bool GS, bool ADJ, bool TL, bool GP>
@@ -1424,18 +1424,16 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     }
 }
 
+// Each unit runs in the body of its strategy; the other body returns after
+// the process draw.  gp units (any_gp: some job of the launch weights gp)
+// thus share the launch with the others, while each body is compiled on its
+// own.
 template <int W, bool GS, bool ADJ, bool TL>
 __global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ order, uint32_t n_grid,
-                                                     int* err) {
+                                                     int* err, int any_gp) {
     step_body<W, GS, ADJ, TL, false>(segs, n_segs, order, n_grid, err);
-}
-
-template <int W, bool GS, bool ADJ, bool TL>
-__global__ __launch_bounds__(kWave) void step_kernel_gp(const Segment* __restrict__ segs, int n_segs,
-                                                        const uint32_t* __restrict__ order, uint32_t n_grid,
-                                                        int* err) {
-    step_body<W, GS, ADJ, TL, true>(segs, n_segs, order, n_grid, err);
+    if (any_gp) step_body<W, GS, ADJ, TL, true>(segs, n_segs, order, n_grid, err);
 }
 
 // Lowest cost over a component's units (out starts at INT_MAX).

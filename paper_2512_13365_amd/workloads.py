@@ -26,8 +26,8 @@ import numpy as np
 STRATEGIES = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
 
 # Default strategy weights of Sec. 3.5.1 scaled by 100 (gi 8, ga 4, gr 2,
-# wr 1, mix 0.1, gp 0.01); gp is not built, so its weight is 0 here.
-PAPER_WEIGHTS = {"gi": 800, "ga": 400, "gr": 200, "wr": 100, "mix": 10}
+# wr 1, mix 0.1, gp 0.01).
+PAPER_WEIGHTS = {"gi": 800, "ga": 400, "gr": 200, "wr": 100, "mix": 10, "gp": 1}
 
 
 def ternary_rows(rng: np.random.Generator, rows: int, cols: int, p: float,

@@ -267,8 +267,10 @@ def test_sharing_6x6x6_full_size_sampled(gpu, oracle):
         prog = cse.cse_get_programs(ctx, job, c, rs.n_proc, info[c][2])
         assert got["epoch"].max() > 0 and (got["steps"] > 0).all()
         best = int(np.argmin(got["cost"]))
+        gp_units = np.flatnonzero(got["strat"] == 6)
+        assert gp_units.size > 0
         sample = np.unique(np.concatenate([[0, best], rng.choice(rs.n_proc, 14, replace=False),
-                                           np.flatnonzero(got["epoch"] > 0)[:8]]))
+                                           np.flatnonzero(got["epoch"] > 0)[:8], gp_units[:4]]))
         for u in sample:
             F = check_program(A, prog[u, :got["steps"][u]], int(got["cost"][u]))
             assert is_terminal(F)
