@@ -805,3 +805,55 @@ def test_greedy_potential_layouts_sharing_driver(gpu, oracle):
     S = [workloads.random_system(71 + i, 30, 12, 0.3, 1, 8) for i in range(3)]
     check_driver(gpu, oracle, S, dict(seed=8, n_proc=48, weights=GP_W, proc0_greedy=True), "gp driver",
                  patience=2, max_iterations=6)
+
+
+def test_greedy_potential_mixed_batch_and_relaunch(gpu, oracle):
+    """One batched launch where some jobs weight gp and others do not (the
+    launch enters the gp body for every segment of its class), with sharing
+    on some, run twice (the relaunch reruns the whole batch); then a gp job
+    relaunched alone with a new seed: every unit equals its own job's oracle
+    run."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(45)
+    shapes = [(3, 3, 3), (2, 3, 4), (4, 3, 3), (3, 2, 4)]
+    weights = [{"gp": 1}, dict(ALL_W), dict(GP_W), {"gi": 1, "ga": 1}]
+    runs = []
+    for i, (n, m, p) in enumerate(shapes):
+        r = workloads.scheme_rank(n, m, p)
+        U, V, Wt = workloads.scheme_systems(rng, n, m, p, r, 0.25)
+        kw = dict(seed=20 + i, n_proc=40 + 8 * i, weights=weights[i], proc0_greedy=bool(i % 2))
+        if i >= 2:
+            kw.update(share_every=4, share_src_pm=100, share_dst_pm=300, share_max_rounds=8)
+        runs.append(((U, V, Wt), kw))
+    sids = [cse.cse_scheme_load(ctx, *S) for S, _ in runs]
+
+    def check(job, S, kw, sid, label):
+        info = cse.cse_scheme_info(ctx, sid)
+        for c, A in enumerate(S):
+            got = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+            got["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+            assert_same(got, oracle.run_pool(A, oracle.make_cfg(**kw), comp=c, n_threads=THREADS),
+                        f"{label} {A.shape} comp {c}")
+            if kw["weights"] == {"gp": 1}:
+                assert (got["strat"] == 6).all()
+
+    say(f"[gpu] gp mixed batch: {[S[0].shape for S, _ in runs]}")
+    jobs = cse.cse_launch_batch(ctx, sids, [cse.cse_run_cfg(**kw) for _, kw in runs], torch.cuda.current_stream())
+    for attempt in range(2):
+        if attempt:
+            cse.cse_relaunch(ctx, jobs[0], None, torch.cuda.current_stream())
+        for j in jobs:
+            cse.cse_wait(ctx, j)
+        for (S, kw), sid, job in zip(runs, sids, jobs):
+            check(job, S, kw, sid, f"gp batch run {attempt}")
+    for job in jobs:
+        cse.cse_job_release(ctx, job)
+    S, kw = runs[0]
+    job = cse.cse_launch(ctx, sids[0], cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    kw = dict(kw, seed=99)
+    cse.cse_relaunch(ctx, job, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+    cse.cse_wait(ctx, job)
+    check(job, S, kw, sids[0], "gp relaunch seed 99")
+    cse.cse_job_release(ctx, job)
+    for sid in sids:
+        cse.cse_scheme_free(ctx, sid)
