@@ -1094,9 +1094,10 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
 // score 2^16 (c - 1) + alpha_q N_new is maximal, ties to the first candidate.
 // One lane per candidate holds the trial column in registers; the loop over
 // the live list is uniform across the wave, so each column word is one
-// broadcast read.  The columns of a and b lose exactly the rewritten rows,
-// so they share none with the fresh column and are skipped.  *n_cols
-// receives m (n_live - 2), the columns counted.
+// broadcast read.  A column's pos and neg sets are disjoint, so each sign
+// pair's count is one popcount of a union.  The columns of a and b lose
+// exactly the rewritten rows, so they share none with the fresh column and
+// are skipped.  *n_cols receives m (n_live - 2), the columns counted.
 template <int W>
 __device__ int select_gp(const uint64_t* cand, int m, const uint64_t* colP, const uint64_t* colN,
                          const uint32_t* live, int n_live, uint32_t alpha_q, long long* n_cols) {
@@ -1125,8 +1126,8 @@ __device__ int select_gp(const uint64_t* cand, int m, const uint64_t* colP, cons
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const uint64_t Px = colP[(x - 1) * W + w], Nx = colN[(x - 1) * W + w];
-                same += popc64(Px & Pk[w]) + popc64(Nx & Nk[w]);
-                opp += popc64(Px & Nk[w]) + popc64(Nx & Pk[w]);
+                same += popc64((Px & Pk[w]) | (Nx & Nk[w]));
+                opp += popc64((Px & Nk[w]) | (Nx & Pk[w]));
             }
             n_new += (x == a || x == b) ? 0 : (same >= 2) + (opp >= 2);
         }
