@@ -166,6 +166,17 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
  * allocation in between; on the same stream the call does not block. */
 int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void* stream);
 
+/* Continue a cancelled job from where its units stopped: every unit keeps
+ * its program prefix, epoch and counters, and the draws of a unit depend
+ * only on its process, epoch and step (Sec. 3.5.1), so the final results
+ * equal those of a run that was never cancelled.  A job launched in a batch
+ * resumes its whole batch (units that finished are unchanged; on a finished
+ * job the call changes nothing).  CSE_EINVAL for server and driver jobs and
+ * for jobs with sharing rounds (their round schedule is not kept across a
+ * cancellation).  Waits for the earlier launch; allocates no device memory;
+ * on `stream` the call does not block. */
+int32_t cse_resume(cse_ctx* ctx, int32_t job_id, void* stream);
+
 /* The tool's outer iterations (Sec. 3.5.1, 3.5.2) and its convergence rule
  * (Sec. 4).  Zero-initialise and set the three fields. */
 typedef struct {
@@ -241,7 +252,7 @@ int32_t cse_wait(cse_ctx* ctx, int32_t job_id);
  * job leaves the queue; a running server job stops after the current round.
  * A job whose device work already completed is left as it is.  Returns
  * CSE_OK once the request is recorded; cse_wait then returns CSE_ECANCELED.
- * A relaunch clears the request.  This is the one call that may run on
+ * A relaunch or cse_resume clears the request.  This is the one call that may run on
  * another thread while cse_wait or cse_run_driver blocks on the same job
  * (a driver run stops after its current iteration); otherwise a context is
  * used by one thread at a time. */

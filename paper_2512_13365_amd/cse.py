@@ -31,7 +31,8 @@ STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4:
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
            "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_scheme_layout", "cse_autotune",
            "cse_launch", "cse_launch_batch",
-           "cse_relaunch", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results", "cse_get_programs",
+           "cse_relaunch", "cse_resume", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results",
+           "cse_get_programs",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
            "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best")
@@ -107,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     L.cse_launch_batch.restype = i32
     L.cse_relaunch.argtypes = [vp, i32, P(CseRunCfg), vp]
     L.cse_relaunch.restype = i32
+    L.cse_resume.argtypes = [vp, i32, vp]
+    L.cse_resume.restype = i32
     L.cse_poll.argtypes = [vp, i32, P(i32), P(i32)]
     L.cse_poll.restype = i32
     L.cse_cancel.argtypes = [vp, i32]
@@ -269,6 +272,10 @@ def cse_launch_batch(ctx, scheme_ids, cfgs, stream=None):
 def cse_relaunch(ctx, job_id, cfg: CseRunCfg | None = None, stream=None):
     _check(ctx, load_library().cse_relaunch(ctx, job_id, ctypes.byref(cfg) if cfg is not None else None,
                                             _stream_ptr(stream)))
+
+
+def cse_resume(ctx, job_id, stream=None):
+    _check(ctx, load_library().cse_resume(ctx, job_id, _stream_ptr(stream)))
 
 
 def cse_poll(ctx, job_id, best=False):

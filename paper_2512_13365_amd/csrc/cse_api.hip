@@ -1331,6 +1331,32 @@ int32_t cse_relaunch(cse_ctx* ctx, int32_t job_id, const cse_run_cfg* cfg, void*
     return CSE_OK;
 }
 
+int32_t cse_resume(cse_ctx* ctx, int32_t job_id, void* stream) {
+    if (!ctx) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (B->is_server) return fail(ctx, CSE_EINVAL, "server jobs cannot be resumed");
+    if (J->driver) return fail(ctx, CSE_EINVAL, "driver jobs cannot be resumed");
+    if (B->rounds) return fail(ctx, CSE_EINVAL, "jobs with sharing rounds cannot be resumed");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = wait_batch(ctx, *B);
+    if (rc) return rc;
+    for (int jid : B->jobs) {
+        JobRec& Jb = ctx->jobs[jid];
+        if (Jb.cancel_slot >= 0) __atomic_store_n(&ctx->h_cancel[Jb.cancel_slot], 0, __ATOMIC_SEQ_CST);
+        Jb.cancelled = false;
+    }
+    B->stream = (hipStream_t)stream;
+    B->finished = false;
+    // Unit state is kept: each active unit replays its prefix (or takes its
+    // HBM slot record) and continues with the draws of its epoch and step.
+    rc = run_batch(ctx, *B, false);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipEventRecord(B->ev_done, B->stream));
+    return CSE_OK;
+}
+
 int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done, int32_t best_cost[3]) {
     if (!ctx || !done) return CSE_EINVAL;
     JobRec* J = nullptr;

@@ -857,3 +857,56 @@ def test_greedy_potential_mixed_batch_and_relaunch(gpu, oracle):
     cse.cse_job_release(ctx, job)
     for sid in sids:
         cse.cse_scheme_free(ctx, sid)
+
+
+def test_cancel_then_resume_equals_uncancelled(gpu, oracle):
+    """Failure injection from the host: a job cancelled mid-run through its
+    host flag and resumed from its units' saved prefixes and epochs ends
+    exactly as a run that was never cancelled (every unit against an
+    uncancelled launch, sampled units against the oracle); server, driver
+    and sharing jobs are refused."""
+    cse, ctx, torch = gpu
+    A = workloads.random_system(4243, 42, 197, 0.2)
+    n = 2048
+    kw = dict(seed=12, n_proc=n, weights={"gi": 2, "ga": 1, "wr": 1})
+    sid = cse.cse_system_load(ctx, A)
+    info = cse.cse_scheme_info(ctx, sid)
+    st = torch.cuda.current_stream()
+
+    def results(job):
+        r = cse.cse_get_unit_results(ctx, job, 0, n)
+        r["prog"] = cse.cse_get_programs(ctx, job, 0, n, max(1, info[0][2]))
+        return r
+
+    say(f"[gpu] cancel + resume: 42x197, {n} units")
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), st)
+    cse.cse_cancel(ctx, job)
+    with pytest.raises(cse.CseError, match="CSE_ECANCELED"):
+        cse.cse_wait(ctx, job)
+    cut = results(job)
+    cse.cse_resume(ctx, job, st)
+    cse.cse_wait(ctx, job)
+    got = results(job)
+    ref_job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), st)
+    cse.cse_wait(ctx, ref_job)
+    ref = results(ref_job)
+    assert (cut["steps"] < ref["steps"]).sum() > n // 2, "the cancellation stopped few units"
+    assert_same(got, ref, "resumed vs uncancelled")
+    # Oracle samples among the cheaper ga and wr units (gi units of this
+    # system take the oracle seconds each); all units were compared above.
+    procs = [int(u) for u in np.flatnonzero(np.isin(got["strat"], (1, 2)))[::97][:8]]
+    orc = oracle.run_pool(A, oracle.make_cfg(**kw), procs=procs, n_threads=THREADS)
+    for i, u in enumerate(procs):
+        assert int(got["cost"][u]) == int(orc["cost"][i]) and (got["prog"][u] == orc["prog"][i]).all(), u
+    cse.cse_resume(ctx, job, st)  # a finished job: nothing changes
+    cse.cse_wait(ctx, job)
+    assert_same(results(job), ref, "resume of a finished job")
+    cse.cse_job_release(ctx, job)
+    cse.cse_job_release(ctx, ref_job)
+    share = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**dict(kw, n_proc=64, share_every=4, share_src_pm=100,
+                                                                share_dst_pm=300, share_max_rounds=4)), st)
+    cse.cse_wait(ctx, share)
+    with pytest.raises(cse.CseError, match="CSE_EINVAL"):
+        cse.cse_resume(ctx, share, st)
+    cse.cse_job_release(ctx, share)
+    cse.cse_scheme_free(ctx, sid)
