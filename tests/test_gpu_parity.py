@@ -910,3 +910,31 @@ def test_cancel_then_resume_equals_uncancelled(gpu, oracle):
         cse.cse_resume(ctx, share, st)
     cse.cse_job_release(ctx, share)
     cse.cse_scheme_free(ctx, sid)
+
+
+def test_units_independent_of_pool_size(gpu):
+    """Without sharing a unit's result depends only on its process index: a
+    pool of 384 processes reproduces the first 384 units of a pool of 1536
+    field by field (the premise of sharding a pool by process index)."""
+    cse, ctx, torch = gpu
+    wl = workloads.plain_4x4x4()
+    sc = wl.schemes[0]
+    sid = cse.cse_scheme_load(ctx, *sc.systems)
+    info = cse.cse_scheme_info(ctx, sid)
+    out = {}
+    for n in (1536, 384):
+        kw = dict(seed=21, n_proc=n, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+        say(f"[gpu] pool of {n}")
+        job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), torch.cuda.current_stream())
+        cse.cse_wait(ctx, job)
+        out[n] = []
+        for c in range(3):
+            r = cse.cse_get_unit_results(ctx, job, c, n)
+            r["prog"] = cse.cse_get_programs(ctx, job, c, n, max(1, info[c][2]))
+            out[n].append(r)
+        cse.cse_job_release(ctx, job)
+    for c in range(3):
+        big = {k: v[:384] for k, v in out[1536][c].items() if k != "finish"}
+        small = {k: v for k, v in out[384][c].items() if k != "finish"}
+        assert_same(small, big, f"pool size comp {c}")
+    cse.cse_scheme_free(ctx, sid)
