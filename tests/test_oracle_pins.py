@@ -387,8 +387,13 @@ def test_gp_matches_independent_potential(oracle):
         A = random_system(int(rng.integers(1 << 30)), rows, cols, float(rng.uniform(0.25, 0.6)))
         if not oracle.analyse(A):
             continue
+        m = sum(1 for c in pair_counts(A).values() if c >= 2)
+        live = int(np.count_nonzero(np.abs(A).sum(axis=0)))
         for alpha_q in (0, 1, 4096, 32767):
             got, n_cols = oracle.select_gp(A, alpha_q)
             assert got == _gp_reference(A, alpha_q), (case, alpha_q)
+            # The work tally counts every candidate against every live
+            # column other than its own two.
+            assert n_cols == m * max(0, live - 2), (case, n_cols)
         assert oracle.select_gp(A, 0)[0] == oracle.select_g(oracle.analyse(A))
 
