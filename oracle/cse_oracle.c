@@ -18,6 +18,9 @@
  *   - selection follows Sec. 3.4 (g, ga, wr, gr, gi, mix) literally, the
  *     Greedy-Intersections score (Sec. 3.4.2, H and I) summed over every
  *     other candidate with an explicit intersection test (the O(m^2) form);
+ *     Greedy-Potential (Sec. 2 and 3.4, described only in words there) does
+ *     each candidate's trial substitution on a copy of the system and counts
+ *     the fresh variable's pairs row by row;
  *   - substitution rewrites every row holding the pair or its negation
  *     (Algorithm 1, Substitution; Sec. 3.2.1).
  *
