@@ -108,3 +108,28 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_null_handles_rejected_before_any_device_call():
+    """Every entry point that takes a context or a server returns CSE_EINVAL
+    for a null one, before any HIP call (so this runs without a GPU), and the
+    error text of a null context is defined."""
+    from paper_2512_13365_amd import cse
+    if not os.path.exists(cse.LIB_PATH):
+        pytest.skip("libcse.so not built")
+    L = cse.load_library()
+    skip = {"cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_server_destroy"}
+    pointer_like = (ctypes.c_void_p, ctypes.c_char_p)
+    checked = 0
+    for name in cse.EXPORTS:
+        if name in skip:
+            continue
+        fn = getattr(L, name)
+        assert fn.argtypes, f"{name} has no declared argument types"
+        args = [0 if isinstance(t, type) and issubclass(t, ctypes._SimpleCData) and t not in pointer_like
+                else None for t in fn.argtypes]
+        assert fn(*args) == -1, name
+        checked += 1
+    assert checked == len(cse.EXPORTS) - len(skip)
+    assert L.cse_last_error(None) == b"null context"
+    L.cse_server_destroy(None)
