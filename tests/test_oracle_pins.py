@@ -376,6 +376,30 @@ def _gp_reference(A, alpha_q):
     return best
 
 
+def test_substitution_only_lowers_old_pair_counts():
+    """The premise of the Greedy-Potential reading: after any substitution
+    every pair of old variables occurs at most as often as before, so the new
+    substitution possibilities are exactly the fresh variable's pairs that
+    occur at least twice (brute force over every candidate)."""
+    rng = np.random.default_rng(23)
+    checked = 0
+    for case in range(10):
+        rows, cols = int(rng.integers(5, 20)), int(rng.integers(4, 10))
+        A = random_system(int(rng.integers(1 << 30)), rows, cols, float(rng.uniform(0.3, 0.6)))
+        before = pair_counts(A)
+        k = A.shape[1] + 1
+        for (a, b, sgn), c in before.items():
+            if c < 2:
+                continue
+            after = pair_counts(replay(A, [(a, b, sgn)])[0])
+            for key, c_new in after.items():
+                if k in key[:2]:
+                    continue
+                assert c_new <= before.get(key, 0), (case, (a, b, sgn), key)
+            checked += 1
+    assert checked > 50
+
+
 def test_gp_matches_independent_potential(oracle):
     """Greedy-Potential (Sec. 2, 3.4; the potential read as the number of the
     fresh variable's pairs that occur at least twice after the trial
