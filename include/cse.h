@@ -75,6 +75,8 @@ extern "C" {
 #define CSE_JOB_QUEUED  0   /* waiting for admission */
 #define CSE_JOB_RUNNING 1   /* admitted; advances one round per tick */
 #define CSE_JOB_DONE    2   /* every unit finished; results readable */
+#define CSE_JOB_FAILED  3   /* its device state could not be allocated at
+                               admission; no results; release it */
 
 typedef struct cse_ctx cse_ctx;
 typedef struct cse_server cse_server;
@@ -203,10 +205,11 @@ typedef struct {
  * last iteration, with executed and ops summed over all iterations, and
  * finish times counted from the start of iteration 0.  *iterations (may be
  * NULL) receives the number of iterations run.  *job_id is written as soon
- * as the job exists, before iteration 0 completes, so another thread may
- * read it and call cse_cancel, which stops the run after the current
- * iteration: CSE_ECANCELED, with the job and its bests kept.  Errors after
- * the job was created leave *job_id set. */
+ * as the job exists, before iteration 0 starts, so another thread may read
+ * it and call cse_cancel, which stops the run after the current iteration
+ * (its units stop early): CSE_ECANCELED, with the job and its bests kept.
+ * Errors after iteration 0 started leave *job_id set; if iteration 0 cannot
+ * be started the job is dropped and *job_id is reset to -1. */
 int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, const cse_driver_cfg* dcfg,
                        void* stream, int32_t* job_id, int32_t* iterations);
 
@@ -225,9 +228,10 @@ int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* tri
 int32_t cse_driver_totals(cse_ctx* ctx, int32_t job_id, int32_t* totals, uint64_t* elapsed_ns, int32_t cap,
                           int32_t* n);
 
-/* The component-wise hybrid over several finished jobs of schemes with the
- * same number of components (Sec. 4: the best U, V and W^T may come from
- * different runs or strategy mixes): for each component, the lowest cost
+/* The component-wise hybrid over several finished jobs of one scheme
+ * (Sec. 4: the best U, V and W^T may come from different runs or strategy
+ * mixes; jobs of different scheme ids give CSE_EINVAL): for each component,
+ * the lowest cost
  * over the jobs, the job and the process holding it (ties: the earlier job
  * in the list, then the lower process).  A driver job counts with its best
  * program so far (read it with cse_driver_best), any other job with its
@@ -303,11 +307,13 @@ int32_t cse_job_release(cse_ctx* ctx, int32_t job_id);
 int32_t cse_server_create(cse_ctx* ctx, uint64_t max_state_bytes, uint32_t round_steps, void* stream,
                           cse_server** out);
 /* Queue a job (not yet admitted).  CSE_ENOMEM if it alone exceeds the
- * server's budget. */
+ * server's budget or its unit state cannot fit a workgroup's LDS. */
 int32_t cse_server_submit(cse_server* s, int32_t scheme_id, const cse_run_cfg* cfg, int32_t* job_id);
 /* Admit what fits, run one round of every admitted job, retire finished
  * jobs; blocks until the round's device work is done.  Reports how many
- * jobs are running and queued afterwards. */
+ * jobs are running and queued afterwards.  A job whose device state cannot
+ * be allocated at admission leaves the queue as CSE_JOB_FAILED (reading its
+ * results gives CSE_ENOMEM) and the other jobs go on. */
 int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued);
 /* State (CSE_JOB_*) and host steady-clock times in ns of submission,
  * admission and completion (0 until reached). */

@@ -78,6 +78,14 @@ uint32_t oc_domain_word(uint32_t tag, uint32_t comp, uint32_t epoch, uint32_t st
     return (tag << 28) | ((comp & 3u) << 26) | ((epoch & 0x3FFu) << 16) | (step & 0xFFFFu);
 }
 
+/* A unit's epoch counts its restarts and can pass the 10 bits of word 1
+ * (sharing events and outer iterations add up).  So that no step or coin key
+ * is ever reused, the epoch's bits above the tenth go to the upper half of
+ * counter word 3 of those draws (whose lower half is 0 for a step draw and
+ * the coin block index, < 2^16, for a coin draw); epochs below 1024 leave
+ * word 3 as it was. */
+uint32_t oc_epoch_high(uint32_t epoch) { return (epoch >> 10) << 16; }
+
 static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4])
 {
     uint32_t ctr[4] = { c0, c1, c2, c3 };
@@ -238,8 +246,9 @@ static int pairs_intersect(uint32_t p, uint32_t q)
  * D_p = sum of c_q - 1 over disjoint q, X_p = the same over intersecting q
  * whose coin is 1.  The intersecting q of p are numbered j = 0, 1, ... in
  * canonical order; coin j is bit (j mod 128) of the 128-bit Philox block
- * counter (process, COIN|comp|epoch|step, key(p), j div 128), taking word
- * (j mod 128) div 32, bit j mod 32.  Ties go to the first in canonical order.
+ * counter (process, COIN|comp|epoch|step, key(p), j div 128 | high epoch
+ * bits), taking word (j mod 128) div 32, bit j mod 32.  Ties go to the first
+ * in canonical order.
  * n_int and n_blk (optional) receive sum_p |I(p)| and the Philox blocks
  * drawn, for the algorithmic work tally. */
 int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
@@ -257,7 +266,10 @@ int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
             if (q == p) continue;
             int64_t wq = C[q].c - 1;
             if (!pairs_intersect(C[p].key, C[q].key)) { D += wq; continue; }
-            if (j % 128 == 0) { draw(seed, proc, dw, C[p].key, (uint32_t)(j / 128), block); tot_blk++; }
+            if (j % 128 == 0) {
+                draw(seed, proc, dw, C[p].key, (uint32_t)(j / 128) | oc_epoch_high(epoch), block);
+                tot_blk++;
+            }
             int r = (int)(j % 128);
             if ((block[r / 32] >> (r % 32)) & 1u) X += wq;
             j++;
@@ -473,7 +485,8 @@ static void unit_run(const oc_problem* P, oc_unit* U, int budget)
         if (budget >= 0 && done >= budget) break;
 
         uint32_t u[4];
-        draw(cfg->seed, U->proc, oc_domain_word(TAG_STEP, P->comp, (uint32_t)U->epoch, (uint32_t)U->t), 0, 0, u);
+        draw(cfg->seed, U->proc, oc_domain_word(TAG_STEP, P->comp, (uint32_t)U->epoch, (uint32_t)U->t), 0,
+             oc_epoch_high((uint32_t)U->epoch), u);
         int strat = U->strat;
         if (strat == S_MIX) {
             static const int mix_map[4] = { S_GI, S_GA, S_GR, S_WR };

@@ -36,7 +36,7 @@ EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
            "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best")
-CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE = 0, 1, 2
+CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE, CSE_JOB_FAILED = 0, 1, 2, 3
 
 
 class CseError(RuntimeError):

@@ -185,6 +185,9 @@ struct cse_server {
 namespace {
 
 int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
+    // A failed runtime call (an allocation beyond device memory, say) stays
+    // HIP's last error until read; later launch checks must not see it.
+    if (code == CSE_EHIP) (void)hipGetLastError();
     if (ctx) {
         char buf[512];
         va_list ap;
@@ -387,6 +390,13 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     // Too large for four units per CU: state in HBM, and gi over ranges, which
     // touches far less of that state per step than building masks does.
     if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
+    // Every layout keeps the variable lists in LDS.
+    if (csek::list_bytes(n_vmax) > ctx->lds_max) {
+        const size_t need = csek::list_bytes(n_vmax);
+        free_component(c);
+        return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax, need,
+                    ctx->lds_max);
+    }
     *out = c;
     return CSE_OK;
 }
@@ -410,30 +420,6 @@ int validate_cfg(cse_ctx* ctx, const cse_run_cfg* cfg) {
     if (cfg->count_path > CSE_COUNT_MFMA) return fail(ctx, CSE_EINVAL, "unknown count path");
     if (cfg->reserved[0] || cfg->reserved[1] || cfg->reserved[2]) return fail(ctx, CSE_EINVAL, "reserved fields must be 0");
     return CSE_OK;
-}
-
-// Strategy of a process (the same per-process draw the kernel makes,
-// Sec. 3.5.1), used only to order the dispatch of units.
-uint32_t host_strategy(const cse_run_cfg& cfg, uint32_t proc) {
-    if (cfg.proc0_greedy && proc == 0 && cfg.iteration == 0) return CSE_STRAT_G;
-    uint32_t c0 = proc, c1 = (1u << 28) | ((cfg.iteration & 0x3FFu) << 16), c2 = 0, c3 = 0;
-    uint32_t k0 = (uint32_t)cfg.seed, k1 = (uint32_t)(cfg.seed >> 32);
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    uint64_t total = 0;
-    for (int i = 0; i < 7; ++i) total += cfg.weights[i];
-    const uint64_t x = ((uint64_t)c0 * total) >> 32;
-    uint64_t run = 0;
-    for (uint32_t i = 0; i < 7; ++i) {
-        run += cfg.weights[i];
-        if (run > x) return i;
-    }
-    return 0;
 }
 
 // Expected relative work of a unit: steps ~ n_fmax, each scanning the
@@ -691,7 +677,32 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
         B.groups.push_back(G);
     }
     // Longest expected work first, so that the long units do not form the
-    // tail of the launch (unit results do not depend on the order).
+    // tail of the launch (unit results do not depend on the order).  Each
+    // process's strategy comes from the kernels' own process draw.
+    std::map<int, std::vector<int32_t>> strat_of;
+    {
+        uint32_t nmax = 0;
+        for (int jid : B.jobs)
+            if (!ctx->jobs[jid].done) nmax = std::max(nmax, ctx->jobs[jid].cfg.n_proc);
+        int32_t* d_strat = nullptr;
+        if (nmax) HIP_TRY(ctx, hipMalloc((void**)&d_strat, sizeof(int32_t) * nmax));
+        hipError_t e = hipSuccess;
+        for (int jid : B.jobs) {
+            JobRec& J = ctx->jobs[jid];
+            if (J.done || e != hipSuccess) continue;
+            std::vector<int32_t>& st = strat_of[jid];
+            st.resize(J.cfg.n_proc);
+            hipLaunchKernelGGL(csek::proc_strategy_kernel, dim3((J.cfg.n_proc + 255) / 256), dim3(256), 0, B.stream,
+                               run_args(ctx, J), J.cfg.n_proc, d_strat);
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(st.data(), d_strat, sizeof(int32_t) * J.cfg.n_proc, hipMemcpyDeviceToHost,
+                                   B.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(B.stream);
+        }
+        if (d_strat) (void)hipFree(d_strat);
+        if (e != hipSuccess) return fail(ctx, CSE_EHIP, "process strategies: %s", hipGetErrorString(e));
+    }
     B.order.clear();
     for (LaunchGroup& G : B.groups) {
         G.order_begin = B.order.size();
@@ -701,8 +712,9 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             const csek::Segment& sg = B.segs[si];
             const JobRec* Jp = &ctx->jobs[B.seg_job[si]];
             const DevComp& dc = ctx->schemes[Jp->scheme].comp[sg.C.comp];
+            const std::vector<int32_t>& st = strat_of[B.seg_job[si]];
             for (uint32_t p = 0; p < sg.R.n_units; ++p)
-                key.emplace_back(-unit_cost(dc, host_strategy(Jp->cfg, p)), sg.unit_begin + p);
+                key.emplace_back(-unit_cost(dc, (uint32_t)st[p]), sg.unit_begin + p);
         }
         std::stable_sort(key.begin(), key.end(),
                          [](const std::pair<double, uint32_t>& a, const std::pair<double, uint32_t>& b) {
@@ -1014,6 +1026,8 @@ int readable(cse_ctx* ctx, int job_id, JobRec** J, int comp) {
     BatchRec* B = batch_of(ctx, job_id, J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (comp < -1 || comp >= (*J)->n_comp) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    if ((*J)->server && (*J)->state == CSE_JOB_FAILED)
+        return fail(ctx, CSE_ENOMEM, "job %d failed at admission; it has no results", job_id);
     if ((*J)->server && (*J)->state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "job %d is not done", job_id);
     if (!(*J)->allocated) return fail(ctx, CSE_EBUSY, "job %d has no results", job_id);
     return wait_batch(ctx, *B);
@@ -1252,10 +1266,13 @@ int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, vo
     return CSE_OK;
 }
 
-int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs, int32_t n,
-                         void* stream, int32_t* job_ids) {
-    if (!ctx || !scheme_ids || !cfgs || !job_ids || n < 1) return CSE_EINVAL;
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
+}  // extern "C"
+
+namespace {
+// A batch of new jobs with their device state, not yet started; on error
+// nothing is left behind.
+int create_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs, int32_t n, void* stream,
+                 int* bid_out) {
     for (int i = 0; i < n; ++i) {
         if (!ctx->schemes.count(scheme_ids[i])) return fail(ctx, CSE_ENOENT, "unknown scheme %d", scheme_ids[i]);
         int rc = validate_cfg(ctx, &cfgs[i]);
@@ -1274,10 +1291,22 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
         B.rounds |= shares(J.cfg);
         rc = alloc_job(ctx, J);
     }
-    if (rc == CSE_OK) {
-        B.finished = false;
-        rc = run_batch(ctx, B);
+    if (rc != CSE_OK) {
+        std::string keep = ctx->err;
+        drop_batch(ctx, bid);
+        ctx->err = keep;
+        return rc;
     }
+    *bid_out = bid;
+    return CSE_OK;
+}
+
+// Run a created batch on its stream (asynchronous unless it has rounds);
+// on error the batch is dropped.
+int start_batch(cse_ctx* ctx, int bid) {
+    BatchRec& B = ctx->batches[bid];
+    B.finished = false;
+    int rc = run_batch(ctx, B);
     if (rc == CSE_OK) {
         hipError_t e = hipEventRecord(B.ev_done, B.stream);
         if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
@@ -1288,9 +1317,24 @@ int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_
         B.finished = true;
         drop_batch(ctx, bid);
         ctx->err = keep;
-        return rc;
     }
-    for (int i = 0; i < n; ++i) job_ids[i] = B.jobs[i];
+    return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t cse_launch_batch(cse_ctx* ctx, const int32_t* scheme_ids, const cse_run_cfg* cfgs, int32_t n,
+                         void* stream, int32_t* job_ids) {
+    if (!ctx || !scheme_ids || !cfgs || !job_ids || n < 1) return CSE_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int bid = -1;
+    int rc = create_batch(ctx, scheme_ids, cfgs, n, stream, &bid);
+    if (rc) return rc;
+    std::vector<int> ids = ctx->batches[bid].jobs;
+    rc = start_batch(ctx, bid);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) job_ids[i] = ids[i];
     return CSE_OK;
 }
 
@@ -1365,7 +1409,7 @@ int32_t cse_poll(cse_ctx* ctx, int32_t job_id, int32_t* done, int32_t best_cost[
     if (best_cost) best_cost[0] = best_cost[1] = best_cost[2] = -1;
     *done = 0;
     if (J->server) {
-        if (J->state != CSE_JOB_DONE) return CSE_OK;
+        if (J->state != CSE_JOB_DONE && J->state != CSE_JOB_FAILED) return CSE_OK;
     } else if (!B->finished) {
         hipError_t e = hipEventQuery(B->ev_done);
         if (e == hipErrorNotReady) return CSE_OK;
@@ -1395,6 +1439,8 @@ int32_t cse_wait(cse_ctx* ctx, int32_t job_id) {
     JobRec* J = nullptr;
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (J->server && J->state == CSE_JOB_FAILED)
+        return fail(ctx, CSE_ENOMEM, "server job %d failed at admission", job_id);
     if (J->server && J->state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
     int rc = J->server ? CSE_OK : wait_batch(ctx, *B);
     if (rc) return rc;
@@ -1408,7 +1454,7 @@ int32_t cse_cancel(cse_ctx* ctx, int32_t job_id) {
     BatchRec* B = batch_of(ctx, job_id, &J);
     if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
     if (J->server) {
-        if (J->state == CSE_JOB_DONE) return CSE_OK;
+        if (J->state == CSE_JOB_DONE || J->state == CSE_JOB_FAILED) return CSE_OK;
         J->cancelled = true;
         if (J->state == CSE_JOB_QUEUED && B->owner) {
             auto& q = B->owner->queue;
@@ -1595,16 +1641,28 @@ int32_t cse_run_driver(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, 
         return fail(ctx, CSE_EINVAL, "driver configuration out of range");
     if (cfg->iteration != 0) return fail(ctx, CSE_EINVAL, "the driver starts at iteration 0");
     if (iterations) *iterations = 0;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
     const uint64_t t_start = now_ns();
-    int32_t jid = -1;
-    int rc = cse_launch(ctx, scheme_id, cfg, stream, &jid);  // iteration 0
+    int bid = -1;
+    int rc = create_batch(ctx, &scheme_id, cfg, 1, stream, &bid);
     if (rc) return rc;
-    *job_id = jid;
+    const int32_t jid = ctx->batches[bid].jobs[0];
+    {
+        // Marked as a running driver before its id is published, so a
+        // cse_cancel from another thread always takes the driver's path.
+        JobRec& J0 = ctx->jobs[jid];
+        J0.driver = true;
+        __atomic_store_n(&J0.driver_running, true, __ATOMIC_SEQ_CST);
+    }
+    __atomic_store_n(job_id, jid, __ATOMIC_SEQ_CST);
+    rc = start_batch(ctx, bid);  // iteration 0
+    if (rc) {
+        __atomic_store_n(job_id, -1, __ATOMIC_SEQ_CST);  // the job was dropped
+        return rc;
+    }
     JobRec& J = ctx->jobs[jid];
     BatchRec& B = ctx->batches[J.batch];
     const SchemeRec& sc = ctx->schemes[J.scheme];
-    J.driver = true;
-    __atomic_store_n(&J.driver_running, true, __ATOMIC_SEQ_CST);
     hipError_t e = hipMalloc((void**)&J.d_bestprog, 4 * best_offset(sc, sc.n_comp));
     if (e == hipSuccess) e = hipMalloc((void**)&J.d_key, sizeof(unsigned long long) * 3);
     if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipMalloc: %s", hipGetErrorString(e));
@@ -1679,13 +1737,16 @@ int32_t cse_driver_best(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t* tri
 int32_t cse_hybrid_best(cse_ctx* ctx, const int32_t* job_ids, int32_t n, int32_t best_cost[3], int32_t best_job[3],
                         int32_t best_proc[3]) {
     if (!ctx || !job_ids || n < 1 || !best_cost) return CSE_EINVAL;
-    int n_comp = -1;
+    int n_comp = -1, scheme = -1;
     for (int i = 0; i < n; ++i) {
         JobRec* J = nullptr;
         int rc = readable(ctx, job_ids[i], &J, -1);
         if (rc) return rc;
-        if (n_comp >= 0 && J->n_comp != n_comp)
-            return fail(ctx, CSE_EINVAL, "jobs have different numbers of components");
+        // Components of different runs combine only within one scheme.
+        if (scheme >= 0 && J->scheme != scheme)
+            return fail(ctx, CSE_EINVAL, "job %d reduces scheme %d, job %d scheme %d", job_ids[i], J->scheme,
+                        job_ids[0], scheme);
+        scheme = J->scheme;
         n_comp = J->n_comp;
     }
     for (int c = 0; c < 3; ++c) {
@@ -1810,6 +1871,13 @@ int32_t cse_server_submit(cse_server* s, int32_t scheme_id, const cse_run_cfg* c
     if (job_bytes(ctx, scheme_id, *cfg) > s->max_bytes)
         return fail(ctx, CSE_ENOMEM, "job needs %zu B, server budget %llu B", job_bytes(ctx, scheme_id, *cfg),
                     (unsigned long long)s->max_bytes);
+    // A job whose unit state cannot fit a workgroup's LDS in its layout
+    // would fail every round's launch: refused here.
+    const SchemeRec& sc = ctx->schemes[scheme_id];
+    for (int c = 0; c < sc.n_comp; ++c)
+        if (lds_bytes(sc.comp[c]) > ctx->lds_max)
+            return fail(ctx, CSE_ENOMEM, "component %d needs %zu B of LDS per unit (max %zu)", c,
+                        lds_bytes(sc.comp[c]), ctx->lds_max);
     const int jid = ctx->next_job++;
     JobRec& J = ctx->jobs[jid];
     J.scheme = scheme_id;
@@ -1835,7 +1903,14 @@ int32_t cse_server_tick(cse_server* s, int32_t* n_running, int32_t* n_queued) {
         const size_t need = job_bytes(ctx, J.scheme, J.cfg);
         if (s->used_bytes + need > s->max_bytes) break;
         int rc = alloc_job(ctx, J);
-        if (rc) { free_job_device(ctx, J); return rc; }
+        if (rc) {
+            // Retired as failed; the queue and the running jobs go on.
+            free_job_device(ctx, J);
+            J.state = CSE_JOB_FAILED;
+            J.t_done = now_ns();
+            s->queue.pop_front();
+            continue;
+        }
         s->used_bytes += J.bytes;
         J.budget = shares(J.cfg) ? (int)J.cfg.share_every : (int)s->round_steps;
         rc = init_job(ctx, J, B.stream);
@@ -1896,7 +1971,12 @@ int32_t cse_server_release(cse_server* s, int32_t job_id) {
     cse_ctx* ctx = s->ctx;
     auto it = ctx->jobs.find(job_id);
     if (it == ctx->jobs.end() || !it->second.server) return fail(ctx, CSE_ENOENT, "unknown server job %d", job_id);
-    if (it->second.state != CSE_JOB_DONE) return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
+    if (it->second.state != CSE_JOB_DONE && it->second.state != CSE_JOB_FAILED)
+        return fail(ctx, CSE_EBUSY, "server job %d is not done", job_id);
+    if (it->second.state == CSE_JOB_FAILED) {
+        ctx->jobs.erase(it);  // holds no device memory
+        return CSE_OK;
+    }
     s->used_bytes -= std::min<uint64_t>(s->used_bytes, it->second.bytes);
     return release_job(ctx, job_id);
 }

@@ -80,6 +80,11 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 __device__ __forceinline__ uint32_t domain(uint32_t tag, uint32_t comp, uint32_t epoch, uint32_t step) {
     return (tag << 28) | ((comp & 3u) << 26) | ((epoch & 0x3FFu) << 16) | (step & 0xFFFFu);
 }
+// A unit's epoch may pass the 10 bits of word 1 (restarts from sharing
+// events and outer iterations add up): its higher bits go to the upper half
+// of counter word 3 of the step and coin draws, whose lower half is 0 or the
+// coin block index (< 2^16), so no key is reused.
+__device__ __forceinline__ uint32_t epoch_high(uint32_t epoch) { return (epoch >> 10) << 16; }
 
 // floor(u * n / 2^32)
 __device__ __forceinline__ uint32_t scale_u32(uint32_t u, uint32_t n) {
@@ -789,25 +794,26 @@ __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const
 }
 
 // The coin stream of one candidate p: bit j is coin j, taken from Philox
-// block (proc, dw, key(p), j div 128), bit j mod 32 of its word
-// (j mod 128) / 32.  Holds the current block and, once needed, the next.
+// block (proc, dw, key(p), j div 128 | eh), bit j mod 32 of its word
+// (j mod 128) / 32, eh the high epoch bits.  Holds the current block and,
+// once needed, the next.
 struct CoinStream {
-    uint32_t proc, dw, kp, k0, k1;
+    uint32_t proc, dw, kp, eh, k0, k1;
     int cb;
     bool has_nb;
     uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
 
-    __device__ void init(uint32_t proc_, uint32_t dw_, uint32_t kp_, uint32_t k0_, uint32_t k1_) {
-        proc = proc_; dw = dw_; kp = kp_; k0 = k0_; k1 = k1_;
+    __device__ void init(uint32_t proc_, uint32_t dw_, uint32_t kp_, uint32_t eh_, uint32_t k0_, uint32_t k1_) {
+        proc = proc_; dw = dw_; kp = kp_; eh = eh_; k0 = k0_; k1 = k1_;
         cb = 0;
         has_nb = false;
-        const U4 x = philox10(proc, dw, kp, 0u, k0, k1);
+        const U4 x = philox10(proc, dw, kp, eh, k0, k1);
         a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
         b0 = b1 = b2 = b3 = 0u;
     }
     __device__ void next_block() {
         if (!has_nb) {
-            const U4 x = philox10(proc, dw, kp, (uint32_t)(cb + 1), k0, k1);
+            const U4 x = philox10(proc, dw, kp, (uint32_t)(cb + 1) | eh, k0, k1);
             b0 = x.x; b1 = x.y; b2 = x.z; b3 = x.w;
             has_nb = true;
         }
@@ -821,7 +827,7 @@ struct CoinStream {
                 next_block();
                 a0 = b0; a1 = b1; a2 = b2; a3 = b3;
             } else {
-                const U4 x = philox10(proc, dw, kp, (uint32_t)blk, k0, k1);
+                const U4 x = philox10(proc, dw, kp, (uint32_t)blk | eh, k0, k1);
                 a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
             }
             cb = blk;
@@ -878,7 +884,7 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, 
 // bit-planes; coins are consumed in that order, as in the other forms.
 __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
                                 const uint32_t* tp, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
-                                uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw,
+                                uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
                                 long long* n_int, long long* n_blk) {
     const int l = lane_id();
     const int T = total_profit(cand, m);
@@ -903,7 +909,7 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             const uint32_t q_lo = (uint32_t)(tprev ? p - 1 : p);
             const int n_ab = (tprev || tnext) ? 2 : 1;
             CoinStream co;
-            co.init(proc, dw, kp, k0, k1);
+            co.init(proc, dw, kp, eh, k0, k1);
             int I = 0, X = 0, j = 0;
             // 1. (x, a) and (x, b), x < a: every (x, a) entry, and the (x, b)
             //    entries before (a, b).
@@ -965,10 +971,11 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
 // with D_p the profit of the disjoint candidates and X_p that of the
 // intersecting candidates whose coin is 1.  The j-th intersecting candidate
 // of p in canonical order uses bit j mod 128 of Philox block
-// (proc, COIN|comp|epoch|step, key(p), j div 128).  This form visits every q
-// (the O(m^2) scan); it serves when the masks of the sparse form do not fit.
+// (proc, COIN|comp|epoch|step, key(p), j div 128 | eh), eh the high epoch
+// bits.  This form visits every q (the O(m^2) scan); it serves when the
+// masks of the sparse form do not fit.
 __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
-                               uint32_t proc, uint32_t dw, long long* n_int, long long* n_blk) {
+                               uint32_t proc, uint32_t dw, uint32_t eh, long long* n_int, long long* n_blk) {
     const int l = lane_id();
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
@@ -979,7 +986,7 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
         const int ap = key_a(kp), bp = key_b(kp);
-        U4 blk = philox10(proc, dw, kp, 0u, k0, k1);
+        U4 blk = philox10(proc, dw, kp, eh, k0, k1);
         int D = 0, X = 0, j = 0;
         for (int q = 0; q < m; ++q) {
             const uint64_t eq = cand[q];
@@ -990,7 +997,7 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
             if (!inter) {
                 D += wq;
             } else if (q != p) {
-                if (j != 0 && (j & 127) == 0) blk = philox10(proc, dw, kp, (uint32_t)(j >> 7), k0, k1);
+                if (j != 0 && (j & 127) == 0) blk = philox10(proc, dw, kp, (uint32_t)(j >> 7) | eh, k0, k1);
                 const int r = j & 127;
                 const uint32_t word = r < 32 ? blk.x : r < 64 ? blk.y : r < 96 ? blk.z : blk.w;
                 if ((word >> (r & 31)) & 1u) X += wq;
@@ -1019,7 +1026,7 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
 // intersecting candidates.  wt[q] = c_q - 1 is filled on the way.
 __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M64,
                                 uint16_t* wt, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc,
-                                uint32_t dw, long long* n_int, long long* n_blk) {
+                                uint32_t dw, uint32_t eh, long long* n_int, long long* n_blk) {
     const int l = lane_id();
     const int nw = (m + 31) >> 5;
     uint32_t* M = (uint32_t*)M64;
@@ -1050,7 +1057,7 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
         CoinStream co;
-        co.init(proc, dw, kp, k0, k1);
+        co.init(proc, dw, kp, eh, k0, k1);
         if (valid) {
             const uint32_t* Ma = M + vpos[key_a(kp) - 1] * nw;
             const uint32_t* Mb = M + vpos[key_b(kp) - 1] * nw;
@@ -1159,6 +1166,31 @@ __device__ __forceinline__ unsigned long long step_ops(int strat, int m, long lo
     return (unsigned long long)(98 + sel + 10 * w + 24 * w * (long long)(n_live - 1));
 }
 
+// Process draws (Sec. 3.5.1): one Philox block (process, PROC|0|iteration|0)
+// gives the strategy by the integer weights (word 0; process 0 of iteration
+// 0 runs g when proc0_greedy), alpha_q = u1 >> 17 in [0, 2^15) and
+// beta_q = 2^15 + (u2 >> 17) in [2^15, 2^16), shared by U, V and W^T.
+struct ProcDraw {
+    int strat;
+    uint32_t alpha_q, beta_q;
+};
+__device__ __forceinline__ ProcDraw process_draw(const RunArgs& R, uint32_t proc) {
+    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    const U4 pu = philox10(proc, domain(TAG_PROC, 0, R.iteration, 0), 0u, 0u, k0, k1);
+    ProcDraw d;
+    d.strat = (R.proc0_greedy && proc == 0 && R.iteration == 0) ? (int)S_G : weighted_pick(R.weights, N_STRAT, pu.x);
+    d.alpha_q = pu.y >> 17;
+    d.beta_q = 32768u + (pu.z >> 17);
+    return d;
+}
+
+// Strategy of every process of a run (the host orders the dispatch of units
+// by expected work with it).
+__global__ void proc_strategy_kernel(RunArgs R, uint32_t n, int32_t* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = process_draw(R, i).strat;
+}
+
 __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uint32_t g) {
     int lo = 0, hi = n_segs - 1;
     while (lo < hi) {
@@ -1227,12 +1259,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
 
     // Process draws (Sec. 3.5.1): strategy, alpha, beta.
-    const U4 pu = philox10(proc, domain(TAG_PROC, 0, R.iteration, 0), 0u, 0u, k0, k1);
-    int strat;
-    if (R.proc0_greedy && proc == 0 && R.iteration == 0) strat = S_G;
-    else strat = weighted_pick(R.weights, N_STRAT, pu.x);
-    const uint32_t alpha_q = pu.y >> 17;
-    const uint32_t beta_q = 32768u + (pu.z >> 17);
+    const ProcDraw pd = process_draw(R, proc);
+    const int strat = pd.strat;
+    const uint32_t alpha_q = pd.alpha_q;
+    const uint32_t beta_q = pd.beta_q;
     // Each unit runs in exactly one of the two kernels of its class.
     if ((strat == S_GP) != GP) return;
     // The second candidate ordering is kept only where gi walks ranges.
@@ -1347,7 +1377,8 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         // The step draw is consumed by ga, wr, gr and mix only.
         U4 su = {0u, 0u, 0u, 0u};
         if (!GP && strat != S_G && strat != S_GI)
-            su = philox10(proc, domain(TAG_STEP, C.comp, (uint32_t)epoch, (uint32_t)t), 0u, 0u, k0, k1);
+            su = philox10(proc, domain(TAG_STEP, C.comp, (uint32_t)epoch, (uint32_t)t), 0u, epoch_high(epoch), k0,
+                          k1);
         int s = strat;
         if (s == S_MIX) {
             const int mi = weighted_pick(R.mix_weights, 4, su.x);
@@ -1367,15 +1398,16 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             pick = select_wr(cand, m, su.z);
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
+            const uint32_t eh = epoch_high((uint32_t)epoch);
             if constexpr (ADJ) {
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tp, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tp, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
-                                        dw, &n_int, &n_blk);
+                                        dw, eh, &n_int, &n_blk);
             } else if (n_live * ((m + 31) / 32) <= 2 * C.m_words)
-                pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw,
+                pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw, eh,
                                         &n_int, &n_blk);
             else
-                pick = select_gi_dense(cand, m, alpha_q, beta_q, k0, k1, proc, dw, &n_int, &n_blk);
+                pick = select_gi_dense(cand, m, alpha_q, beta_q, k0, k1, proc, dw, eh, &n_int, &n_blk);
         }
         if (pick < 0 || pick >= m) { err_flags |= ERR_BAD_PICK; active = 0; break; }
 

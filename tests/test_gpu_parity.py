@@ -108,6 +108,20 @@ def test_ragged_shapes_all_strategies(gpu, oracle, rows, cols, p, hi):
     check_workload(gpu, oracle, [A], kw, f"system {rows}x{cols}")
 
 
+def test_mix_single_weight_is_that_strategy(gpu, oracle):
+    """mix (Sec. 3.4.3) with all weight on gi, ga, gr or wr in turn runs that
+    strategy on every step: each such pool equals the GPU pool of the plain
+    strategy and the oracle's."""
+    A = workloads.random_system(4412, 24, 12, 0.4)
+    base = dict(seed=5, n_proc=256)
+    for name, mixw in (("gi", (1, 0, 0, 0)), ("ga", (0, 1, 0, 0)), ("gr", (0, 0, 1, 0)), ("wr", (0, 0, 0, 1))):
+        plain = run_gpu(gpu, [A], dict(base, weights={name: 1}))[0]
+        got, _ = check_workload(gpu, oracle, [A], dict(base, weights={"mix": 1}, mix_weights=mixw),
+                                f"mix on {name}")
+        assert np.array_equal(got[0]["prog"], plain["prog"]), name
+        assert np.array_equal(got[0]["cost"], plain["cost"]), name
+
+
 def test_step_cap_and_seeds(gpu, oracle):
     A = workloads.random_system(77, 49, 16, 0.3, 1, 8)
     for seed, cap in ((0, 1), (1, 5), (2 ** 40 + 3, 17)):
@@ -286,6 +300,57 @@ def test_sharing_6x6x6_full_size_sampled(gpu, oracle):
         assert np.array_equal(ref["cost"], got["cost"][sample])
     cse.cse_job_release(ctx, job)
     cse.cse_scheme_free(ctx, sid)
+
+
+@pytest.mark.parametrize("rows,cols,p,hi,n_proc,every", [
+    (30, 12, 0.35, None, 4096, 2), (24, 12, 0.4, None, 16384, 3), (40, 16, 0.3, 8, 16384, 4),
+    (70, 14, 0.25, 8, 5000, 2)])
+def test_sharing_large_pools_every_unit(gpu, oracle, rows, cols, p, hi, n_proc, every):
+    """Sharing rounds (Sec. 3.5.2, top 1% -> 10%) on pools of thousands of
+    units, whose source ranking spans many 256-unit blocks and key tiles:
+    every unit, restarts included, equals the oracle's full pool run."""
+    A = workloads.random_system(rows * 100 + cols, rows, cols, p, 1, hi)
+    kw = dict(seed=7, n_proc=n_proc, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True,
+              share_every=every, share_src_pm=10, share_dst_pm=100, share_max_rounds=64)
+    got, _ = check_workload(gpu, oracle, [A], kw, f"share {rows}x{cols} pool {n_proc} every {every}")
+    assert (got[0]["epoch"] > 0).sum() > n_proc // 10
+
+
+def test_batch_large_pools_with_sharing(gpu, oracle):
+    """A batch whose pools hold 600-3000 units each, all sharing every 3
+    steps: every unit of every pool equals the oracle's run of its job."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(46)
+    shapes = [(2, 3, 2), (3, 3, 2), (2, 2, 3), (3, 2, 3), (2, 2, 2)]
+    ranks = [workloads.scheme_rank(*s) for s in shapes]
+    pools = workloads.pools_by_rank(ranks, 8192)
+    assert min(pools) > 256
+    runs = []
+    for i, ((n, m, p), r) in enumerate(zip(shapes, ranks)):
+        U, V, Wt = workloads.scheme_systems(rng, n, m, p, r, 0.3)
+        sc = workloads.Scheme(f"{n}x{m}x{p}:{r}", U, V, Wt)
+        kw = dict(seed=20 + i, n_proc=pools[i], weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True,
+                  share_every=3, share_src_pm=10, share_dst_pm=100, share_max_rounds=64)
+        runs.append((sc, kw))
+    sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc, _ in runs]
+    say(f"[gpu] batch with sharing, pools {pools}")
+    jobs = cse.cse_launch_batch(ctx, sids, [cse.cse_run_cfg(**kw) for _, kw in runs],
+                                torch.cuda.current_stream())
+    restarted = 0
+    for (sc, kw), sid, job in zip(runs, sids, jobs):
+        ocfg = oracle.make_cfg(**kw)
+        info = cse.cse_scheme_info(ctx, sid)
+        for c, A in enumerate(sc.systems):
+            got = cse.cse_get_unit_results(ctx, job, c, kw["n_proc"])
+            got["prog"] = cse.cse_get_programs(ctx, job, c, kw["n_proc"], max(1, info[c][2]))
+            ref = oracle.run_pool(A, ocfg, comp=c, n_threads=THREADS)
+            assert_same(got, ref, f"batch {sc.name} comp {c}")
+            restarted += int((got["epoch"] > 0).sum())
+    assert restarted > 0
+    for job in jobs:
+        cse.cse_job_release(ctx, job)
+    for sid in sids:
+        cse.cse_scheme_free(ctx, sid)
 
 
 def test_server_continuous_batching(gpu, oracle):
@@ -594,6 +659,17 @@ def test_driver_with_sharing_rounds_and_layouts(gpu, oracle):
     check_driver(gpu, oracle, S, kw, "4x4x4 sharing hbm+range", layouts=[3, 1, 2], patience=2, max_iterations=5)
 
 
+def test_driver_epochs_past_ten_bits(gpu, oracle):
+    """Sharing after every step with every active non-source unit a target,
+    over many outer iterations: unit epochs pass 1023, where the step and
+    coin draws carry the epoch's high bits.  The GPU equals the oracle."""
+    A = workloads.random_system(4321, 30, 12, 0.35)
+    kw = dict(seed=9, n_proc=48, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True,
+              share_every=1, share_src_pm=25, share_dst_pm=1000, share_max_rounds=20)
+    got = check_driver(gpu, oracle, [A], kw, "epochs past 1023", patience=1000, max_iterations=60)
+    assert int(got["last"][0]["epoch"].min()) > 1100
+
+
 def test_driver_tiny_and_edge_settings(gpu, oracle):
     """gi only on the tiny system; every process restarts from a prefix;
     no restarts; a single iteration."""
@@ -710,37 +786,43 @@ def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
         assert_same(got, ref, f"resume {rows}x{cols} layout {lay}")
 
 
-def test_hybrid_best_over_jobs(gpu):
+def test_hybrid_best_over_jobs(gpu, oracle):
     """Component-wise hybrid (Sec. 4): per component, the lowest cost over a
     gi-only job, a ga-only job and a driver job, with the job and process that
-    hold it; each chosen program re-expands exactly."""
+    hold it (ties: the earlier job, then the lower process).  The expected
+    hybrid is computed from the oracle's runs of the same jobs; each chosen
+    program re-expands exactly.  Jobs of different schemes are refused."""
     cse, ctx, torch = gpu
     wl = workloads.plain_4x4x4(n_proc=256)
     S = wl.schemes[0].systems
     sid = cse.cse_scheme_load(ctx, *S)
     st = torch.cuda.current_stream()
-    jobs = []
+    jobs, ref_best = [], []
     for w in ({"gi": 1}, {"ga": 1}):
-        j = cse.cse_launch(ctx, sid, cse.cse_run_cfg(seed=4, n_proc=256, weights=w), st)
+        kw = dict(seed=4, n_proc=256, weights=w)
+        j = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), st)
         cse.cse_wait(ctx, j)
         jobs.append(j)
-    dj, _ = cse.cse_run_driver(ctx, sid, cse.cse_run_cfg(seed=5, n_proc=256, weights=dict(workloads.PAPER_WEIGHTS)),
-                               st, patience=2, max_iterations=6)
+        per_comp = []
+        for c, A in enumerate(S):
+            r = oracle.run_pool(A, oracle.make_cfg(**kw), comp=c, n_threads=THREADS)
+            u = int(np.lexsort((np.arange(256), r["cost"]))[0])
+            per_comp.append((int(r["cost"][u]), u))
+        ref_best.append(per_comp)
+    dkw = dict(seed=5, n_proc=256, weights=dict(workloads.PAPER_WEIGHTS))
+    dj, _ = cse.cse_run_driver(ctx, sid, cse.cse_run_cfg(**dkw), st, patience=2, max_iterations=6)
     jobs.append(dj)
+    dref = oracle.run_driver(S, oracle.make_cfg(**dkw), patience=2, max_iterations=6, n_threads=THREADS)
+    ref_best.append([(b["cost"], b["proc"]) for b in dref["best"]])
     hyb = cse.cse_hybrid_best(ctx, jobs)
     assert len(hyb) == 3
     for c in range(3):
-        per_job = []
-        for j in jobs:
-            if j == dj:
-                b = cse.cse_driver_best(ctx, j, c)
-                per_job.append((b["cost"], j, b["proc"]))
-            else:
-                cost = cse.cse_get_unit_results(ctx, j, c, 256)["cost"]
-                u = int(np.argmin(cost))
-                per_job.append((int(cost[u]), j, u))
-        want = min(per_job, key=lambda x: x[0])
-        assert hyb[c] == want, (c, hyb[c], per_job)
+        want = None
+        for j, per_comp in zip(jobs, ref_best):
+            cost, u = per_comp[c]
+            if want is None or cost < want[0]:
+                want = (cost, j, u)
+        assert hyb[c] == want, (c, hyb[c], ref_best)
         cost, j, u = hyb[c]
         if j == dj:
             prog = cse.cse_driver_best(ctx, j, c)["prog"]
@@ -748,8 +830,60 @@ def test_hybrid_best_over_jobs(gpu):
             prog, pc = cse.cse_get_program(ctx, j, c, proc=u)
             assert pc == cost
         check_program(S[c], prog, cost)
+    # A job of another scheme (even with the same shapes) is refused.
+    sid2 = cse.cse_scheme_load(ctx, *S)
+    j2 = cse.cse_launch(ctx, sid2, cse.cse_run_cfg(seed=4, n_proc=64, weights={"gi": 1}), st)
+    cse.cse_wait(ctx, j2)
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_hybrid_best(ctx, [jobs[0], j2])
+    assert e.value.status == -1
+    cse.cse_job_release(ctx, j2)
+    cse.cse_scheme_free(ctx, sid2)
     for j in jobs:
         cse.cse_job_release(ctx, j)
+    cse.cse_scheme_free(ctx, sid)
+
+
+def test_refusals_keep_other_work_going(gpu, oracle):
+    """A system whose variable lists alone exceed a workgroup's LDS is refused
+    at load (CSE_ENOMEM).  A served job whose device state cannot be
+    allocated at admission (far beyond HBM) leaves the queue as failed, and
+    the jobs before and after it run to the oracle's results."""
+    cse, ctx, torch = gpu
+    rng = np.random.default_rng(3)
+    big = np.zeros((512, 10000), np.int8)
+    for i in range(512):
+        big[i, rng.choice(10000, 45, replace=False)] = rng.choice(np.array([-1, 1], np.int8), 45)
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_system_load(ctx, big)
+    assert e.value.status == -2
+    huge_sys = workloads.random_system(42 + 7 * 197, 42, 197, 0.2)
+    small = workloads.random_system(4321, 30, 12, 0.35)
+    hid = cse.cse_system_load(ctx, huge_sys)
+    sid = cse.cse_system_load(ctx, small)
+    srv = cse.cse_server_create(ctx, max_state_bytes=1 << 52, round_steps=4, stream=torch.cuda.current_stream())
+    kws = [dict(seed=1, n_proc=64, weights=dict(ALL_W)), dict(seed=2, n_proc=96, weights=dict(ALL_W))]
+    say("[gpu] server with a job far beyond device memory")
+    ja = cse.cse_server_submit(srv, sid, cse.cse_run_cfg(**kws[0]))
+    jh = cse.cse_server_submit(srv, hid, cse.cse_run_cfg(seed=3, n_proc=1 << 24, weights={"gi": 1}))
+    jb = cse.cse_server_submit(srv, sid, cse.cse_run_cfg(**kws[1]))
+    for _ in range(500):
+        running, queued = cse.cse_server_tick(srv)
+        if running == 0 and queued == 0:
+            break
+    assert cse.cse_server_job_info(srv, jh)[0] == cse.CSE_JOB_FAILED
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_get_unit_results(ctx, jh, 0, 1)
+    assert e.value.status == -2
+    for j, kw in ((ja, kws[0]), (jb, kws[1])):
+        assert cse.cse_server_job_info(srv, j)[0] == cse.CSE_JOB_DONE
+        got = cse.cse_get_unit_results(ctx, j, 0, kw["n_proc"])
+        got["prog"] = cse.cse_get_programs(ctx, j, 0, kw["n_proc"], max(1, oracle.bounds(small)[0]))
+        assert_same(got, oracle.run_pool(small, oracle.make_cfg(**kw), n_threads=THREADS), "served beside a failure")
+        cse.cse_server_release(srv, j)
+    cse.cse_server_release(srv, jh)
+    cse.cse_server_destroy(srv)
+    cse.cse_scheme_free(ctx, hid)
     cse.cse_scheme_free(ctx, sid)
 
 

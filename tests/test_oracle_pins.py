@@ -312,6 +312,108 @@ def test_mix_and_gr_degenerate_weights(oracle):
     assert np.array_equal(wr["prog"], gr0["prog"])
 
 
+@pytest.mark.parametrize("name,mixw", [("gi", (1, 0, 0, 0)), ("ga", (0, 1, 0, 0)),
+                                       ("gr", (0, 0, 1, 0)), ("wr", (0, 0, 0, 1))])
+def test_mix_single_weight_is_that_strategy(oracle, name, mixw):
+    """mix (Sec. 3.4.3) draws one of gi, ga, gr, wr per step by the weights
+    8, 4, 2, 1; with all weight on one of them every step is that strategy,
+    so the whole pool equals a pool of that strategy.  The four strategies
+    give different pools here, so a permuted map fails one of the cases."""
+    A = random_system(44, 24, 12, 0.4)
+    base = dict(seed=5, n_proc=48)
+    pools = {s: oracle.run_pool(A, oracle.make_cfg(weights={s: 1}, **base))["prog"]
+             for s in ("gi", "ga", "gr", "wr")}
+    names = list(pools)
+    for i in range(4):
+        for j in range(i + 1, 4):
+            assert not np.array_equal(pools[names[i]], pools[names[j]]), (names[i], names[j])
+    mix = oracle.run_pool(A, oracle.make_cfg(weights={"mix": 1}, mix_weights=mixw, **base))
+    assert np.array_equal(mix["prog"], pools[name])
+
+
+def test_gr_exploit_rate(oracle):
+    """Greedy-Random (Sec. 3.4.1) takes the ga branch with probability p
+    (0.75 here) and wr otherwise.  On a system whose candidates are one pair
+    of count 3 and K disjoint pairs of count 2, ga always takes the count-3
+    pair and wr takes it with probability 2 / (2 + K), so the first pick of
+    a gr process is that pair with probability p + (1 - p) 2 / (2 + K).
+    Estimated over 6000 processes and compared with a 4.5-sigma binomial
+    band; p = 0.5 or a reversed comparison lie far outside it."""
+    K = 30
+    rows = []
+    n_x = 2 + 2 * K
+    for _ in range(3):
+        r = np.zeros(n_x, np.int8); r[0] = 1; r[1] = 1; rows.append(r)
+    for i in range(K):
+        for _ in range(2):
+            r = np.zeros(n_x, np.int8); r[2 + 2 * i] = 1; r[3 + 2 * i] = -1; rows.append(r)
+    A = np.array(rows, np.int8)
+    n = 6000
+    r = oracle.run_pool(A, oracle.make_cfg(seed=17, n_proc=n, weights={"gr": 1}, step_cap=1), n_threads=8)
+    assert np.all(r["steps"] == 1)
+    hit = int(np.sum((r["prog"][:, 0, 0] == 1) & (r["prog"][:, 0, 1] == 2)))
+    q = 2.0 / (2 + K)
+    for p, inside in ((0.75, True), (0.5, False), (0.25, False)):
+        f = p + (1 - p) * q
+        z = abs(hit - n * f) / np.sqrt(n * f * (1 - f))
+        assert (z < 4.5) == inside, (p, hit, z)
+
+
+def test_gi_work_tally_independent_count(oracle):
+    """The gi work tally (n_int = sum over p of the candidates intersecting p,
+    n_blk = sum over p of ceil(n_int(p) / 128) coin blocks) against a count
+    written here from the intersection rule (shared variable index, p itself
+    excluded), on candidate sets large enough that some p exceed 128."""
+    rng = np.random.default_rng(15)
+    big = 0
+    for trial in range(40):
+        n_v = int(rng.integers(4, 40))
+        m = int(rng.integers(1, min(400, n_v * (n_v - 1))))
+        cands = _random_cands(rng, m, n_v)
+        if trial % 4 == 0:
+            # hub variables: every pair (h, x, +-) of two hubs h, so the
+            # candidates holding a hub intersect well over 128 others
+            n_v = int(rng.integers(70, 90))
+            hub = {(h, x, s) for h in (1, 2) for x in range(h + 1, n_v + 1) for s in (1, -1)}
+            rest = {(a, b, s) for a, b, s, _ in _random_cands(rng, 150, n_v)}
+            cands = [(a, b, s, int(rng.integers(2, 9))) for a, b, s in hub | rest]
+            cands.sort(key=lambda t: (t[0], t[1], t[2] < 0))
+        n_int = n_blk = 0
+        for p, (pa, pb, _, _) in enumerate(cands):
+            k = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and {pa, pb} & {qa, qb})
+            n_int += k
+            n_blk += -(-k // 128)
+            big += k > 128
+        _, got_int, got_blk = oracle.select_gi(cands, int(rng.integers(0, 32768)), 40000, seed=trial)
+        assert (got_int, got_blk) == (n_int, n_blk)
+    assert big > 0
+
+
+def test_epochs_never_reuse_draws(oracle):
+    """A unit's epoch counts its restarts and may pass 1023; its step and
+    coin draws must then still be new (no random key is reused, so a unit
+    restarted 1024 times does not repeat the choices of its first epochs).
+    Units started at epoch e, e + 1024 and e + 2048 from the input choose
+    differently; epochs below 1024 keep the draws they always had."""
+    A = random_system(45, 30, 12, 0.4)
+    n = 64
+    cfg = oracle.make_cfg(seed=11, n_proc=n, weights={"gi": 2, "ga": 1, "wr": 1, "mix": 1})
+    cap = max(1, oracle.bounds(A)[0])
+    zero = np.zeros((n, cap, 3), np.int32)
+    runs = {}
+    for e in (3, 3 + 1024, 3 + 2048):
+        runs[e] = oracle.run_pool(A, cfg, init_prog=zero, init_len=np.zeros(n, np.int32),
+                                  init_epoch=np.full(n, e, np.int32))
+    for e1, e2 in ((3, 1027), (3, 2051), (1027, 2051)):
+        differ = sum(not np.array_equal(runs[e1]["prog"][u], runs[e2]["prog"][u]) for u in range(n))
+        assert differ > n // 2, (e1, e2, differ)
+    # Epoch 0 from an explicit start equals the plain pool run.
+    plain = oracle.run_pool(A, cfg)
+    again = oracle.run_pool(A, cfg, init_prog=zero, init_len=np.zeros(n, np.int32),
+                            init_epoch=np.zeros(n, np.int32))
+    assert np.array_equal(plain["prog"], again["prog"])
+
+
 def test_step_cap(oracle):
     A = random_system(43, 30, 10, 0.5)
     r = oracle.run_pool(A, oracle.make_cfg(n_proc=8, weights={"gi": 1, "wr": 1}, step_cap=3))
