@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the randomized-CSE hot path on one MI355X.
 
-A step is one whole job: every process of every component of the workload
-(U, V and W^T) reduced until no pair repeats (Algorithm 1 with the
-strategies of Sec. 3.4).  The default workload is the synthetic 4x4x4
-rank-49 system (U, V 49x16, W^T 16x49, 4096 processes, gi / ga / wr in equal
-shares).  Inputs are resident in HBM before the timed region; the timed
-region is K back-to-back relaunches of the job on one stream, bracketed by
-device synchronisation, timed with HIP events on that stream.
+A step is one pass of the whole path over the default workload, 32
+synthetic schemes of uneven shape in one batch (65536 processes, pools
+proportional to rank, sharing rounds): load every scheme from device-resident
+int8 tensors (validation and input analysis on the device), run all of them
+in one batched launch (each unit reduces U, V or W^T by Algorithm 1 with the
+strategies of Sec. 3.4, the pools sharing every 32 steps as in Sec. 3.5.2),
+read every unit's results.  K passes are timed back to back, bracketed by
+device synchronisation.  The same passes run plain (one launch per scheme,
+one after another) for the batched-vs-plain comparison.
 
-Prints one JSON line: substitution steps per second (all units), time to
-the best addition count, the roofline position of the step kernel, the CPU
-oracle timed on the host cores, and batched vs plain launches of 32 uneven
-schemes.  Other workloads (--workload 6x6x6 | batch | serve) print their own
-line.
+Prints one JSON line: substitution steps per second over all units, time to
+the best addition count per scheme, the roofline position of the step-kernel
+class with the most device time (HIP events around each of its launches),
+the CPU oracle timed on the host cores over a sample of units, and, as extra
+keys, the 4x4x4, 6x6x6 and serving workloads.  --workload 4x4x4 | 6x6x6 |
+serve | driver prints that workload's own line instead.
 """
 import argparse
 import json
@@ -31,16 +34,19 @@ METRIC = "CSE substitution steps/s and time-to-best additions; batched vs plain,
 PEAK_ALU_OPS = 256 * 4 * 16 * 2.4e9
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
-    kernel sources changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary profiles/step_kernel_<workload>_hbm_counters.txt
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when there
+    is none for this kernel or the kernel sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "step_kernel_plain_4x4x4_hbm_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_hbm_counters.txt")
     try:
         with open(path) as f:
             fields = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l)
     except OSError:
+        return None
+    if fields.get("kernel", "").strip() != kernel:
         return None
     h = hashlib.sha256()
     for name in ("cse_kernels.hpp", "cse_api.hip"):
@@ -154,7 +160,8 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
                         "note": "job plus host copy of all unit results and programs"},
         roofline={"kernel": "step_kernel<1, false, false, false>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
-                  "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
+                  "traffic": measured_traffic("step_kernel<1, false, false, false>", "plain_4x4x4"),
+                  "traffic_unit": "HBM bytes per launch",
                   "algorithmic_ops_per_launch": ops / launches,
                   "avg_launch_ms": avg_launch * 1e3})
     cse.cse_job_release(ctx, job)
@@ -171,68 +178,185 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
     return out
 
 
-def batch_vs_plain(cse, workloads, torch, ctx, stream, reps=1, autotune=False):
-    """32 uneven schemes: one batched launch vs 32 sequential plain launches,
-    same pools and seeds (so the same results).  With autotune, every
-    component first gets its fastest layout from cse_autotune (timed apart)."""
+BATCH_NAME = ("batch-32-uneven: 32 schemes, (n,m,p) uniform in {2..7}^3, r = round((nmp)^0.93), U r x nm, "
+              "V r x mp, W^T np x r, ternary p = 0.2; pools proportional to r summing to 65536 processes; paper "
+              "weights, proc0 = g; sharing every 32 steps, 1% -> 10%; inputs resident in HBM, each pass loads "
+              "(validates and analyses) all 32 schemes on the device, runs them and reads every unit's results")
+
+
+def kernel_name(W, layout):
+    gs, adj, tl = bool(layout & 1), bool(layout & 2), bool(layout & 4)
+    b = lambda x: "true" if x else "false"
+    return f"step_kernel<{W}, {b(gs)}, {b(adj)}, {b(tl)}>"
+
+
+def scheme_pass(cse, ctx, stream, dev, cfgs, batched):
+    """One pass over the batch: load every scheme from its device tensors,
+    run the jobs (one batched launch, or one plain launch after another),
+    read every unit's results, release.  Returns per-pass figures."""
+    import numpy as np
+    t0 = time.perf_counter()
+    out = {"subs": 0, "best": [], "ttb_s": [], "per_class_ops": {}, "classes": {}}
+    pending = []
+
+    def collect(j, sid, n, t_start):
+        best_total, ttb = 0, 0.0
+        _, hz = cse.cse_job_timing(ctx, j)
+        for c in range(3):
+            r = cse.cse_get_unit_results(ctx, j, c, n)
+            out["subs"] += int(r["executed"].sum())
+            b = int(r["cost"].min())
+            best_total += b
+            ttb = max(ttb, min(int(f) for cc, f in zip(r["cost"], r["finish"]) if cc == b) / hz)
+            rows = cse.cse_scheme_info(ctx, sid)[c][0]
+            key = ((rows + 63) // 64, cse.cse_scheme_layout(ctx, sid, c))
+            out["per_class_ops"][key] = out["per_class_ops"].get(key, 0) + int(r["ops"].sum())
+        out["best"].append(best_total)
+        out["ttb_s"].append(t_start + ttb)
+
+    if batched:
+        sids = [cse.cse_scheme_load_device(ctx, *d, stream=stream) for d in dev]
+        t_launch = time.perf_counter() - t0
+        jobs = cse.cse_launch_batch(ctx, sids, cfgs, stream)
+        for j in jobs:
+            cse.cse_wait(ctx, j)
+        out["kernel_times"] = cse.cse_kernel_times(ctx, jobs[0], reset=True)
+        for j, sid, cfg in zip(jobs, sids, cfgs):
+            collect(j, sid, cfg.n_proc, t_launch)
+        for j in jobs:
+            cse.cse_job_release(ctx, j)
+        for sid in sids:
+            cse.cse_scheme_free(ctx, sid)
+    else:
+        for d, cfg in zip(dev, cfgs):
+            t_start = time.perf_counter() - t0
+            sid = cse.cse_scheme_load_device(ctx, *d, stream=stream)
+            j = cse.cse_launch(ctx, sid, cfg, stream)
+            cse.cse_wait(ctx, j)
+            collect(j, sid, cfg.n_proc, t_start)
+            cse.cse_job_release(ctx, j)
+            cse.cse_scheme_free(ctx, sid)
+    torch_sync()
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def cpu_baseline_batch(wl, n_threads, budget_s=10.0, seed=7):
+    """The oracle on a seeded uniform sample of the batch's units (scheme,
+    component, process), each reduced from its input to the end without the
+    sharing rounds (which need the whole pool); units are started until
+    budget_s has passed, then the running ones finish."""
+    import numpy as np
+    from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import cse_oracle
+    rng = np.random.default_rng(seed)
+    offs = np.cumsum([0] + [3 * rs.n_proc for rs in wl.runs])
+    cfgs = [cse_oracle.make_cfg(**dict(rs.as_kwargs(), share_every=0)) for rs in wl.runs]
+
+    def one(u):
+        i = int(np.searchsorted(offs, u, side="right") - 1)
+        c, p = divmod(int(u - offs[i]), wl.runs[i].n_proc)
+        r = cse_oracle.run_pool(wl.schemes[i].systems[c], cfgs[i], comp=c, procs=[p])
+        return int(r["executed"][0])
+
+    steps, units = 0, 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(n_threads) as ex:
+        live = set()
+        for u in rng.permutation(int(offs[-1])):
+            if time.perf_counter() - t0 >= budget_s:
+                break
+            if len(live) >= n_threads:
+                done, live = wait(live, return_when=FIRST_COMPLETED)
+                for f in done:
+                    steps += f.result()
+                    units += 1
+            live.add(ex.submit(one, u))
+        for f in live:
+            steps += f.result()
+            units += 1
+    return steps, time.perf_counter() - t0, units
+
+
+def run_batch(args, cse, workloads, torch, ctx, stream):
+    import numpy as np
     wl = workloads.batch_uneven()
-    sids = [cse.cse_scheme_load(ctx, *sc.systems) for sc in wl.schemes]
+    dev = [tuple(torch.from_numpy(A).to("cuda") for A in sc.systems) for sc in wl.schemes]
     cfgs = [cse.cse_run_cfg(**rs.as_kwargs()) for rs in wl.runs]
-    n_procs = [rs.n_proc for rs in wl.runs]
-    stats = {}
-    tuning = None
-    if autotune:
-        t0 = time.perf_counter()
-        chosen = [cse.cse_autotune(ctx, s, c, stream) for s, c in zip(sids, cfgs)]
-        tuning = {"seconds": time.perf_counter() - t0,
-                  "layouts": [[x for x in ch if x >= 0] for ch in chosen]}
-        log(f"[bench] autotune: {tuning['seconds']:.1f} s")
-    for mode in ("batched", "plain"):
-        best_t = None
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if mode == "batched":
-                jobs = cse.cse_launch_batch(ctx, sids, cfgs, stream)
-                for j in jobs:
-                    cse.cse_wait(ctx, j)
-                starts = [0.0] * len(jobs)
-            else:
-                jobs, starts = [], []
-                for s, c in zip(sids, cfgs):
-                    starts.append(time.perf_counter() - t0)
-                    j = cse.cse_launch(ctx, s, c, stream)
-                    cse.cse_wait(ctx, j)
-                    jobs.append(j)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            steps, bests, ttbs = 0, [], []
-            for j, n, st in zip(jobs, n_procs, starts):
-                res = job_results(cse, ctx, j, n)
-                _, hz = cse.cse_job_timing(ctx, j)
-                steps += sum(int(r["executed"].sum()) for r in res)
-                tb = time_to_best(res, hz)
-                bests.append(sum(b for b, _ in tb))
-                ttbs.append(st + max(t for _, t in tb))
-            for j in jobs:
-                cse.cse_job_release(ctx, j)
-            if best_t is None or dt < best_t:
-                best_t = dt
-                stats[mode] = {"seconds": dt, "substitutions": steps, "steps_per_s": steps / dt,
-                               "mean_time_to_best_ms": 1e3 * sum(ttbs) / len(ttbs),
-                               "max_time_to_best_ms": 1e3 * max(ttbs), "best_additions": bests}
-        log(f"[bench] batch-32 {mode}: {stats[mode]['seconds'] * 1e3:.1f} ms, "
-            f"{stats[mode]['steps_per_s'] / 1e6:.1f} M steps/s")
-    for s in sids:
-        cse.cse_scheme_free(ctx, s)
-    same = stats["batched"]["best_additions"] == stats["plain"]["best_additions"]
-    return {"workload": "batch-32-uneven: (n,m,p) in {2..7}^3, r=round((nmp)^0.93), p=0.2; pools ~ r summing "
-                        "to 65536; paper weights; sharing 32 steps 1% -> 10%",
-            "batched": {k: v for k, v in stats["batched"].items() if k != "best_additions"},
-            "plain": {k: v for k, v in stats["plain"].items() if k != "best_additions"},
-            "speedup": stats["batched"]["steps_per_s"] / stats["plain"]["steps_per_s"],
-            "scheme_best_additions": stats["batched"]["best_additions"], "identical_results": same,
-            "autotune": tuning}
+    torch.cuda.synchronize()
+    log(f"[bench] workload batch-32: {len(wl.schemes)} schemes, {sum(rs.n_proc for rs in wl.runs)} processes")
+    cse.cse_ctx_set_timing(ctx, True)
+    for w in range(args.warmup):
+        p = scheme_pass(cse, ctx, stream, dev, cfgs, True)
+        log(f"[bench] warmup {w}: {p['seconds'] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    passes = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        passes.append(scheme_pass(cse, ctx, stream, dev, cfgs, True))
+        log(f"[bench] batched pass {k}: {passes[-1]['seconds'] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    cse.cse_ctx_set_timing(ctx, False)
+    plain = []
+    for k in range(args.plain_passes):
+        plain.append(scheme_pass(cse, ctx, stream, dev, cfgs, False))
+        log(f"[bench] plain pass {k}: {plain[-1]['seconds'] * 1e3:.1f} ms")
+    subs = sum(p["subs"] for p in passes)
+    sec = [p["seconds"] for p in passes]
+    # Roofline of the kernel class with the most device time.
+    cls_ns, cls_launch, cls_ops = {}, {}, {}
+    for p in passes:
+        for kt in p["kernel_times"]:
+            key = (kt["row_words"], kt["layout"])
+            cls_ns[key] = cls_ns.get(key, 0) + kt["device_ns"]
+            cls_launch[key] = cls_launch.get(key, 0) + kt["launches"]
+        for key, v in p["per_class_ops"].items():
+            cls_ops[key] = cls_ops.get(key, 0) + v
+    dom = max(cls_ns, key=cls_ns.get)
+    avg_launch_s = cls_ns[dom] / 1e9 / cls_launch[dom]
+    ops_per_launch = cls_ops.get(dom, 0) / cls_launch[dom]
+    achieved = ops_per_launch / avg_launch_s
+    first = passes[0]
+    out = base_line(
+        args, value=subs / total, unit="substitution steps/s", ms_per_step=total / args.steps * 1e3,
+        config={"workload": BATCH_NAME, "schemes": len(wl.schemes), "n_proc_total": sum(rs.n_proc for rs in wl.runs),
+                "substitutions_per_step": first["subs"], "inputs_sha256": workloads.workload_digest(wl)},
+        ms_per_step_median=float(np.median(sec)) * 1e3,
+        time_to_best_ms={"mean_over_schemes": float(np.mean(first["ttb_s"])) * 1e3,
+                         "max_over_schemes": float(np.max(first["ttb_s"])) * 1e3},
+        batched_vs_plain={
+            "plain": None if not plain else {
+                "passes": len(plain), "seconds_median": float(np.median([p["seconds"] for p in plain])),
+                "steps_per_s": plain[0]["subs"] / float(np.median([p["seconds"] for p in plain])),
+                "mean_time_to_best_ms": float(np.mean(plain[0]["ttb_s"])) * 1e3,
+                "max_time_to_best_ms": float(np.max(plain[0]["ttb_s"])) * 1e3},
+            "speedup": None if not plain else float(np.median([p["seconds"] for p in plain])) / float(np.median(sec)),
+            "identical_results": None if not plain else all(p["best"] == first["best"] for p in passes + plain),
+            "scheme_best_additions": first["best"]},
+        roofline={"kernel": kernel_name(*dom), "bound": "alu", "achieved": achieved / 1e12,
+                  "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
+                  "traffic": measured_traffic(kernel_name(*dom), "batch"), "traffic_unit": "HBM bytes per launch",
+                  "algorithmic_ops_per_launch": ops_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
+                  "launches": cls_launch[dom],
+                  "device_ms_per_class": {kernel_name(*k): v / 1e6 / args.steps for k, v in sorted(cls_ns.items())}})
+    if not args.no_cpu_baseline:
+        n_threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu oracle on {n_threads} threads (sample of units)")
+        steps, dt, units = cpu_baseline_batch(wl, n_threads)
+        out["cpu_baseline"] = {"value": steps / dt, "unit": "substitution steps/s", "cores": n_threads,
+                               "kind": "oracle",
+                               "sample": f"{units} units drawn uniformly (seeded) from the batch's "
+                                         f"{3 * sum(rs.n_proc for rs in wl.runs)} (scheme, component, process) "
+                                         f"units, each reduced from its input to the end without sharing rounds: "
+                                         f"{steps} substitutions in {dt:.2f} s"}
+    return out
 
 
 COUNT_PATHS = {"auto": 0, "popcount": 1, "mfma": 2}
@@ -404,15 +528,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="4x4x4", choices=["4x4x4", "6x6x6", "batch", "serve", "driver"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "4x4x4", "6x6x6", "serve", "driver"])
+    ap.add_argument("--plain-passes", type=int, default=2, help="batch: plain passes (one launch per scheme)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch: skip the 4x4x4, 6x6x6 and serving lines added as extra keys")
     ap.add_argument("--patience", type=int, default=10, help="driver: iterations without improvement to stop")
     ap.add_argument("--driver-scheme", default="4x4x4", choices=["4x4x4", "6x6x6"], help="driver: which systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix", "gp"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched vs plain section")
-    ap.add_argument("--autotune", action="store_true",
-                    help="batch / 6x6x6: pick component layouts with cse_autotune first")
+    ap.add_argument("--autotune", action="store_true", help="6x6x6: pick component layouts with cse_autotune first")
     ap.add_argument("--count-path", default="auto", choices=list(COUNT_PATHS),
                     help="4x4x4 / 6x6x6: how the input's pair counts are computed (same results)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
@@ -443,18 +568,25 @@ def main():
         del src, dst
     ctx = cse.cse_ctx_create(0)
     try:
-        if args.workload == "4x4x4":
+        if args.workload == "batch":
+            out = run_batch(args, cse, workloads, torch, ctx, stream)
+            if not args.no_extras:
+                # The other workloads, each timed on its own, as extra keys.
+                sub = argparse.Namespace(**dict(vars(args), no_cpu_baseline=True, steps=min(args.steps, 10),
+                                                warmup=1, strategy=None, autotune=False))
+                keep = ("value", "unit", "ms_per_step", "config", "time_to_best_ms", "best_additions", "roofline",
+                        "serving", "pcie_inclusive")
+                for name, fn in (("plain_4x4x4", run_plain44), ("plain_6x6x6", run_6x6x6),
+                                 ("serving", run_serve)):
+                    log(f"[bench] extra: {name}")
+                    r = fn(sub, cse, workloads, torch, ctx, stream)
+                    out[name] = {k: v for k, v in r.items() if k in keep}
+        elif args.workload == "4x4x4":
             out = run_plain44(args, cse, workloads, torch, ctx, stream)
-            if not args.no_batch:
-                out["batched_vs_plain"] = batch_vs_plain(cse, workloads, torch, ctx, stream)
         elif args.workload == "6x6x6":
             out = run_6x6x6(args, cse, workloads, torch, ctx, stream)
         elif args.workload == "driver":
             out = run_driver(args, cse, workloads, torch, ctx, stream)
-        elif args.workload == "batch":
-            bp = batch_vs_plain(cse, workloads, torch, ctx, stream, reps=2, autotune=args.autotune)
-            out = base_line(args, value=bp["batched"]["steps_per_s"], unit="substitution steps/s",
-                            ms_per_step=None, config={"workload": bp["workload"]}, batched_vs_plain=bp)
         else:
             out = run_serve(args, cse, workloads, torch, ctx, stream)
     finally:

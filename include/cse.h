@@ -122,6 +122,18 @@ int32_t cse_scheme_load(cse_ctx* ctx,
                         const int8_t* Wt, int32_t w_rows, int32_t w_cols,
                         int32_t* scheme_id);
 
+/* cse_scheme_load from device memory: U, V and W^T are device pointers
+ * (HIP), read on `stream` after the work already queued there, copied (the
+ * caller keeps them) and validated and sized on the device; V and W^T both
+ * NULL loads U alone as a one-component scheme.  Same rules and errors as
+ * cse_scheme_load (CSE_ENOMEM also when a system's variable lists cannot
+ * fit a workgroup's LDS); blocking. */
+int32_t cse_scheme_load_device(cse_ctx* ctx,
+                               const int8_t* U, int32_t u_rows, int32_t u_cols,
+                               const int8_t* V, int32_t v_rows, int32_t v_cols,
+                               const int8_t* Wt, int32_t w_rows, int32_t w_cols,
+                               void* stream, int32_t* scheme_id);
+
 /* Shape of a loaded scheme: *n_comp components; info (4 per component):
  * n_e, n_x, n_fmax (the fresh-variable bound floor((nnz - n_e) / 2)), and
  * the naive count (Sec. 3.2.1). */
@@ -286,6 +298,29 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
                         int32_t* triples, int32_t cap, int32_t* n_fresh, int32_t* cost,
                         int32_t* needed);
 
+/* Device time of step-kernel launches, per kernel class. */
+typedef struct {
+    int32_t row_words;   /* W: rows <= 64 W */
+    int32_t layout;      /* CSE_LAYOUT_* of the components it ran */
+    int32_t launches;    /* launches timed */
+    int32_t reserved;
+    uint64_t device_ns;  /* summed time between the HIP events around them */
+} cse_kernel_time;
+
+/* Kernel timing on a context (off by default).  While on, every step-kernel
+ * launch is bracketed by two HIP events on the stream it runs on, and the
+ * rounds of sharing jobs and servers are launched directly rather than
+ * replayed as a captured graph (so their launches can be timed). */
+int32_t cse_ctx_set_timing(cse_ctx* ctx, int32_t on);
+
+/* The timed launches of the batch (or server) that runs job_id, summed per
+ * kernel class (row words, layout) over its runs since the last reset;
+ * waits for a non-server batch to finish.  *n receives the number of
+ * classes; out (may be NULL) receives them when cap >= *n, else
+ * CSE_ERANGE.  reset != 0 clears the sums after reading. */
+int32_t cse_kernel_times(cse_ctx* ctx, int32_t job_id, cse_kernel_time* out, int32_t cap, int32_t* n,
+                         int32_t reset);
+
 /* Timing of a finished job: device ticks from job start to the last unit's
  * finish, and the tick rate in Hz. */
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz);
@@ -323,6 +358,70 @@ int32_t cse_server_job_info(cse_server* s, int32_t job_id, int32_t* state, uint6
 int32_t cse_server_release(cse_server* s, int32_t job_id);
 /* Destroy the server and every job it owns. */
 void cse_server_destroy(cse_server* s);
+
+/* ---------------------------------------------------------------------------
+ * Random flips of a scheme (Sec. 3.5.3).  A scheme of format (n, m, p : r) is
+ * r products t = U_t (x) V_t (x) W_t: U (r x nm) over the entries of A
+ * (n x m), V (r x mp) over B (m x p), W (r x np) over C (n x p), all
+ * row-major and ternary; its systems E_U, E_V, E_W of Sec. 3.2 are U, V and
+ * W transposed.  A flip rewrites two products that share a factor up to
+ * sign, X_j = s X_i (X one of U, V, W), into two others computing the same
+ * tensor: X_i (x) (Y_i + s Y_j) (x) Z_i + X_j (x) Y_j (x) (Z_j - Z_i), or
+ * the same with Y and Z exchanged ((Y, Z) = (V, W), (U, W), (U, V) for
+ * X = U, V, W); it is valid when both changed vectors stay ternary and
+ * nonzero, so every variant computes C = A B with the same rank.  Valid
+ * flips are numbered in the order (X, i, j, Y-or-Z first).  Variant 0 is
+ * the scheme itself; variant v > 0 at iteration `it` applies
+ * 1 + floor(u max_flips / 2^32) flips (u: word 0 of Philox (v,
+ * FLIP|0|it|0, 0, 0), FLIP = 6 in the tag nibble), flip f taking valid flip
+ * floor(u' n_valid / 2^32), u' word 0 of (v, FLIP|0|it|f+1, 0, 0), and
+ * stops early when none is valid.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n, m, p;      /* format: A n x m, B m x p, C n x p (each <= 4096 entries) */
+    int32_t n_variants;   /* M (paper: 32), variant 0 the scheme itself */
+    int32_t max_flips;    /* flips per variant uniform in [1, max_flips], <= 65534 */
+    int32_t reserved;     /* must be 0 */
+} cse_flip_cfg;
+
+/* The M variants of one iteration, generated on the device from host
+ * arrays (copied): outU (M x r x nm), outV (M x r x mp), outW (M x r x np)
+ * host arrays; n_flips (M, may be NULL) receives the flips applied.
+ * CSE_EINVAL for a bad format or non-ternary coefficients, CSE_ENOMEM when
+ * r (nm + mp + np) bytes exceed a workgroup's LDS.  Blocking. */
+int32_t cse_flip_variants(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int32_t rank,
+                          const cse_flip_cfg* fcfg, uint64_t seed, uint32_t iteration,
+                          int8_t* outU, int8_t* outV, int8_t* outW, int32_t* n_flips);
+
+/* The random-flip mode (Sec. 3.5.3).  Iteration it (from 0) generates the M
+ * variants of iteration it (seed cfg->seed) and reduces each of them with
+ * cfg->n_proc processes, variant v with seed cfg->seed + v and cfg's
+ * iteration field set to it, all in one batch (sharing rounds as cfg says).
+ * A variant's total is the sum of its three component bests (components
+ * only combine within one variant); the lowest total over the variants of
+ * an iteration (ties: lower v) replaces the best so far when strictly lower.
+ * Stops when the best total has not changed for `patience` iterations or
+ * after max_iterations (<= 1024).  *run_id receives the run (read it with
+ * cse_flip_best / cse_flip_program, free it with cse_flip_release);
+ * *iterations (may be NULL) the iterations run.  Blocking. */
+int32_t cse_run_flips(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int32_t rank,
+                      const cse_flip_cfg* fcfg, const cse_run_cfg* cfg, int32_t patience, int32_t max_iterations,
+                      void* stream, int32_t* run_id, int32_t* iterations);
+
+/* The best variant of a flip run: its U, V, W (host arrays of the input's
+ * sizes; each may be NULL), component costs, variant and iteration, and the
+ * best total after each iteration (totals, cap entries; may be NULL;
+ * CSE_ERANGE when cap is too small), *n_iter the iteration count. */
+int32_t cse_flip_best(cse_ctx* ctx, int32_t run_id, int8_t* U, int8_t* V, int8_t* W, int32_t best_cost[3],
+                      int32_t* variant, int32_t* iteration, int32_t* totals, int32_t cap, int32_t* n_iter);
+
+/* Program of component comp (0 U, 1 V, 2 W^T) of the best variant, as in
+ * cse_get_program. */
+int32_t cse_flip_program(cse_ctx* ctx, int32_t run_id, int32_t comp, int32_t* triples, int32_t cap,
+                         int32_t* n_fresh, int32_t* needed);
+
+/* Free a flip run's results. */
+int32_t cse_flip_release(cse_ctx* ctx, int32_t run_id);
 
 #ifdef __cplusplus
 }

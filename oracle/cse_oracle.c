@@ -43,7 +43,7 @@ enum { S_G = 0, S_GA = 1, S_WR = 2, S_GR = 3, S_GI = 4, S_MIX = 5, S_GP = 6, N_S
 
 /* Random-stream tags placed in the top nibble of counter word 1 (REINIT is
  * drawn by the outer-iteration driver, which composes pool runs). */
-enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4, TAG_REINIT = 5 };
+enum { TAG_PROC = 1, TAG_STEP = 2, TAG_COIN = 3, TAG_SHARE = 4, TAG_REINIT = 5, TAG_FLIP = 6 };
 
 /* ------------------------------------------------------------------------
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
@@ -81,9 +81,9 @@ uint32_t oc_domain_word(uint32_t tag, uint32_t comp, uint32_t epoch, uint32_t st
 /* A unit's epoch counts its restarts and can pass the 10 bits of word 1
  * (sharing events and outer iterations add up).  So that no step or coin key
  * is ever reused, the epoch's bits above the tenth go to the upper half of
- * counter word 3 of those draws (whose lower half is 0 for a step draw and
- * the coin block index, < 2^16, for a coin draw); epochs below 1024 leave
- * word 3 as it was. */
+ * counter word 3 of those draws (whose lower half is 0 for a step draw, and
+ * a coin stream's block index, < 2^15, plus its side bit 2^15 for a coin
+ * draw); epochs below 1024 leave word 3 as it was. */
 uint32_t oc_epoch_high(uint32_t epoch) { return (epoch >> 10) << 16; }
 
 static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4])
@@ -228,14 +228,6 @@ int oc_select_wr(const oc_cand* C, int m, uint32_t u)
     return -1;
 }
 
-/* Two canonical pairs intersect when they share a variable index (sign is
- * ignored: substitution removes both variables from the affected rows). */
-static int pairs_intersect(uint32_t p, uint32_t q)
-{
-    int pa = key_a(p), pb = key_b(p), qa = key_a(q), qb = key_b(q);
-    return pa == qa || pa == qb || pb == qa || pb == qb;
-}
-
 /* Greedy-Intersections (gi), Sec. 3.4.2, scores
  *     H(p) = (c_p - 1) + alpha * sum_{q != p} I(p, q)
  *     I(p, q) = c_q - 1                          if p and q are disjoint,
@@ -244,37 +236,61 @@ static int pairs_intersect(uint32_t p, uint32_t q)
  * 2^32 H is evaluated exactly in 64-bit integers:
  *     (c_p - 1) 2^32 + alpha_q (D_p 2^16 + beta_q X_p),
  * D_p = sum of c_q - 1 over disjoint q, X_p = the same over intersecting q
- * whose coin is 1.  The intersecting q of p are numbered j = 0, 1, ... in
- * canonical order; coin j is bit (j mod 128) of the 128-bit Philox block
- * counter (process, COIN|comp|epoch|step, key(p), j div 128 | high epoch
- * bits), taking word (j mod 128) div 32, bit j mod 32.  Ties go to the first
- * in canonical order.
- * n_int and n_blk (optional) receive sum_p |I(p)| and the Philox blocks
- * drawn, for the algorithmic work tally. */
+ * whose coin is 1.  Ties go to the first in canonical order.
+ *
+ * Two candidates intersect when they share a variable index (the sign is
+ * ignored: a substitution removes both variables from the affected rows).
+ * Coins: every intersecting q of p = (a, b) gets one fair coin of its own.
+ * The intersecting candidates are split by the variable they share with p:
+ * A_p = the candidates holding a (p's twin of the other sign included),
+ * B_p = those holding b but not a; each list is numbered i = 0, 1, ... in
+ * canonical order, and the i-th member of A_p (of B_p) takes bit i mod 128
+ * of the Philox block counter (process, COIN|comp|epoch|step, key(p),
+ * i div 128 | side | high epoch bits), side = 0 for A_p and 2^15 for B_p,
+ * as word (i mod 128) div 32, bit i mod 32.
+ *
+ * n_int and n_blk (optional) receive sum_p (|A_p| + |B_p|) and the Philox
+ * blocks drawn, sum_p (ceil(|A_p| / 128) + ceil(|B_p| / 128)), for the
+ * algorithmic work tally. */
 int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
                  uint64_t seed, uint32_t proc, uint32_t comp, uint32_t epoch, uint32_t step,
                  int64_t* n_int, int64_t* n_blk)
 {
     int best = -1;
     int64_t best_h = 0, tot_int = 0, tot_blk = 0;
-    uint32_t dw = oc_domain_word(TAG_COIN, comp, epoch, step);
+    const uint32_t dw = oc_domain_word(TAG_COIN, comp, epoch, step);
+    const uint32_t eh = oc_epoch_high(epoch);
     for (int p = 0; p < m; p++) {
+        const int pa = key_a(C[p].key), pb = key_b(C[p].key);
         int64_t D = 0, X = 0;
-        int64_t j = 0;
-        uint32_t block[4] = { 0, 0, 0, 0 };
+        int64_t ia = 0, ib = 0;             /* members of A_p and B_p so far */
+        uint32_t blk_a[4] = { 0, 0, 0, 0 }, blk_b[4] = { 0, 0, 0, 0 };
         for (int q = 0; q < m; q++) {
             if (q == p) continue;
-            int64_t wq = C[q].c - 1;
-            if (!pairs_intersect(C[p].key, C[q].key)) { D += wq; continue; }
-            if (j % 128 == 0) {
-                draw(seed, proc, dw, C[p].key, (uint32_t)(j / 128) | oc_epoch_high(epoch), block);
-                tot_blk++;
+            const int64_t wq = C[q].c - 1;
+            const int qa = key_a(C[q].key), qb = key_b(C[q].key);
+            int coin;
+            if (qa == pa || qb == pa) {
+                if (ia % 128 == 0) {
+                    draw(seed, proc, dw, C[p].key, (uint32_t)(ia / 128) | eh, blk_a);
+                    tot_blk++;
+                }
+                coin = (int)((blk_a[(ia % 128) / 32] >> (ia % 32)) & 1u);
+                ia++;
+            } else if (qa == pb || qb == pb) {
+                if (ib % 128 == 0) {
+                    draw(seed, proc, dw, C[p].key, (uint32_t)(ib / 128) | 0x8000u | eh, blk_b);
+                    tot_blk++;
+                }
+                coin = (int)((blk_b[(ib % 128) / 32] >> (ib % 32)) & 1u);
+                ib++;
+            } else {
+                D += wq;
+                continue;
             }
-            int r = (int)(j % 128);
-            if ((block[r / 32] >> (r % 32)) & 1u) X += wq;
-            j++;
+            if (coin) X += wq;
         }
-        tot_int += j;
+        tot_int += ia + ib;
         int64_t h = ((int64_t)(C[p].c - 1) << 32) + (int64_t)alpha_q * ((D << 16) + (int64_t)beta_q * X);
         if (best < 0 || h > best_h) { best = p; best_h = h; }
     }
@@ -728,5 +744,116 @@ int oc_bounds(const int8_t* A0, int n_e, int n_x, int32_t* n_fmax, int64_t* occ_
     for (int64_t i = 0; i < (int64_t)n_e * n_x; i++) nnz0 += A0[i] != 0;
     if (n_fmax) *n_fmax = (int32_t)((nnz0 - n_e) / 2);
     if (occ_cap) *occ_cap = oc_pair_occurrences(A0, n_e, n_x, n_x);
+    return OC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Random flips of a scheme (Sec. 3.5.3).  A scheme of format (n, m, p : r)
+ * is r products t, each the tensor product U_t (x) V_t (x) W_t of three
+ * ternary vectors: U_t over the entries of A (n x m, row-major), V_t over B
+ * (m x p), W_t over C (n x p); the system E_W of Sec. 3.2 is W transposed.
+ * The paper takes its flips from the ternary flip graph of another work;
+ * reading used here: when two products i != j share a factor up to sign,
+ * X_j = s X_i (s = +1 or -1, X one of U, V, W, X_i nonzero), then
+ *     X_i (x) Y_i (x) Z_i + X_j (x) Y_j (x) Z_j
+ *   = X_i (x) (Y_i + s Y_j) (x) Z_i + X_j (x) Y_j (x) (Z_j - Z_i)     (h = 0)
+ *   = X_i (x) Y_i (x) (Z_i + s Z_j) + X_j (x) (Y_j - Y_i) (x) Z_j     (h = 1)
+ * with (Y, Z) = (V, W) for X = U, (U, W) for X = V and (U, V) for X = W.
+ * Both sides are the same tensor, so the scheme stays a valid algorithm of
+ * the same rank.  A flip is valid when the two changed vectors stay ternary
+ * and nonzero.  Valid flips are numbered in the order (X, i, j, h).
+ *
+ * Variant v at iteration `iteration`: variant 0 is the scheme itself; any
+ * other draws F = 1 + floor(u F_max / 2^32) from the Philox block
+ * (v, FLIP|0|iteration|0, 0, 0) and applies F flips in turn, flip f being
+ * valid flip number floor(u' n_valid / 2^32) of the current scheme, u' word
+ * 0 of (v, FLIP|0|iteration|f+1, 0, 0); it stops early when no flip is
+ * valid.  *n_done receives the flips applied.
+ * ---------------------------------------------------------------------- */
+static int8_t* flip_row(int8_t* M, int len, int t) { return M + (size_t)t * len; }
+
+/* 1 if Y_a + s Y_b and the other update stay ternary and nonzero. */
+static int row_sum_ok(const int8_t* a, const int8_t* b, int s, int len)
+{
+    int nz = 0;
+    for (int k = 0; k < len; k++) {
+        int v = a[k] + s * b[k];
+        if (v < -1 || v > 1) return 0;
+        nz |= v != 0;
+    }
+    return nz;
+}
+
+/* Sign s with X_j = s X_i (X_i nonzero), or 0. */
+static int factor_sign(const int8_t* xi, const int8_t* xj, int len)
+{
+    int sp = 1, sm = 1, nz = 0;
+    for (int k = 0; k < len; k++) {
+        sp &= xj[k] == xi[k];
+        sm &= xj[k] == -xi[k];
+        nz |= xi[k] != 0;
+    }
+    if (!nz) return 0;
+    return sp ? 1 : (sm ? -1 : 0);
+}
+
+/* Visit the valid flips in order; apply number `want` (>= 0) or count them
+ * (want < 0).  Returns the count, or 1 when the flip was applied. */
+static int64_t flips_visit(int8_t* M[3], const int len[3], int r, int64_t want)
+{
+    static const int other[3][2] = { { 1, 2 }, { 0, 2 }, { 0, 1 } };
+    int64_t count = 0;
+    for (int X = 0; X < 3; X++) {
+        const int Y = other[X][0], Z = other[X][1];
+        for (int i = 0; i < r; i++) {
+            for (int j = 0; j < r; j++) {
+                if (i == j) continue;
+                const int s = factor_sign(flip_row(M[X], len[X], i), flip_row(M[X], len[X], j), len[X]);
+                if (!s) continue;
+                for (int h = 0; h < 2; h++) {
+                    /* h = 0: Y_i += s Y_j, Z_j -= Z_i;  h = 1: Z_i += s Z_j, Y_j -= Y_i. */
+                    const int P = h ? Z : Y, Q = h ? Y : Z;
+                    int8_t* Pi = flip_row(M[P], len[P], i);
+                    const int8_t* Pj = flip_row(M[P], len[P], j);
+                    int8_t* Qj = flip_row(M[Q], len[Q], j);
+                    const int8_t* Qi = flip_row(M[Q], len[Q], i);
+                    if (!row_sum_ok(Pi, Pj, s, len[P]) || !row_sum_ok(Qj, Qi, -1, len[Q])) continue;
+                    if (count == want) {
+                        for (int k = 0; k < len[P]; k++) Pi[k] = (int8_t)(Pi[k] + s * Pj[k]);
+                        for (int k = 0; k < len[Q]; k++) Qj[k] = (int8_t)(Qj[k] - Qi[k]);
+                        return 1;
+                    }
+                    count++;
+                }
+            }
+        }
+    }
+    return count;
+}
+
+int oc_flip_variant(const int8_t* U, const int8_t* V, const int8_t* W, int n, int m, int p, int r,
+                    uint64_t seed, uint32_t variant, uint32_t iteration, uint32_t max_flips,
+                    int8_t* outU, int8_t* outV, int8_t* outW, int32_t* n_done)
+{
+    if (n < 1 || m < 1 || p < 1 || r < 1 || max_flips < 1 || max_flips > 65534) return OC_EINVAL;
+    const int len[3] = { n * m, m * p, n * p };
+    memcpy(outU, U, (size_t)r * len[0]);
+    memcpy(outV, V, (size_t)r * len[1]);
+    memcpy(outW, W, (size_t)r * len[2]);
+    int8_t* M[3] = { outU, outV, outW };
+    int done = 0;
+    if (variant != 0) {
+        uint32_t u[4];
+        draw(seed, variant, oc_domain_word(TAG_FLIP, 0, iteration, 0), 0, 0, u);
+        const uint32_t F = 1 + scale_index(u[0], max_flips);
+        for (uint32_t f = 0; f < F; f++) {
+            const int64_t n_valid = flips_visit(M, len, r, -1);
+            if (n_valid == 0) break;
+            draw(seed, variant, oc_domain_word(TAG_FLIP, 0, iteration, f + 1), 0, 0, u);
+            flips_visit(M, len, r, (int64_t)scale_index(u[0], (uint64_t)n_valid));
+            done++;
+        }
+    }
+    if (n_done) *n_done = done;
     return OC_OK;
 }

@@ -92,6 +92,11 @@ def lib():
         L.oc_bounds.argtypes = [P(ctypes.c_int8), ctypes.c_int, ctypes.c_int,
                                 P(ctypes.c_int32), P(ctypes.c_int64)]
         L.oc_bounds.restype = ctypes.c_int
+        L.oc_flip_variant.argtypes = [P(ctypes.c_int8), P(ctypes.c_int8), P(ctypes.c_int8), ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_uint32, P(ctypes.c_int8), P(ctypes.c_int8),
+                                      P(ctypes.c_int8), P(ctypes.c_int32)]
+        L.oc_flip_variant.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -351,3 +356,20 @@ def run_driver(systems, cfg, reinit_pm=400, patience=10, max_iterations=100, n_t
         last[c] = dict(last[c], executed=executed[c], ops=ops[c])
     return dict(iterations=it, totals=totals, best=best, last=last)
 
+
+
+def flip_variant(U, V, W, n, m, p, seed, variant, iteration, max_flips):
+    """Variant `variant` of the scheme (U r x nm, V r x mp, W r x np; W holds
+    the products' C coefficients, W^T is the E_W system) at `iteration`:
+    (U', V', W', flips applied)."""
+    U, V, W = (np.ascontiguousarray(x, dtype=np.int8) for x in (U, V, W))
+    r = U.shape[0]
+    assert U.shape == (r, n * m) and V.shape == (r, m * p) and W.shape == (r, n * p)
+    oU, oV, oW = np.zeros_like(U), np.zeros_like(V), np.zeros_like(W)
+    done = ctypes.c_int32()
+    rc = lib().oc_flip_variant(_ptr(U, ctypes.c_int8), _ptr(V, ctypes.c_int8), _ptr(W, ctypes.c_int8), n, m, p, r,
+                               seed, variant, iteration, max_flips, _ptr(oU, ctypes.c_int8),
+                               _ptr(oV, ctypes.c_int8), _ptr(oW, ctypes.c_int8), ctypes.byref(done))
+    if rc != 0:
+        raise ValueError(f"oracle flip_variant failed with status {rc}")
+    return oU, oV, oW, int(done.value)

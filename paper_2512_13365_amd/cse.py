@@ -29,13 +29,16 @@ STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4:
 
 # Every symbol declared in include/cse.h.
 EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error", "cse_system_load",
-           "cse_scheme_load", "cse_scheme_info", "cse_scheme_free", "cse_scheme_layout", "cse_autotune",
+           "cse_scheme_load", "cse_scheme_load_device", "cse_scheme_info", "cse_scheme_free", "cse_scheme_layout",
+           "cse_autotune",
            "cse_launch", "cse_launch_batch",
            "cse_relaunch", "cse_resume", "cse_poll", "cse_wait", "cse_cancel", "cse_get_unit_results",
            "cse_get_programs",
            "cse_get_program", "cse_job_timing", "cse_job_release", "cse_server_create", "cse_server_submit",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
-           "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best")
+           "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best", "cse_ctx_set_timing",
+           "cse_kernel_times", "cse_flip_variants", "cse_run_flips", "cse_flip_best", "cse_flip_program",
+           "cse_flip_release")
 CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE, CSE_JOB_FAILED = 0, 1, 2, 3
 
 
@@ -43,6 +46,16 @@ class CseError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class CseKernelTime(ctypes.Structure):
+    _fields_ = [("row_words", ctypes.c_int32), ("layout", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("device_ns", ctypes.c_uint64)]
+
+
+class CseFlipCfg(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("n_variants", ctypes.c_int32), ("max_flips", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CseRunCfg(ctypes.Structure):
@@ -98,7 +111,27 @@ def load_library(path: str = LIB_PATH):
     L.cse_scheme_load.argtypes = [vp, P(ctypes.c_int8), i32, i32, P(ctypes.c_int8), i32, i32,
                                   P(ctypes.c_int8), i32, i32, P(i32)]
     L.cse_scheme_load.restype = i32
+    L.cse_scheme_load_device.argtypes = [vp, vp, i32, i32, vp, i32, i32, vp, i32, i32, vp, P(i32)]
+    L.cse_scheme_load_device.restype = i32
     L.cse_scheme_info.argtypes = [vp, i32, P(i32), P(i32)]
+    L.cse_flip_variants.argtypes = [vp, P(ctypes.c_int8), P(ctypes.c_int8), P(ctypes.c_int8), i32, P(CseFlipCfg),
+                                    ctypes.c_uint64, ctypes.c_uint32, P(ctypes.c_int8), P(ctypes.c_int8),
+                                    P(ctypes.c_int8), P(i32)]
+    L.cse_flip_variants.restype = i32
+    L.cse_run_flips.argtypes = [vp, P(ctypes.c_int8), P(ctypes.c_int8), P(ctypes.c_int8), i32, P(CseFlipCfg),
+                                P(CseRunCfg), i32, i32, vp, P(i32), P(i32)]
+    L.cse_run_flips.restype = i32
+    L.cse_flip_best.argtypes = [vp, i32, P(ctypes.c_int8), P(ctypes.c_int8), P(ctypes.c_int8), P(i32), P(i32),
+                                P(i32), P(i32), i32, P(i32)]
+    L.cse_flip_best.restype = i32
+    L.cse_flip_program.argtypes = [vp, i32, i32, P(i32), i32, P(i32), P(i32)]
+    L.cse_flip_program.restype = i32
+    L.cse_flip_release.argtypes = [vp, i32]
+    L.cse_flip_release.restype = i32
+    L.cse_ctx_set_timing.argtypes = [vp, i32]
+    L.cse_ctx_set_timing.restype = i32
+    L.cse_kernel_times.argtypes = [vp, i32, P(CseKernelTime), i32, P(i32), i32]
+    L.cse_kernel_times.restype = i32
     L.cse_scheme_info.restype = i32
     L.cse_scheme_free.argtypes = [vp, i32]
     L.cse_scheme_free.restype = i32
@@ -230,6 +263,108 @@ def cse_scheme_load(ctx, U, V, Wt) -> int:
         ctx, _p(U, ctypes.c_int8), U.shape[0], U.shape[1], _p(V, ctypes.c_int8), V.shape[0], V.shape[1],
         _p(Wt, ctypes.c_int8), Wt.shape[0], Wt.shape[1], ctypes.byref(sid)))
     return sid.value
+
+
+def cse_scheme_load_device(ctx, U, V=None, Wt=None, stream=None) -> int:
+    """U, V, W^T as int8 device tensors (rows x cols, contiguous); V and W^T
+    None load U alone."""
+    mats = [U, V, Wt]
+    args = []
+    for M in mats:
+        if M is None:
+            args += [None, 0, 0]
+            continue
+        if M.dtype != __import__("torch").int8 or not M.is_cuda or not M.is_contiguous() or M.dim() != 2:
+            raise ValueError("device systems must be contiguous 2-D int8 GPU tensors")
+        args += [ctypes.c_void_p(M.data_ptr()), M.shape[0], M.shape[1]]
+    sid = ctypes.c_int32()
+    _check(ctx, load_library().cse_scheme_load_device(ctx, *args, _stream_ptr(stream), ctypes.byref(sid)))
+    return sid.value
+
+
+def _flip_args(U, V, W, n, m, p, n_variants, max_flips):
+    U, V, W = _i8(U), _i8(V), _i8(W)
+    r = U.shape[0]
+    if U.shape != (r, n * m) or V.shape != (r, m * p) or W.shape != (r, n * p):
+        raise ValueError("U, V, W must be r x nm, r x mp, r x np")
+    f = CseFlipCfg()
+    f.n, f.m, f.p, f.n_variants, f.max_flips, f.reserved = n, m, p, n_variants, max_flips, 0
+    return U, V, W, r, f
+
+
+def cse_flip_variants(ctx, U, V, W, n, m, p, n_variants, max_flips, seed=0, iteration=0):
+    """[(U_v, V_v, W_v, flips)] for the M variants of one iteration."""
+    U, V, W, r, f = _flip_args(U, V, W, n, m, p, n_variants, max_flips)
+    oU = np.zeros((n_variants, r, n * m), np.int8)
+    oV = np.zeros((n_variants, r, m * p), np.int8)
+    oW = np.zeros((n_variants, r, n * p), np.int8)
+    nf = np.zeros(n_variants, np.int32)
+    i8 = ctypes.c_int8
+    _check(ctx, load_library().cse_flip_variants(ctx, _p(U, i8), _p(V, i8), _p(W, i8), r, ctypes.byref(f), seed,
+                                                 iteration, _p(oU, i8), _p(oV, i8), _p(oW, i8),
+                                                 _p(nf, ctypes.c_int32)))
+    return [(oU[v], oV[v], oW[v], int(nf[v])) for v in range(n_variants)]
+
+
+def cse_run_flips(ctx, U, V, W, n, m, p, cfg: CseRunCfg, n_variants=32, max_flips=32, patience=10,
+                  max_iterations=100, stream=None):
+    """Random-flip mode (blocking).  Returns (run id, iterations)."""
+    U, V, W, r, f = _flip_args(U, V, W, n, m, p, n_variants, max_flips)
+    run, its = ctypes.c_int32(-1), ctypes.c_int32(0)
+    i8 = ctypes.c_int8
+    _check(ctx, load_library().cse_run_flips(ctx, _p(U, i8), _p(V, i8), _p(W, i8), r, ctypes.byref(f),
+                                             ctypes.byref(cfg), patience, max_iterations, _stream_ptr(stream),
+                                             ctypes.byref(run), ctypes.byref(its)))
+    return run.value, its.value
+
+
+def cse_flip_best(ctx, run_id, shape):
+    """shape = (n, m, p, r): dict(U, V, W, cost[3], variant, iteration, totals)."""
+    n, m, p, r = shape
+    U = np.zeros((r, n * m), np.int8)
+    V = np.zeros((r, m * p), np.int8)
+    W = np.zeros((r, n * p), np.int8)
+    cost = (ctypes.c_int32 * 3)()
+    var, it, ni = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    L = load_library()
+    i8 = ctypes.c_int8
+    _check(ctx, L.cse_flip_best(ctx, run_id, None, None, None, None, None, None, None, 0, ctypes.byref(ni)))
+    totals = np.zeros(max(1, ni.value), np.int32)
+    _check(ctx, L.cse_flip_best(ctx, run_id, _p(U, i8), _p(V, i8), _p(W, i8), cost, ctypes.byref(var),
+                                ctypes.byref(it), _p(totals, ctypes.c_int32), ni.value, ctypes.byref(ni)))
+    return dict(U=U, V=V, W=W, cost=list(cost), variant=var.value, iteration=it.value,
+                totals=[int(x) for x in totals[:ni.value]])
+
+
+def cse_flip_program(ctx, run_id, comp):
+    L = load_library()
+    n, need = ctypes.c_int32(), ctypes.c_int32()
+    rc = L.cse_flip_program(ctx, run_id, comp, None, 0, ctypes.byref(n), ctypes.byref(need))
+    if rc not in (0, -3):
+        _check(ctx, rc)
+    tr = np.zeros((max(1, need.value), 3), np.int32)
+    _check(ctx, L.cse_flip_program(ctx, run_id, comp, _p(tr, ctypes.c_int32), need.value, ctypes.byref(n),
+                                   ctypes.byref(need)))
+    return tr[:n.value]
+
+
+def cse_flip_release(ctx, run_id):
+    _check(ctx, load_library().cse_flip_release(ctx, run_id))
+
+
+def cse_ctx_set_timing(ctx, on: bool):
+    _check(ctx, load_library().cse_ctx_set_timing(ctx, 1 if on else 0))
+
+
+def cse_kernel_times(ctx, job_id, reset=False):
+    """[{row_words, layout, launches, device_ns}] per step-kernel class."""
+    L = load_library()
+    n = ctypes.c_int32()
+    _check(ctx, L.cse_kernel_times(ctx, job_id, None, 0, ctypes.byref(n), 0))
+    out = (CseKernelTime * max(1, n.value))()
+    _check(ctx, L.cse_kernel_times(ctx, job_id, out, n.value, ctypes.byref(n), 1 if reset else 0))
+    return [dict(row_words=t.row_words, layout=t.layout, launches=t.launches, device_ns=int(t.device_ns))
+            for t in out[:n.value]]
 
 
 def cse_scheme_info(ctx, scheme_id):

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "cse.h"
+#include "cse_flip.hpp"
 #include "cse_input.hpp"
 #include "cse_kernels.hpp"
 #include "cse_share.hpp"
@@ -155,9 +156,26 @@ struct BatchRec {
     hipEvent_t ev_order = nullptr;
     hipGraphExec_t gexec = nullptr;
     uint32_t pool_grid_x = 1;
+    // Kernel timing (context switch): two events per launch group, the
+    // groups' launches not yet read, and device time per class (W, layout)
+    // since the run started.
+    std::vector<hipEvent_t> tev;
+    std::vector<int> t_pending;
+    std::map<std::pair<int, int>, std::pair<int32_t, uint64_t>> t_class;
 };
 
 }  // namespace
+
+// A random-flip run (Sec. 3.5.3): the best variant found, with its
+// matrices, component costs and programs, and the best total per iteration.
+struct FlipRun {
+    int n = 0, m = 0, p = 0, r = 0;
+    std::vector<int8_t> U, V, W;
+    int32_t best_cost[3] = {-1, -1, -1};
+    int32_t best_total = -1, variant = -1, iteration = -1;
+    std::vector<uint32_t> keys[3];
+    std::vector<int32_t> totals;
+};
 
 struct cse_ctx {
     int device = 0;
@@ -165,9 +183,11 @@ struct cse_ctx {
     std::map<int, SchemeRec> schemes;
     std::map<int, JobRec> jobs;
     std::map<int, BatchRec> batches;
-    int next_scheme = 1, next_job = 1, next_batch = 1;
+    std::map<int, FlipRun> flips;
+    int next_scheme = 1, next_job = 1, next_batch = 1, next_flip = 1;
     size_t lds_max = 65536;
     uint64_t tick_hz = 100000000ull;
+    bool timing = false;          // step-kernel launches bracketed by events
     int32_t* h_cancel = nullptr;  // kCancelSlots flags, pinned host memory
     int32_t* d_cancel = nullptr;  // the same as seen by the device
     std::vector<int> free_slots;
@@ -324,44 +344,34 @@ void set_layout(DevComp& c, int layout) {
     c.tl = (layout & CSE_LAYOUT_LDS_TABLES) != 0;
 }
 
-int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
-    if (!A || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
-    if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
-    long long nnz = 0, occ = 0, naive = 0;
-    for (int i = 0; i < rows; ++i) {
-        long long r = 0;
-        for (int j = 0; j < cols; ++j) {
-            const int8_t v = A[(size_t)i * cols + j];
-            if (v < -1 || v > 1) return fail(ctx, CSE_EINVAL, "entry (%d,%d) = %d not ternary", i, j, v);
-            r += v != 0;
-        }
-        if (r == 0) return fail(ctx, CSE_EINVAL, "row %d is all zero", i);
-        nnz += r;
-        occ += r * (r - 1) / 2;
-        naive += r - 1;
-    }
-    DevComp c;
-    c.n_e = rows;
-    c.n_x = cols;
+// A component from an input already copied to c->d_A (rows x cols int8)
+// and its sizes: nonzeros, pair occurrences and naive count (Sec. 3.2.1).
+// Builds the bitsets, analyses the input and picks the layout; frees the
+// component on error.
+int finish_component(cse_ctx* ctx, DevComp& c, long long nnz, long long occ, long long naive, DevComp* out) {
+    const int rows = c.n_e, cols = c.n_x;
     // Each substitution removes c >= 2 nonzeros and no row empties, so at
     // most floor((nnz - n_e) / 2) fresh variables; every candidate uses at
     // least two of the pair occurrences, whose number never grows.
     c.n_fmax = (int)((nnz - rows) / 2);
-    if ((long long)cols + c.n_fmax > kMaxVars)
+    if ((long long)cols + c.n_fmax > kMaxVars) {
+        free_component(c);
         return fail(ctx, CSE_EINVAL, "variables %lld exceed %d", (long long)cols + c.n_fmax, kMaxVars);
+    }
     c.W = (rows + 63) / 64;
     c.occ0 = occ;
     // The range form of gi packs candidate indices in 23 bits.
-    if (occ / 2 >= (1ll << 23)) return fail(ctx, CSE_EINVAL, "%lld candidates exceed 2^23", occ / 2);
+    if (occ / 2 >= (1ll << 23)) {
+        free_component(c);
+        return fail(ctx, CSE_EINVAL, "%lld candidates exceed 2^23", occ / 2);
+    }
     c.m_cap = (int)std::max<long long>(1, occ / 2);
     c.kbits = csek::weight_bits(rows);
     c.naive0 = (int)naive;
     const int n_vmax = cols + c.n_fmax;
     c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
     const size_t col_bytes = (size_t)cols * c.W * 8;
-    hipError_t e = hipMalloc(&c.d_A, (size_t)rows * cols);
-    if (e == hipSuccess) e = hipMemcpy(c.d_A, A, (size_t)rows * cols, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&c.d_P, col_bytes);
+    hipError_t e = hipMalloc(&c.d_P, col_bytes);
     if (e == hipSuccess) e = hipMalloc(&c.d_N, col_bytes);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(csek::input_columns_kernel, dim3((cols * c.W + 255) / 256), dim3(256), 0, nullptr,
@@ -399,6 +409,67 @@ int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* o
     }
     *out = c;
     return CSE_OK;
+}
+
+// A component from a host matrix (copied; the caller keeps it).
+int load_component(cse_ctx* ctx, const int8_t* A, int rows, int cols, DevComp* out) {
+    if (!A || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
+    if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
+    long long nnz = 0, occ = 0, naive = 0;
+    for (int i = 0; i < rows; ++i) {
+        long long r = 0;
+        for (int j = 0; j < cols; ++j) {
+            const int8_t v = A[(size_t)i * cols + j];
+            if (v < -1 || v > 1) return fail(ctx, CSE_EINVAL, "entry (%d,%d) = %d not ternary", i, j, v);
+            r += v != 0;
+        }
+        if (r == 0) return fail(ctx, CSE_EINVAL, "row %d is all zero", i);
+        nnz += r;
+        occ += r * (r - 1) / 2;
+        naive += r - 1;
+    }
+    DevComp c;
+    c.n_e = rows;
+    c.n_x = cols;
+    hipError_t e = hipMalloc(&c.d_A, (size_t)rows * cols);
+    if (e == hipSuccess) e = hipMemcpy(c.d_A, A, (size_t)rows * cols, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_component(c);
+        return fail(ctx, CSE_EHIP, "loading a %d x %d system: %s", rows, cols, hipGetErrorString(e));
+    }
+    return finish_component(ctx, c, nnz, occ, naive, out);
+}
+
+// A component from a device matrix (copied on `stream` after the caller's
+// work there; the caller keeps it), validated and sized on the device.
+int load_component_device(cse_ctx* ctx, const int8_t* dA, int rows, int cols, hipStream_t stream,
+                          unsigned long long* d_st, DevComp* out) {
+    if (!dA || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
+    if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
+    DevComp c;
+    c.n_e = rows;
+    c.n_x = cols;
+    unsigned long long st[5] = {0, 0, 0, 0, 0};
+    hipError_t e = hipMalloc(&c.d_A, (size_t)rows * cols);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.d_A, dA, (size_t)rows * cols, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, stream, (int32_t*)d_st, 10, 0);
+        hipLaunchKernelGGL(csek::input_stats_kernel, dim3((rows + 255) / 256), dim3(256), 0, stream, c.d_A, rows, cols,
+                           d_st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(st, d_st, sizeof st, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        free_component(c);
+        return fail(ctx, CSE_EHIP, "loading a %d x %d device system: %s", rows, cols, hipGetErrorString(e));
+    }
+    if (st[3] || st[4]) {
+        free_component(c);
+        return fail(ctx, CSE_EINVAL, "device system %d x %d: %llu entries not ternary, %llu all-zero rows", rows, cols,
+                    st[3], st[4]);
+    }
+    return finish_component(ctx, c, (long long)st[0], (long long)st[1], (long long)st[2], out);
 }
 
 bool shares(const cse_run_cfg& c) { return c.share_every > 0 && c.share_src_pm > 0 && c.share_max_rounds > 0; }
@@ -565,6 +636,10 @@ int alloc_job(cse_ctx* ctx, JobRec& J) {
 }
 
 void free_batch_device(BatchRec& B) {
+    for (hipEvent_t e : B.tev)
+        if (e) (void)hipEventDestroy(e);
+    B.tev.clear();
+    B.t_pending.clear();
     if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
     if (B.gstream) (void)hipStreamDestroy(B.gstream);
     if (B.ev_order) (void)hipEventDestroy(B.ev_order);
@@ -853,8 +928,38 @@ int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_s
     }
 }
 
-int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
-    for (const LaunchGroup& G : B.groups) {
+// Device time of the timed launches queued since the last call, added to
+// their classes (call once the stream holding them has been synchronised).
+int collect_times(cse_ctx* ctx, BatchRec& B) {
+    for (int g : B.t_pending) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, B.tev[2 * g], B.tev[2 * g + 1]));
+        const LaunchGroup& G = B.groups[g];
+        const int layout = (G.gs ? CSE_LAYOUT_HBM : 0) | (G.adj ? CSE_LAYOUT_RANGE : 0) | (G.tl ? CSE_LAYOUT_LDS_TABLES : 0);
+        auto& slot = B.t_class[std::make_pair(G.W, layout)];
+        slot.first += 1;
+        slot.second += (uint64_t)((double)ms * 1e6 + 0.5);
+    }
+    B.t_pending.clear();
+    return CSE_OK;
+}
+
+int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s, bool timed = false) {
+    if (timed && !B.t_pending.empty()) {
+        // Launches of an earlier run not read yet (a relaunch queued behind
+        // it on the same stream): read them before their events are reused.
+        HIP_TRY(ctx, hipEventSynchronize(B.tev[2 * B.t_pending.back() + 1]));
+        int rc = collect_times(ctx, B);
+        if (rc) return rc;
+    }
+    if (timed && B.tev.size() < 2 * B.groups.size()) {
+        size_t have = B.tev.size();
+        B.tev.resize(2 * B.groups.size(), nullptr);
+        for (size_t i = have; i < B.tev.size(); ++i) HIP_TRY(ctx, hipEventCreate(&B.tev[i]));
+    }
+    for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+        const LaunchGroup& G = B.groups[gi];
+        if (timed) HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi], s));
         int rc;
         if (G.gs && G.adj)
             rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
@@ -865,6 +970,10 @@ int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s) {
             rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
                        : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
         if (rc) return rc;
+        if (timed) {
+            HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi + 1], s));
+            B.t_pending.push_back((int)gi);
+        }
     }
     return CSE_OK;
 }
@@ -880,6 +989,8 @@ int wait_batch(cse_ctx* ctx, BatchRec& B) {
     if (!B.finished) {
         HIP_TRY(ctx, hipEventSynchronize(B.ev_done));
         B.finished = true;
+        int rc = collect_times(ctx, B);
+        if (rc) return rc;
         return check_err(ctx, B);
     }
     return CSE_OK;
@@ -913,22 +1024,26 @@ int init_job(cse_ctx* ctx, JobRec& J, hipStream_t s) {
 // memory) and replayed on the batch's internal stream, after the work the
 // caller queued on the batch's stream.  The host waits for the counts; a job
 // with no active unit left is done.
-int capture_round(cse_ctx* ctx, BatchRec& B) {
+// One round's work on stream s: every group's launch, then the pool kernels
+// and the copy of the active counts to pinned host memory.
+int enqueue_round(cse_ctx* ctx, BatchRec& B, hipStream_t s, bool timed) {
     const int n_pools = (int)B.pools.size();
+    int rc = launch_groups(ctx, B, s, timed);
+    if (rc) return rc;
+    const dim3 pg(B.pool_grid_x, (unsigned)n_pools), blk(256);
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), blk, 0, s, B.d_counts, n_pools, 0);
+    hipLaunchKernelGGL(csek::pools_count_kernel, pg, blk, 0, s, B.d_pools, B.d_counts);
+    hipLaunchKernelGGL(csek::pools_rank_kernel, pg, blk, 0, s, B.d_pools);
+    hipLaunchKernelGGL(csek::pools_target_kernel, pg, blk, 0, s, B.d_pools);
+    hipLaunchKernelGGL(csek::pools_round_kernel, dim3(1), blk, 0, s, B.d_pools, n_pools);
+    hipError_t e = hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(ctx, CSE_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    return CSE_OK;
+}
+
+int capture_round(cse_ctx* ctx, BatchRec& B) {
     HIP_TRY(ctx, hipStreamBeginCapture(B.gstream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_groups(ctx, B, B.gstream);
-    if (rc == CSE_OK) {
-        const dim3 pg(B.pool_grid_x, (unsigned)n_pools), blk(256);
-        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((n_pools + 255) / 256), blk, 0, B.gstream, B.d_counts,
-                           n_pools, 0);
-        hipLaunchKernelGGL(csek::pools_count_kernel, pg, blk, 0, B.gstream, B.d_pools, B.d_counts);
-        hipLaunchKernelGGL(csek::pools_rank_kernel, pg, blk, 0, B.gstream, B.d_pools);
-        hipLaunchKernelGGL(csek::pools_target_kernel, pg, blk, 0, B.gstream, B.d_pools);
-        hipLaunchKernelGGL(csek::pools_round_kernel, dim3(1), blk, 0, B.gstream, B.d_pools, n_pools);
-        hipError_t e = hipMemcpyAsync(B.h_counts, B.d_counts, sizeof(int32_t) * n_pools, hipMemcpyDeviceToHost,
-                                      B.gstream);
-        if (e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-    }
+    int rc = enqueue_round(ctx, B, B.gstream, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(B.gstream, &g);
     if (rc == CSE_OK && e != hipSuccess) rc = fail(ctx, CSE_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -943,14 +1058,25 @@ int capture_round(cse_ctx* ctx, BatchRec& B) {
 int round_once(cse_ctx* ctx, BatchRec& B) {
     if (!B.gstream) HIP_TRY(ctx, hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking));
     if (!B.ev_order) HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_order, hipEventDisableTiming));
-    if (!B.gexec) {
+    // Timed rounds are launched directly, each step-kernel launch between
+    // two events; otherwise the round is a captured graph.
+    if (!ctx->timing && !B.gexec) {
         int rc = capture_round(ctx, B);
         if (rc) return rc;
     }
     HIP_TRY(ctx, hipEventRecord(B.ev_order, B.stream));
     HIP_TRY(ctx, hipStreamWaitEvent(B.gstream, B.ev_order, 0));
-    HIP_TRY(ctx, hipGraphLaunch(B.gexec, B.gstream));
+    if (ctx->timing) {
+        int rc = enqueue_round(ctx, B, B.gstream, true);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(ctx, hipGraphLaunch(B.gexec, B.gstream));
+    }
     HIP_TRY(ctx, hipStreamSynchronize(B.gstream));
+    if (ctx->timing) {
+        int rc = collect_times(ctx, B);
+        if (rc) return rc;
+    }
     const int n_pools = (int)B.pools.size();
     std::map<int, long long> active;
     for (int p = 0; p < n_pools; ++p) active[B.pools[p].job] += B.h_counts[p];
@@ -984,7 +1110,7 @@ int run_batch(cse_ctx* ctx, BatchRec& B, bool fresh = true) {
     }
     int rc = B.built ? CSE_OK : build_segments(ctx, B);
     if (rc) return rc;
-    if (!B.rounds) return launch_groups(ctx, B, B.stream);
+    if (!B.rounds) return launch_groups(ctx, B, B.stream, ctx->timing);
     for (;;) {
         rc = round_once(ctx, B);
         if (rc) return rc;
@@ -1112,6 +1238,33 @@ int32_t cse_scheme_load(cse_ctx* ctx, const int8_t* U, int32_t u_rows, int32_t u
             return rc;
         }
     }
+    const int id = ctx->next_scheme++;
+    ctx->schemes[id] = s;
+    *scheme_id = id;
+    return CSE_OK;
+}
+
+int32_t cse_scheme_load_device(cse_ctx* ctx, const int8_t* U, int32_t u_rows, int32_t u_cols, const int8_t* V,
+                               int32_t v_rows, int32_t v_cols, const int8_t* Wt, int32_t w_rows, int32_t w_cols,
+                               void* stream, int32_t* scheme_id) {
+    if (!ctx || !scheme_id) return CSE_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int8_t* mats[3] = {U, V, Wt};
+    const int rows[3] = {u_rows, v_rows, w_rows}, cols[3] = {u_cols, v_cols, w_cols};
+    const int n = (V || Wt) ? 3 : 1;
+    if (n == 3 && (!V || !Wt)) return fail(ctx, CSE_EINVAL, "V and W^T are both given or both null");
+    unsigned long long* d_st = nullptr;
+    HIP_TRY(ctx, hipMalloc((void**)&d_st, 64));
+    SchemeRec s;
+    s.n_comp = n;
+    int rc = CSE_OK;
+    for (int c = 0; c < n && rc == CSE_OK; ++c) {
+        rc = load_component_device(ctx, mats[c], rows[c], cols[c], (hipStream_t)stream, d_st, &s.comp[c]);
+        if (rc)
+            for (int k = 0; k < c; ++k) free_component(s.comp[k]);
+    }
+    (void)hipFree(d_st);
+    if (rc) return rc;
     const int id = ctx->next_scheme++;
     ctx->schemes[id] = s;
     *scheme_id = id;
@@ -1563,6 +1716,39 @@ int32_t cse_get_program(cse_ctx* ctx, int32_t job_id, int32_t comp, int32_t proc
     return CSE_OK;
 }
 
+int32_t cse_ctx_set_timing(cse_ctx* ctx, int32_t on) {
+    if (!ctx) return CSE_EINVAL;
+    ctx->timing = on != 0;
+    return CSE_OK;
+}
+
+int32_t cse_kernel_times(cse_ctx* ctx, int32_t job_id, cse_kernel_time* out, int32_t cap, int32_t* n,
+                         int32_t reset) {
+    if (!ctx || !n) return CSE_EINVAL;
+    JobRec* J = nullptr;
+    BatchRec* B = batch_of(ctx, job_id, &J);
+    if (!B) return fail(ctx, CSE_ENOENT, "unknown job %d", job_id);
+    if (!J->server) {
+        int rc = wait_batch(ctx, *B);
+        if (rc) return rc;
+    }
+    *n = (int32_t)B->t_class.size();
+    if (out && cap < *n) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, *n);
+    int i = 0;
+    for (const auto& kv : B->t_class) {
+        if (out) {
+            out[i].row_words = kv.first.first;
+            out[i].layout = kv.first.second;
+            out[i].launches = kv.second.first;
+            out[i].reserved = 0;
+            out[i].device_ns = kv.second.second;
+        }
+        ++i;
+    }
+    if (reset) B->t_class.clear();
+    return CSE_OK;
+}
+
 int32_t cse_job_timing(cse_ctx* ctx, int32_t job_id, uint64_t* ticks, uint64_t* tick_hz) {
     if (!ctx) return CSE_EINVAL;
     JobRec* J = nullptr;
@@ -1987,6 +2173,305 @@ void cse_server_destroy(cse_server* s) {
     (void)hipSetDevice(ctx->device);
     drop_batch(ctx, s->batch);
     delete s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Random flips of a scheme (Sec. 3.5.3).
+// ---------------------------------------------------------------------------
+namespace {
+
+int validate_flip(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int32_t rank,
+                  const cse_flip_cfg* f) {
+    if (!U || !V || !W || !f || rank < 1) return fail(ctx, CSE_EINVAL, "null scheme or configuration");
+    if (f->n < 1 || f->m < 1 || f->p < 1 || f->n * f->m > 4096 || f->m * f->p > 4096 || f->n * f->p > 4096)
+        return fail(ctx, CSE_EINVAL, "format %d x %d x %d out of range", f->n, f->m, f->p);
+    if (f->n_variants < 1 || f->n_variants > 4096) return fail(ctx, CSE_EINVAL, "n_variants %d out of range", f->n_variants);
+    if (f->max_flips < 1 || f->max_flips > 65534) return fail(ctx, CSE_EINVAL, "max_flips %d out of range", f->max_flips);
+    if (f->reserved) return fail(ctx, CSE_EINVAL, "reserved field must be 0");
+    const int len[3] = {f->n * f->m, f->m * f->p, f->n * f->p};
+    for (int x = 0; x < 3; ++x) {
+        const int8_t* M = x == 0 ? U : x == 1 ? V : W;
+        for (size_t k = 0; k < (size_t)rank * len[x]; ++k)
+            if (M[k] < -1 || M[k] > 1) return fail(ctx, CSE_EINVAL, "scheme coefficient not ternary");
+    }
+    if (csek::flip_lds_bytes(rank, len[0], len[1], len[2]) > ctx->lds_max)
+        return fail(ctx, CSE_ENOMEM, "a %d-product scheme needs %zu B of LDS to flip (max %zu)", rank,
+                    csek::flip_lds_bytes(rank, len[0], len[1], len[2]), ctx->lds_max);
+    return CSE_OK;
+}
+
+// Device buffers of one flip generation: the scheme and all its variants.
+struct FlipBufs {
+    int8_t* base = nullptr;  // U | V | W
+    int8_t* var = nullptr;   // M x (U | V | W) then M x W^T
+    int32_t* n_done = nullptr;
+    ~FlipBufs() {
+        if (base) (void)hipFree(base);
+        if (var) (void)hipFree(var);
+        if (n_done) (void)hipFree(n_done);
+    }
+};
+
+int flip_generate(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int r, const cse_flip_cfg* f,
+                  uint64_t seed, uint32_t iteration, hipStream_t s, FlipBufs& B, csek::FlipArgs* out) {
+    const int len[3] = {f->n * f->m, f->m * f->p, f->n * f->p};
+    const size_t per = (size_t)r * (len[0] + len[1] + len[2]);
+    const int Mv = f->n_variants;
+    if (!B.base) {
+        HIP_TRY(ctx, hipMalloc((void**)&B.base, per));
+        HIP_TRY(ctx, hipMalloc((void**)&B.var, per * Mv + (size_t)Mv * r * len[2]));
+        HIP_TRY(ctx, hipMalloc((void**)&B.n_done, sizeof(int32_t) * Mv));
+        HIP_TRY(ctx, hipMemcpyAsync(B.base, U, (size_t)r * len[0], hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipMemcpyAsync(B.base + (size_t)r * len[0], V, (size_t)r * len[1], hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipMemcpyAsync(B.base + (size_t)r * (len[0] + len[1]), W, (size_t)r * len[2],
+                                    hipMemcpyHostToDevice, s));
+    }
+    csek::FlipArgs A{};
+    A.U = B.base;
+    A.V = B.base + (size_t)r * len[0];
+    A.W = B.base + (size_t)r * (len[0] + len[1]);
+    A.outU = B.var;
+    A.outV = B.var + (size_t)Mv * r * len[0];
+    A.outW = B.var + (size_t)Mv * r * (len[0] + len[1]);
+    A.outWt = B.var + per * Mv;
+    A.n_done = B.n_done;
+    A.r = r;
+    for (int x = 0; x < 3; ++x) A.len[x] = len[x];
+    A.max_flips = (uint32_t)f->max_flips;
+    A.iteration = iteration;
+    A.seed = seed;
+    const size_t lds = csek::flip_lds_bytes(r, len[0], len[1], len[2]);
+    if (lds > 65536)
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::flip_variants_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(csek::flip_variants_kernel, dim3(Mv), dim3(csek::kWave), lds, s, A);
+    HIP_TRY(ctx, hipGetLastError());
+    *out = A;
+    return CSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cse_flip_variants(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int32_t rank,
+                          const cse_flip_cfg* fcfg, uint64_t seed, uint32_t iteration, int8_t* outU, int8_t* outV,
+                          int8_t* outW, int32_t* n_flips) {
+    if (!ctx) return CSE_EINVAL;
+    int rc = validate_flip(ctx, U, V, W, rank, fcfg);
+    if (rc) return rc;
+    if (!outU || !outV || !outW) return fail(ctx, CSE_EINVAL, "null output");
+    if (iteration > 1023) return fail(ctx, CSE_EINVAL, "iteration %u exceeds 1023", iteration);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    FlipBufs B;
+    csek::FlipArgs A{};
+    rc = flip_generate(ctx, U, V, W, rank, fcfg, seed, iteration, nullptr, B, &A);
+    if (rc) return rc;
+    const size_t Mv = (size_t)fcfg->n_variants;
+    HIP_TRY(ctx, hipMemcpy(outU, A.outU, Mv * rank * A.len[0], hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(outV, A.outV, Mv * rank * A.len[1], hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(outW, A.outW, Mv * rank * A.len[2], hipMemcpyDeviceToHost));
+    if (n_flips) HIP_TRY(ctx, hipMemcpy(n_flips, A.n_done, sizeof(int32_t) * Mv, hipMemcpyDeviceToHost));
+    return CSE_OK;
+}
+
+int32_t cse_run_flips(cse_ctx* ctx, const int8_t* U, const int8_t* V, const int8_t* W, int32_t rank,
+                      const cse_flip_cfg* fcfg, const cse_run_cfg* cfg, int32_t patience, int32_t max_iterations,
+                      void* stream, int32_t* run_id, int32_t* iterations) {
+    if (!ctx || !run_id) return CSE_EINVAL;
+    int rc = validate_flip(ctx, U, V, W, rank, fcfg);
+    if (rc) return rc;
+    rc = validate_cfg(ctx, cfg);
+    if (rc) return rc;
+    if (cfg->iteration != 0) return fail(ctx, CSE_EINVAL, "the flip mode starts at iteration 0");
+    if (max_iterations < 1 || max_iterations > 1024 || patience < 0)
+        return fail(ctx, CSE_EINVAL, "iterations out of range");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    const int Mv = fcfg->n_variants;
+    const int len[3] = {fcfg->n * fcfg->m, fcfg->m * fcfg->p, fcfg->n * fcfg->p};
+    FlipRun R;
+    R.n = fcfg->n;
+    R.m = fcfg->m;
+    R.p = fcfg->p;
+    R.r = rank;
+    FlipBufs B;
+    unsigned long long* d_st = nullptr;
+    unsigned long long* d_key = nullptr;
+    HIP_TRY(ctx, hipMalloc((void**)&d_st, 64));
+    if (hipMalloc((void**)&d_key, sizeof(unsigned long long) * 3 * Mv) != hipSuccess) {
+        (void)hipFree(d_st);
+        return fail(ctx, CSE_EHIP, "hipMalloc of %d argmin keys failed", 3 * Mv);
+    }
+    int it = 0, unchanged = 0;
+    std::vector<int32_t> sids, jobs;
+    auto cleanup = [&]() {
+        for (int j : jobs) (void)release_job(ctx, j);
+        for (int sid : sids) {
+            for (int c = 0; c < ctx->schemes[sid].n_comp; ++c) free_component(ctx->schemes[sid].comp[c]);
+            ctx->schemes.erase(sid);
+        }
+        jobs.clear();
+        sids.clear();
+    };
+    while (rc == CSE_OK) {
+        csek::FlipArgs A{};
+        rc = flip_generate(ctx, U, V, W, rank, fcfg, cfg->seed, (uint32_t)it, s, B, &A);
+        if (rc) break;
+        // Each variant as a scheme: U_v, V_v and W_v^T, analysed on the device.
+        for (int v = 0; v < Mv && rc == CSE_OK; ++v) {
+            SchemeRec sc;
+            sc.n_comp = 3;
+            const int8_t* comp[3] = {A.outU + (size_t)v * rank * len[0], A.outV + (size_t)v * rank * len[1],
+                                     A.outWt + (size_t)v * rank * len[2]};
+            const int rows[3] = {rank, rank, len[2]}, cols[3] = {len[0], len[1], rank};
+            int c = 0;
+            for (; c < 3 && rc == CSE_OK; ++c)
+                rc = load_component_device(ctx, comp[c], rows[c], cols[c], s, d_st, &sc.comp[c]);
+            if (rc) {
+                for (int k = 0; k + 1 < c; ++k) free_component(sc.comp[k]);
+                break;
+            }
+            const int id = ctx->next_scheme++;
+            ctx->schemes[id] = sc;
+            sids.push_back(id);
+        }
+        if (rc) break;
+        // All variants in one batch: variant v with seed + v and this iteration's draws.
+        std::vector<cse_run_cfg> cfgs((size_t)Mv, *cfg);
+        for (int v = 0; v < Mv; ++v) {
+            cfgs[v].seed = cfg->seed + (uint64_t)v;
+            cfgs[v].iteration = (uint32_t)it;
+        }
+        int bid = -1;
+        rc = create_batch(ctx, sids.data(), cfgs.data(), Mv, stream, &bid);
+        if (rc) break;
+        jobs = ctx->batches[bid].jobs;
+        rc = start_batch(ctx, bid);
+        if (rc) {
+            jobs.clear();  // dropped with the batch
+            break;
+        }
+        rc = wait_batch(ctx, ctx->batches[bid]);
+        if (rc) break;
+        // Each variant's best unit per component: (cost, process) argmin.
+        hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((6 * Mv + 255) / 256), dim3(256), 0, s, (int32_t*)d_key,
+                           6 * Mv, -1);
+        for (int v = 0; v < Mv; ++v)
+            for (int c = 0; c < 3; ++c)
+                hipLaunchKernelGGL(csek::driver_argmin_kernel, dim3((cfg->n_proc + 255) / 256), dim3(256), 0, s,
+                                   ctx->jobs[jobs[v]].cj[c].st.cost, cfg->n_proc, d_key + 3 * v + c);
+        std::vector<unsigned long long> key((size_t)3 * Mv);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(key.data(), d_key, sizeof(unsigned long long) * 3 * Mv, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = fail(ctx, CSE_EHIP, "variant bests: %s", hipGetErrorString(e));
+            break;
+        }
+        int best_v = 0;
+        int32_t best_t = -1;
+        for (int v = 0; v < Mv; ++v) {
+            int32_t t = 0;
+            for (int c = 0; c < 3; ++c) t += (int32_t)(key[3 * v + c] >> 32);
+            if (best_t < 0 || t < best_t) {
+                best_t = t;
+                best_v = v;
+            }
+        }
+        if (R.best_total < 0 || best_t < R.best_total) {
+            R.best_total = best_t;
+            R.variant = best_v;
+            R.iteration = it;
+            R.U.resize((size_t)rank * len[0]);
+            R.V.resize((size_t)rank * len[1]);
+            R.W.resize((size_t)rank * len[2]);
+            e = hipMemcpy(R.U.data(), A.outU + (size_t)best_v * rank * len[0], R.U.size(), hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(R.V.data(), A.outV + (size_t)best_v * rank * len[1], R.V.size(), hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(R.W.data(), A.outW + (size_t)best_v * rank * len[2], R.W.size(), hipMemcpyDeviceToHost);
+            const JobRec& J = ctx->jobs[jobs[best_v]];
+            for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+                const uint32_t proc = (uint32_t)(key[3 * best_v + c] & 0xFFFFFFFFu);
+                const int nf = std::max(1, ctx->schemes[sids[best_v]].comp[c].n_fmax);
+                int32_t L = 0;
+                R.best_cost[c] = (int32_t)(key[3 * best_v + c] >> 32);
+                e = hipMemcpy(&L, J.cj[c].st.t + proc, 4, hipMemcpyDeviceToHost);
+                R.keys[c].assign((size_t)std::max(0, L), 0u);
+                if (e == hipSuccess && L > 0)
+                    e = hipMemcpy(R.keys[c].data(), J.cj[c].st.prog + (size_t)proc * nf, (size_t)L * 4,
+                                  hipMemcpyDeviceToHost);
+            }
+            if (e != hipSuccess) {
+                rc = fail(ctx, CSE_EHIP, "best variant readback: %s", hipGetErrorString(e));
+                break;
+            }
+        }
+        unchanged = (!R.totals.empty() && R.best_total == R.totals.back()) ? unchanged + 1 : 0;
+        R.totals.push_back(R.best_total);
+        cleanup();
+        ++it;
+        if (unchanged >= patience || it >= max_iterations) break;
+    }
+    cleanup();
+    (void)hipFree(d_st);
+    (void)hipFree(d_key);
+    if (iterations) *iterations = it;
+    if (rc) return rc;
+    const int id = ctx->next_flip++;
+    ctx->flips[id] = std::move(R);
+    *run_id = id;
+    return CSE_OK;
+}
+
+int32_t cse_flip_best(cse_ctx* ctx, int32_t run_id, int8_t* U, int8_t* V, int8_t* W, int32_t best_cost[3],
+                      int32_t* variant, int32_t* iteration, int32_t* totals, int32_t cap, int32_t* n_iter) {
+    if (!ctx) return CSE_EINVAL;
+    auto it = ctx->flips.find(run_id);
+    if (it == ctx->flips.end()) return fail(ctx, CSE_ENOENT, "unknown flip run %d", run_id);
+    const FlipRun& R = it->second;
+    if (U) std::memcpy(U, R.U.data(), R.U.size());
+    if (V) std::memcpy(V, R.V.data(), R.V.size());
+    if (W) std::memcpy(W, R.W.data(), R.W.size());
+    if (best_cost)
+        for (int c = 0; c < 3; ++c) best_cost[c] = R.best_cost[c];
+    if (variant) *variant = R.variant;
+    if (iteration) *iteration = R.iteration;
+    if (n_iter) *n_iter = (int32_t)R.totals.size();
+    if (totals) {
+        if (cap < (int32_t)R.totals.size()) return fail(ctx, CSE_ERANGE, "cap %d < %zu", cap, R.totals.size());
+        for (size_t i = 0; i < R.totals.size(); ++i) totals[i] = R.totals[i];
+    }
+    return CSE_OK;
+}
+
+int32_t cse_flip_program(cse_ctx* ctx, int32_t run_id, int32_t comp, int32_t* triples, int32_t cap, int32_t* n_fresh,
+                         int32_t* needed) {
+    if (!ctx) return CSE_EINVAL;
+    auto it = ctx->flips.find(run_id);
+    if (it == ctx->flips.end()) return fail(ctx, CSE_ENOENT, "unknown flip run %d", run_id);
+    if (comp < 0 || comp > 2) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    const std::vector<uint32_t>& k = it->second.keys[comp];
+    const int len = (int)k.size();
+    if (n_fresh) *n_fresh = len;
+    if (needed) *needed = len;
+    if (cap < len || (!triples && len > 0)) return fail(ctx, CSE_ERANGE, "cap %d < %d", cap, len);
+    for (int i = 0; i < len; ++i) {
+        triples[3 * i + 0] = (int32_t)(k[i] >> 16);
+        triples[3 * i + 1] = (int32_t)((k[i] >> 1) & 0x7FFFu);
+        triples[3 * i + 2] = (k[i] & 1u) ? -1 : 1;
+    }
+    return CSE_OK;
+}
+
+int32_t cse_flip_release(cse_ctx* ctx, int32_t run_id) {
+    if (!ctx) return CSE_EINVAL;
+    if (!ctx->flips.erase(run_id)) return fail(ctx, CSE_ENOENT, "unknown flip run %d", run_id);
+    return CSE_OK;
 }
 
 }  // extern "C"

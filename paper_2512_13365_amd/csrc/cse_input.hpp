@@ -71,6 +71,26 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
     return before + incl - v;
 }
 
+// Validation and sizes of a device-resident input (Sec. 3.2.1): per row its
+// nonzeros r; st[0] += sum r, st[1] += sum r (r - 1) / 2 (pair occurrences),
+// st[2] += sum (r - 1) (the naive count), st[3] counts entries outside
+// {-1, 0, 1}, st[4] counts all-zero rows.  st starts at zero.
+__global__ void input_stats_kernel(const int8_t* __restrict__ A, int rows, int cols, unsigned long long* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    long long r = 0, bad = 0;
+    for (int j = 0; j < cols; ++j) {
+        const int v = A[(size_t)i * cols + j];
+        r += v != 0;
+        bad += v < -1 || v > 1;
+    }
+    atomicAdd(&st[0], (unsigned long long)r);
+    atomicAdd(&st[1], (unsigned long long)(r * (r - 1) / 2));
+    if (r > 0) atomicAdd(&st[2], (unsigned long long)(r - 1));
+    if (bad) atomicAdd(&st[3], (unsigned long long)bad);
+    if (r == 0) atomicAdd(&st[4], 1ull);
+}
+
 // P[v W + w] bit i: A[64 w + i][v] > 0; N likewise for < 0.
 __global__ void input_columns_kernel(const int8_t* __restrict__ A, int rows, int cols, int W, uint64_t* P,
                                      uint64_t* N) {

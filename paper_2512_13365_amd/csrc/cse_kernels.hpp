@@ -19,15 +19,15 @@
 //   newc[]                  the pairs of the fresh variable (update scratch);
 //   M[], wt[]               per-variable candidate masks and weights (the
 //                           mask form of gi; they share newc's region);
-//   cand2[], tl[], tp[], pl[], rng[], remap[], kpre[]
+//   cand2[], tl[], tinv[], pl[], rng[], remap[], kpre[]
 //                           for large candidate sets (the range form of gi):
 //                           a second candidate buffer, the second ordering
-//                           (by second variable) plain and packed with
-//                           weights, weight bit-planes, per-variable ranges
+//                           (by second variable) and each candidate's place
+//                           in it, weight bit-planes, per-variable ranges
 //                           and the index map of the update.
 // The lists live in LDS; the rest lives in LDS too, or, for systems whose
 // state would leave fewer than four units per CU, in a per-unit slot in HBM
-// (optionally with tp, pl and rng in LDS).  A slot also records which state
+// (optionally with tinv, pl and rng in LDS).  A slot also records which state
 // it holds, so a unit that was not restarted resumes from it at its next
 // launch instead of replaying its program.
 // The pair count of (a, b, +) is popc(Pa & Pb) + popc(Na & Nb) and of
@@ -82,8 +82,9 @@ __device__ __forceinline__ uint32_t domain(uint32_t tag, uint32_t comp, uint32_t
 }
 // A unit's epoch may pass the 10 bits of word 1 (restarts from sharing
 // events and outer iterations add up): its higher bits go to the upper half
-// of counter word 3 of the step and coin draws, whose lower half is 0 or the
-// coin block index (< 2^16), so no key is reused.
+// of counter word 3 of the step and coin draws, whose lower half is 0 or a
+// coin stream's block index (< 2^15) and side bit (2^15), so no key is
+// reused.
 __device__ __forceinline__ uint32_t epoch_high(uint32_t epoch) { return (epoch >> 10) << 16; }
 
 // floor(u * n / 2^32)
@@ -194,7 +195,7 @@ struct Segment {
 // weight bit-planes of both orderings instead of the gi masks.  m_words is
 // the mask capacity in 64-bit words.
 struct BulkLayout {
-    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, tp, pl, bytes;
+    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, tinv, pl, bytes;
 };
 // Words of one bit-plane (one bit per candidate, 64-candidate granules).
 __host__ __device__ inline int plane_words(int m_cap) { return 2 * ((m_cap + 63) / 64); }
@@ -220,7 +221,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
         L.M = o;
         L.wt = o + (size_t)m_words * 8;
         o += gi > up ? gi : up;
-        L.cand2 = L.tl = L.remap = L.kpre = L.rng = L.tp = L.pl = o;
+        L.cand2 = L.tl = L.remap = L.kpre = L.rng = L.tinv = L.pl = o;
         L.bytes = (o + 255) & ~size_t(255);
         return L;
     }
@@ -232,7 +233,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     L.kpre = o;  o += ((size_t)m_cap * 4 + 8) & ~size_t(7);
     o = (o + 15) & ~size_t(15);
     L.rng = o;   o += (size_t)n_vmax * 16;
-    L.tp = o;    o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
+    L.tinv = o;  o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
     L.pl = o;    o += (size_t)2 * kbits * plane_words(m_cap) * 4;
     L.bytes = (o + 255) & ~size_t(255);
     return L;
@@ -241,17 +242,17 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
 __host__ __device__ inline size_t list_bytes(int n_vmax) { return ((size_t)n_vmax * 8 + 15) & ~size_t(15); }
 
 // Units with state in HBM slots may keep the per-step tables of the range
-// form of gi (ranges, second ordering with weights, weight bit-planes) in
+// form of gi (ranges, places in the second ordering, weight bit-planes) in
 // LDS after their lists instead of in the slot: offsets in LDS, and bytes
 // of LDS in all.
 struct TableLayout {
-    size_t rng, tp, pl, bytes;
+    size_t rng, tinv, pl, bytes;
 };
 __host__ __device__ inline TableLayout table_layout(int n_vmax, int m_cap, int kbits) {
     TableLayout T;
     size_t o = list_bytes(n_vmax);
     T.rng = o;  o += (size_t)n_vmax * 16;
-    T.tp = o;   o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
+    T.tinv = o; o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
     T.pl = o;   o += (size_t)2 * kbits * plane_words(m_cap) * 4;
     T.bytes = (o + 15) & ~size_t(15);
     return T;
@@ -737,13 +738,13 @@ __device__ void build_tl(const uint64_t* colP, const uint64_t* colN, const uint3
 // Per-step tables of the range form of gi, indexed by live position v:
 // rng[v] = (first, end) of the canonical-list range of the pairs whose first
 // variable is v, then (first, end) of the range of the second ordering
-// holding the pairs whose second variable is v.  tp[i] packs entry i of the
-// second ordering with its weight: index | (c - 1) << 23.  pl holds kbits
-// bit-planes of the weights c - 1 in canonical order, then kbits in the
-// second ordering (bit i of word w is candidate 32 w + i).  Returns the
-// number of planes in use: the bit length of the largest weight.
+// holding the pairs whose second variable is v.  tinv[q] is the place of
+// candidate q in the second ordering.  pl holds kbits bit-planes of the
+// weights c - 1 in canonical order, then kbits in the second ordering (bit
+// i of word w is candidate 32 w + i).  Returns the number of planes in use:
+// the bit length of the largest weight.
 __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
-                          int32_t* rng, uint32_t* tp, uint32_t* pl, int pw, int kbits) {
+                          int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits) {
     const int l = lane_id();
     for (int i = l; i < 4 * n_live; i += kWave) rng[i] = 0;
     __syncthreads();
@@ -774,7 +775,7 @@ __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const
             if (a != na) rng[4 * va + 1] = i + 1;
             if (b != pb) rng[4 * vb + 2] = i;
             if (b != nb) rng[4 * vb + 3] = i + 1;
-            tp[i] = q | ((uint32_t)wq << 23);
+            tinv[q] = i;
         }
         wmax = w > wmax ? w : wmax;
         const int word = 2 * (base / kWave);
@@ -793,22 +794,22 @@ __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const
     return K;
 }
 
-// The coin stream of one candidate p: bit j is coin j, taken from Philox
-// block (proc, dw, key(p), j div 128 | eh), bit j mod 32 of its word
-// (j mod 128) / 32, eh the high epoch bits.  Holds the current block and,
-// once needed, the next.
+// One coin stream of candidate p: bit j is coin j, taken from Philox block
+// (proc, dw, key(p), j div 128 | eh), bit j mod 32 of its word
+// (j mod 128) / 32, eh the stream's side bit and the high epoch bits.  Holds
+// the current block and, once needed, the next.
 struct CoinStream {
     uint32_t proc, dw, kp, eh, k0, k1;
     int cb;
     bool has_nb;
     uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
 
+    // No block is drawn until a coin is needed.
     __device__ void init(uint32_t proc_, uint32_t dw_, uint32_t kp_, uint32_t eh_, uint32_t k0_, uint32_t k1_) {
         proc = proc_; dw = dw_; kp = kp_; eh = eh_; k0 = k0_; k1 = k1_;
-        cb = 0;
+        cb = -1;
         has_nb = false;
-        const U4 x = philox10(proc, dw, kp, eh, k0, k1);
-        a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
+        a0 = a1 = a2 = a3 = 0u;
         b0 = b1 = b2 = b3 = 0u;
     }
     __device__ void next_block() {
@@ -875,23 +876,24 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, 
 }
 
 // Greedy-Intersections over per-variable ranges (any number of candidates).
-// For p = (a, b, s), a < b, the candidates sharing a variable with p, in
-// canonical order, are: the pairs (x, a) and (x, b) with x < a, merged by x;
-// the pairs (a, y) (a canonical range holding p and its twin of the other
-// sign); the pairs (x, b) with a < x < b (a range of the second ordering);
-// the pairs (b, y) (a canonical range).  Lane p merges the first part
-// candidate by candidate and sums the three ranges through the weight
-// bit-planes; coins are consumed in that order, as in the other forms.
+// The intersecting candidates of p = (a, b), a < b, and their coin streams:
+//   A_p (stream 0): the candidates holding a, in canonical order: the pairs
+//       (x, a), x < a (a's range of the second ordering), then the pairs
+//       (a, y) (a's canonical range, which holds p and its twin; p skipped);
+//   B_p (stream 1): the candidates holding b but not a: the pairs (x, b),
+//       x < b, without (a, b, +-) (b's range of the second ordering, where
+//       those entries sit together at tinv of the first), then the pairs
+//       (b, y) (b's canonical range).
+// Every part is a contiguous range whose members take consecutive coins, so
+// lane p sums them 32 candidates at a time through the weight bit-planes.
 __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
-                                const uint32_t* tp, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
+                                const int32_t* tinv, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
                                 uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
                                 long long* n_int, long long* n_blk) {
     const int l = lane_id();
     const int T = total_profit(cand, m);
     const uint32_t* plc = pl;               // canonical order
     const uint32_t* plt = pl + kbits * pw;  // second ordering
-    constexpr uint32_t kQ = (1u << 23) - 1u;
-    constexpr uint32_t kEnd = 0xFFFFFFFFu;
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
@@ -903,62 +905,28 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             const int va = vpos[key_a(kp) - 1], vb = vpos[key_b(kp) - 1];
             const int4 ra = *(const int4*)(rng + 4 * va);
             const int4 rb = *(const int4*)(rng + 4 * vb);
-            // The twin (a, b, other sign) is adjacent in canonical order.
+            // The twin (a, b, other sign) is adjacent in both orderings.
             const bool tprev = p > 0 && ((uint32_t)cand[p - 1] >> 1) == (kp >> 1);
             const bool tnext = p + 1 < m && ((uint32_t)cand[p + 1] >> 1) == (kp >> 1);
-            const uint32_t q_lo = (uint32_t)(tprev ? p - 1 : p);
+            const int q_lo = tprev ? p - 1 : p;
             const int n_ab = (tprev || tnext) ? 2 : 1;
+            const int t_ab = tinv[q_lo];
+            int I = 0, X = 0, ja = 0, jb = 0;
             CoinStream co;
             co.init(proc, dw, kp, eh, k0, k1);
-            int I = 0, X = 0, j = 0;
-            // 1. (x, a) and (x, b), x < a: every (x, a) entry, and the (x, b)
-            //    entries before (a, b).
-            // Each stream keeps its head and the entry after it, so the load
-            // issued when a stream advances is needed one advance later.
-            int ia = ra.z, ib = rb.z;
-            uint32_t ea = ia < ra.w ? tp[ia] : kEnd;
-            uint32_t ea1 = ia + 1 < ra.w ? tp[ia + 1] : kEnd;
-            uint32_t eb = ib < rb.w ? tp[ib] : kEnd;
-            uint32_t eb1 = ib + 1 < rb.w ? tp[ib + 1] : kEnd;
-            uint32_t cw = co.word(0);
-            int left = 32;
-            for (;;) {
-                const uint32_t qa = ea == kEnd ? kEnd : (ea & kQ);
-                const uint32_t qb = (eb & kQ) < q_lo ? (eb & kQ) : kEnd;
-                if ((qa & qb) == kEnd) break;
-                const bool ta = qa < qb;
-                const uint32_t w = (ta ? ea : eb) >> 23;
-                I += (int)w;
-                X += (int)((cw & 1u) * w);
-                cw >>= 1;
-                ++j;
-                if (--left == 0) {
-                    cw = co.word(j >> 5);
-                    left = 32;
-                }
-                if (ta) {
-                    ++ia;
-                    ea = ea1;
-                    ea1 = ia + 1 < ra.w ? tp[ia + 1] : kEnd;
-                } else {
-                    ++ib;
-                    eb = eb1;
-                    eb1 = ib + 1 < rb.w ? tp[ib + 1] : kEnd;
-                }
-            }
-            // 2. (a, y): the canonical range of a without p.
-            plane_window(plc, pw, K, ra.x, p, j, co, I, X);
-            plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
-            // 3. (x, b), a < x < b: after (a, b) in b's range of the second ordering.
-            plane_window(plt, pw, K, ib + n_ab, rb.w, j, co, I, X);
-            // 4. (b, y): the canonical range of b.
-            plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
+            plane_window(plt, pw, K, ra.z, ra.w, ja, co, I, X);
+            plane_window(plc, pw, K, ra.x, p, ja, co, I, X);
+            plane_window(plc, pw, K, p + 1, ra.y, ja, co, I, X);
+            co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
+            plane_window(plt, pw, K, rb.z, t_ab, jb, co, I, X);
+            plane_window(plt, pw, K, t_ab + n_ab, rb.w, jb, co, I, X);
+            plane_window(plc, pw, K, rb.x, rb.y, jb, co, I, X);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
             if (hsc > best_h) { best_h = hsc; best_p = p; }
-            my_int += j;
-            my_blk += (j + 127) >> 7;
+            my_int += ja + jb;
+            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
         }
     }
     *n_int = wave_sum(my_int);
@@ -969,9 +937,11 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
 // Greedy-Intersections (Sec. 3.4.2).  Lane p scores candidate p:
 //   2^32 H = (c_p - 1) 2^32 + alpha_q (D_p 2^16 + beta_q X_p)
 // with D_p the profit of the disjoint candidates and X_p that of the
-// intersecting candidates whose coin is 1.  The j-th intersecting candidate
-// of p in canonical order uses bit j mod 128 of Philox block
-// (proc, COIN|comp|epoch|step, key(p), j div 128 | eh), eh the high epoch
+// intersecting candidates whose coin is 1.  The intersecting candidates of
+// p = (a, b) form two lists in canonical order, those holding a (p's twin
+// included) and those holding b but not a; the i-th member of a list uses
+// bit i mod 128 of Philox block (proc, COIN|comp|epoch|step, key(p),
+// i div 128 | side | eh), side 0 or 2^15 for the list, eh the high epoch
 // bits.  This form visits every q (the O(m^2) scan); it serves when the
 // masks of the sparse form do not fit.
 __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
@@ -986,30 +956,40 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
         const int ap = key_a(kp), bp = key_b(kp);
-        U4 blk = philox10(proc, dw, kp, eh, k0, k1);
-        int D = 0, X = 0, j = 0;
+        U4 ba = {0u, 0u, 0u, 0u}, bb = {0u, 0u, 0u, 0u};
+        int D = 0, X = 0, ja = 0, jb = 0;
         for (int q = 0; q < m; ++q) {
             const uint64_t eq = cand[q];
             const uint32_t kq = (uint32_t)eq;
             const int qa = key_a(kq), qb = key_b(kq);
             const int wq = entry_c(eq) - 1;
-            const bool inter = (qa == ap) | (qa == bp) | (qb == ap) | (qb == bp);
-            if (!inter) {
+            const bool sa = (qa == ap) | (qb == ap);
+            const bool sb = (qa == bp) | (qb == bp);
+            if (!sa && !sb) {
                 D += wq;
             } else if (q != p) {
-                if (j != 0 && (j & 127) == 0) blk = philox10(proc, dw, kp, (uint32_t)(j >> 7) | eh, k0, k1);
+                int j;
+                U4 blk;
+                if (sa) {
+                    if ((ja & 127) == 0) ba = philox10(proc, dw, kp, (uint32_t)(ja >> 7) | eh, k0, k1);
+                    j = ja++;
+                    blk = ba;
+                } else {
+                    if ((jb & 127) == 0) bb = philox10(proc, dw, kp, (uint32_t)(jb >> 7) | 0x8000u | eh, k0, k1);
+                    j = jb++;
+                    blk = bb;
+                }
                 const int r = j & 127;
                 const uint32_t word = r < 32 ? blk.x : r < 64 ? blk.y : r < 96 ? blk.z : blk.w;
                 if ((word >> (r & 31)) & 1u) X += wq;
-                ++j;
             }
         }
         if (valid) {
             const long long wp = (long long)entry_c(ep) - 1;
             const long long h = (wp << 32) + (long long)aq * (((long long)D << 16) + (long long)bq * X);
             if (h > best_h) { best_h = h; best_p = p; }
-            my_int += j;
-            my_blk += (j + 127) >> 7;
+            my_int += ja + jb;
+            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
         }
     }
     *n_int = wave_sum64(my_int);
@@ -1019,11 +999,33 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
 
 // Greedy-Intersections, sparse form: M[v] marks (bit i of 32-bit word w)
 // the candidates 32 w + i that contain the live variable at position v.
-// Lane p walks the set bits of M[a] | M[b] (minus p itself) in increasing
-// index, i.e. exactly its intersecting candidates in canonical order, so the
-// coin order is the same as the other forms'; each word's members take the
-// next 32-coin window.  D_p = T - (c_p - 1) - I_p with I_p the profit of all
-// intersecting candidates.  wt[q] = c_q - 1 is filled on the way.
+// Lane p walks the set bits of M[a] (minus p itself), then those of
+// M[b] & ~M[a], in increasing index: the two coin lists of the other forms
+// (candidates holding a, twin included; those holding b only), each taking
+// its own stream, the members of a word the next 32-coin window.
+// D_p = T - (c_p - 1) - I_p with I_p the profit of all intersecting
+// candidates.  wt[q] = c_q - 1 is filled on the way.
+__device__ __forceinline__ void mask_walk(const uint32_t* Ma, const uint32_t* Mb, int nw, int self_w,
+                                          uint32_t self_bit, const uint16_t* wt, CoinStream& co, int& I, int& X,
+                                          int& j) {
+    for (int w = 0; w < nw; ++w) {
+        uint32_t u = Ma[w] & (w == self_w ? ~self_bit : 0xFFFFFFFFu);
+        if (Mb) u = Mb[w] & ~Ma[w];
+        if (u == 0) continue;
+        uint32_t cw = co.bits32(j);
+        j += __popc(u);
+        const uint16_t* wrow = wt + (w << 5);
+        do {
+            const int bit = __builtin_ctz(u);
+            u &= u - 1u;
+            const uint32_t wq = wrow[bit];
+            I += (int)wq;
+            X = mad_u24(cw & 1u, wq, X);
+            cw >>= 1;
+        } while (u);
+    }
+}
+
 __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos, int n_live, uint64_t* M64,
                                 uint16_t* wt, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc,
                                 uint32_t dw, uint32_t eh, long long* n_int, long long* n_blk) {
@@ -1056,37 +1058,23 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
         const bool valid = p < m;
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
-        CoinStream co;
-        co.init(proc, dw, kp, eh, k0, k1);
         if (valid) {
             const uint32_t* Ma = M + vpos[key_a(kp) - 1] * nw;
             const uint32_t* Mb = M + vpos[key_b(kp) - 1] * nw;
             const int self_w = p >> 5;
             const uint32_t self_bit = 1u << (p & 31);
-            int I = 0, X = 0, j = 0;
-            // Word by word (the same word in every lane); coins j .. j+31 are
-            // the window for the word's members, taken in increasing index.
-            for (int w = 0; w < nw; ++w) {
-                uint32_t u = (Ma[w] | Mb[w]) & (w == self_w ? ~self_bit : 0xFFFFFFFFu);
-                if (u == 0) continue;
-                uint32_t cw = co.bits32(j);
-                j += __popc(u);
-                const uint16_t* wrow = wt + (w << 5);
-                do {
-                    const int bit = __builtin_ctz(u);
-                    u &= u - 1u;
-                    const uint32_t wq = wrow[bit];
-                    I += (int)wq;
-                    X = mad_u24(cw & 1u, wq, X);
-                    cw >>= 1;
-                } while (u);
-            }
+            int I = 0, X = 0, ja = 0, jb = 0;
+            CoinStream co;
+            co.init(proc, dw, kp, eh, k0, k1);
+            mask_walk(Ma, nullptr, nw, self_w, self_bit, wt, co, I, X, ja);
+            co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
+            mask_walk(Ma, Mb, nw, self_w, self_bit, wt, co, I, X, jb);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
             if (hsc > best_h) { best_h = hsc; best_p = p; }
-            my_int += j;
-            my_blk += (j + 127) >> 7;
+            my_int += ja + jb;
+            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
         }
     }
     *n_int = wave_sum(my_int);
@@ -1250,7 +1238,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     int32_t* kpre = (int32_t*)(bulk + BL.kpre);
     const TableLayout TB = table_layout(n_vmax, C.m_cap, C.kbits);
     int32_t* rng = TL ? (int32_t*)((char*)smem + TB.rng) : (int32_t*)(bulk + BL.rng);
-    uint32_t* tp = TL ? (uint32_t*)((char*)smem + TB.tp) : (uint32_t*)(bulk + BL.tp);
+    int32_t* tinv = TL ? (int32_t*)((char*)smem + TB.tinv) : (int32_t*)(bulk + BL.tinv);
     uint32_t* pl = TL ? (uint32_t*)((char*)smem + TB.pl) : (uint32_t*)(bulk + BL.pl);
     const int pw = plane_words(C.m_cap);
     uint32_t* live = (uint32_t*)lists;
@@ -1400,8 +1388,8 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             const uint32_t eh = epoch_high((uint32_t)epoch);
             if constexpr (ADJ) {
-                const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tp, pl, pw, C.kbits);
-                pick = select_gi_planes(cand, m, vpos, rng, tp, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
+                const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
+                pick = select_gi_planes(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
                                         dw, eh, &n_int, &n_blk);
             } else if (n_live * ((m + 31) / 32) <= 2 * C.m_words)
                 pick = select_gi_sparse(cand, m, vpos, n_live, M, wt, alpha_q, beta_q, k0, k1, proc, dw, eh,

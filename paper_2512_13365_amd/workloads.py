@@ -19,6 +19,7 @@ number, drawn in a fixed order, so every input is reproducible.
 from __future__ import annotations
 
 import hashlib
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -221,3 +222,40 @@ WORKLOADS = {
     "batch": batch_uneven,
     "serve": serving_stream,
 }
+
+DIGEST_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workload_digests.txt")
+
+
+def workload_digest(wl: Workload) -> str:
+    """sha256 over every input matrix of a workload (and its arrival times)."""
+    arrs = [A for sc in wl.schemes for A in sc.systems]
+    if wl.arrivals_s is not None:
+        arrs.append(wl.arrivals_s)
+    return digest(*arrs)
+
+
+def stored_digests() -> dict:
+    """{workload name: sha256} as persisted in workload_digests.txt."""
+    out = {}
+    with open(DIGEST_FILE) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if len(line) == 2:
+                out[line[0]] = line[1]
+    return out
+
+
+def write_digests() -> None:
+    """Persist the digest of every workload's inputs (run when a generator
+    is deliberately changed; the tests check the inputs still match)."""
+    lines = ["# sha256 of each workload's inputs (workloads.workload_digest); written by",
+             "# python -m paper_2512_13365_amd.workloads"]
+    for fn in WORKLOADS.values():
+        wl = fn()
+        lines.append(f"{wl.name} {workload_digest(wl)}")
+    with open(DIGEST_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    write_digests()

@@ -164,3 +164,33 @@ def brute_force_optimum(A0) -> int:
         return best
 
     return naive - best_saving(canon(rows))
+
+
+def standard_scheme(n, m, p):
+    """The definition of the product C = A B as a scheme of rank n m p: one
+    product A_ij B_jk per (i, j, k), added into C_ik.  U over A (n x m), V
+    over B (m x p), W over C (n x p), all row-major."""
+    r = n * m * p
+    U = np.zeros((r, n * m), np.int8)
+    V = np.zeros((r, m * p), np.int8)
+    W = np.zeros((r, n * p), np.int8)
+    t = 0
+    for i in range(n):
+        for j in range(m):
+            for k in range(p):
+                U[t, i * m + j] = V[t, j * p + k] = W[t, i * p + k] = 1
+                t += 1
+    return U, V, W
+
+
+def brent_ok(U, V, W, n, m, p) -> bool:
+    """The Brent equations: sum_t U_t[i,j] V_t[j',k] W_t[i',k'] equals 1 when
+    j = j', i = i', k = k' and 0 otherwise, i.e. the products reconstruct
+    C = A B for every A and B."""
+    T = np.einsum("ta,tb,tc->abc", U.astype(np.int64), V.astype(np.int64), W.astype(np.int64))
+    ref = np.zeros((n * m, m * p, n * p), np.int64)
+    for i in range(n):
+        for j in range(m):
+            for k in range(p):
+                ref[i * m + j, j * p + k, i * p + k] = 1
+    return bool(np.array_equal(T, ref))

@@ -133,3 +133,15 @@ def test_null_handles_rejected_before_any_device_call():
     assert checked == len(cse.EXPORTS) - len(skip)
     assert L.cse_last_error(None) == b"null context"
     L.cse_server_destroy(None)
+
+
+def test_workload_inputs_match_persisted_digests():
+    """Every workload's inputs regenerate to the sha256 persisted beside the
+    generator (a changed numpy stream or generator would change the inputs
+    of every parity test and measurement silently)."""
+    from paper_2512_13365_amd import workloads
+    stored = workloads.stored_digests()
+    assert len(stored) == len(workloads.WORKLOADS)
+    for fn in workloads.WORKLOADS.values():
+        wl = fn()
+        assert stored[wl.name] == workloads.workload_digest(wl), wl.name

@@ -122,6 +122,36 @@ def test_mix_single_weight_is_that_strategy(gpu, oracle):
         assert np.array_equal(got[0]["cost"], plain["cost"]), name
 
 
+def test_device_resident_input_load(gpu, oracle):
+    """cse_scheme_load_device: systems already in HBM are validated and
+    analysed on the device; the job equals the oracle's (and so the
+    host-loaded job); bad entries and zero rows are refused."""
+    cse, ctx, torch = gpu
+    wl = workloads.plain_4x4x4(n_proc=128)
+    S = wl.schemes[0].systems
+    kw = dict(wl.runs[0].as_kwargs(), n_proc=128)
+    st = torch.cuda.current_stream()
+    dev = [torch.from_numpy(A).to("cuda") for A in S]
+    sid = cse.cse_scheme_load_device(ctx, *dev, stream=st)
+    assert cse.cse_scheme_info(ctx, sid) == [(A.shape[0], A.shape[1], oracle.bounds(A)[0], oracle.naive(A)) for A in S]
+    job = cse.cse_launch(ctx, sid, cse.cse_run_cfg(**kw), st)
+    cse.cse_wait(ctx, job)
+    ref = compare(oracle, S, kw, "device load")
+    for c in range(3):
+        got = cse.cse_get_unit_results(ctx, job, c, 128)
+        got["prog"] = cse.cse_get_programs(ctx, job, c, 128, max(1, ref[c]["n_fmax"]))
+        assert_same(got, ref[c], f"device load comp {c}")
+    cse.cse_job_release(ctx, job)
+    cse.cse_scheme_free(ctx, sid)
+    one = cse.cse_scheme_load_device(ctx, dev[2], stream=st)
+    assert cse.cse_scheme_info(ctx, one) == [(16, 49, oracle.bounds(S[2])[0], oracle.naive(S[2]))]
+    cse.cse_scheme_free(ctx, one)
+    for bad in (np.array([[1, 2], [1, 1]], np.int8), np.array([[1, 1], [0, 0]], np.int8)):
+        with pytest.raises(cse.CseError) as e:
+            cse.cse_scheme_load_device(ctx, torch.from_numpy(bad).to("cuda"), stream=st)
+        assert e.value.status == -1
+
+
 def test_step_cap_and_seeds(gpu, oracle):
     A = workloads.random_system(77, 49, 16, 0.3, 1, 8)
     for seed, cap in ((0, 1), (1, 5), (2 ** 40 + 3, 17)):
@@ -249,11 +279,13 @@ def test_batch_equals_separate_jobs(gpu, oracle):
         cse.cse_scheme_free(ctx, sid)
 
 
-@pytest.mark.parametrize("rows,cols,p,cap", [(42, 197, 0.2, 40), (331, 64, 0.12, 25), (64, 331, 0.12, 12)])
+@pytest.mark.parametrize("rows,cols,p,cap", [(42, 197, 0.2, 40), (331, 64, 0.12, 25), (64, 331, 0.12, 12),
+                                             (400, 64, 0.12, 20)])
 def test_hbm_state_large_systems(gpu, oracle, rows, cols, p, cap):
     """Systems whose state exceeds the LDS budget keep it in HBM slots
-    (shapes of the 7x7x4-r197 W^T and the 8x8x8-r331 U and W^T components,
-    the largest of the serving stream)."""
+    (shapes of the 6x7x7-r197 W^T and the 8x8x8-r331 U and W^T components,
+    the largest of the serving stream, and the 400 x 64 stress shape of an
+    8x8x8 scheme of rank 400)."""
     A = workloads.random_system(rows + 7 * cols, rows, cols, p)
     kw = dict(seed=3, n_proc=12, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True, step_cap=cap)
     check_workload(gpu, oracle, [A], kw, f"hbm-state {rows}x{cols}")
@@ -1072,3 +1104,67 @@ def test_units_independent_of_pool_size(gpu):
         small = {k: v for k, v in out[384][c].items() if k != "finish"}
         assert_same(small, big, f"pool size comp {c}")
     cse.cse_scheme_free(ctx, sid)
+
+
+def _flip_schemes():
+    from cse_helpers import standard_scheme
+    g = read_golden("strassen_2x2x2.txt")
+    S = [np.array([[int(x) for x in r] for r in g[k]], np.int8) for k in ("U", "V", "Wt")]
+    out = [((2, 2, 2), (S[0], S[1], np.ascontiguousarray(S[2].T)))]
+    for shape in ((2, 3, 4), (3, 3, 3), (4, 4, 4)):
+        out.append((shape, standard_scheme(*shape)))
+    return out
+
+
+def test_flip_variants_match_oracle(gpu, oracle):
+    """Random flips (Sec. 3.5.3) generated on the device equal the oracle's
+    variant for variant, over three iterations; every variant satisfies the
+    Brent equations."""
+    from cse_helpers import brent_ok
+    cse, ctx, torch = gpu
+    for (n, m, p), (U, V, W) in _flip_schemes():
+        for it in range(3):
+            got = cse.cse_flip_variants(ctx, U, V, W, n, m, p, n_variants=8, max_flips=40, seed=11, iteration=it)
+            for v, (gU, gV, gW, nf) in enumerate(got):
+                rU, rV, rW, rn = oracle.flip_variant(U, V, W, n, m, p, seed=11, variant=v, iteration=it,
+                                                     max_flips=40)
+                assert nf == rn, ((n, m, p), it, v)
+                assert np.array_equal(gU, rU) and np.array_equal(gV, rV) and np.array_equal(gW, rW), \
+                    ((n, m, p), it, v)
+                assert brent_ok(gU, gV, gW, n, m, p)
+
+
+def test_flip_mode_against_oracle(gpu, oracle):
+    """The flip mode: every iteration regenerates the variants and reduces
+    each with its own pool; the best total per iteration, the chosen variant
+    and its component costs equal what the oracle computes from its own
+    variants and pool runs, and the best programs re-expand exactly on the
+    chosen variant (which is a valid scheme)."""
+    from cse_helpers import brent_ok, standard_scheme
+    cse, ctx, torch = gpu
+    n, m, p = 3, 3, 3
+    U, V, W = standard_scheme(n, m, p)
+    kw = dict(seed=21, n_proc=24, weights=dict(workloads.PAPER_WEIGHTS), proc0_greedy=True)
+    M, F, its = 6, 12, 3
+    run, n_it = cse.cse_run_flips(ctx, U, V, W, n, m, p, cse.cse_run_cfg(**kw), n_variants=M, max_flips=F,
+                                  patience=100, max_iterations=its, stream=torch.cuda.current_stream())
+    assert n_it == its
+    best = cse.cse_flip_best(ctx, run, (n, m, p, 27))
+    want_tot, want = [], None
+    for it in range(its):
+        for v in range(M):
+            vU, vV, vW, _ = oracle.flip_variant(U, V, W, n, m, p, seed=21, variant=v, iteration=it, max_flips=F)
+            cfg = oracle.make_cfg(**dict(kw, seed=21 + v, iteration=it))
+            costs = [int(oracle.run_pool(A, cfg, comp=c, n_threads=THREADS)["cost"].min())
+                     for c, A in enumerate((vU, vV, np.ascontiguousarray(vW.T)))]
+            if want is None or sum(costs) < want[0]:
+                want = (sum(costs), v, it, costs, (vU, vV, vW))
+        want_tot.append(want[0])
+    assert best["totals"] == want_tot
+    assert (best["variant"], best["iteration"], best["cost"]) == (want[1], want[2], want[3])
+    assert np.array_equal(best["U"], want[4][0]) and np.array_equal(best["V"], want[4][1])
+    assert np.array_equal(best["W"], want[4][2])
+    assert brent_ok(best["U"], best["V"], best["W"], n, m, p)
+    for c, A in enumerate((best["U"], best["V"], np.ascontiguousarray(best["W"].T))):
+        check_program(A, cse.cse_flip_program(ctx, run, c), best["cost"][c])
+    cse.cse_flip_release(ctx, run)

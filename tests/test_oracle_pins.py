@@ -224,19 +224,25 @@ def test_gi_score_against_float_formula(oracle):
         dw = oracle.domain_word(3, 1, 2, step)
         H = []
         for p, (pa, pb, ps, pc) in enumerate(cands):
-            j = 0
+            # coins: the i-th candidate holding pa (twin included), and the
+            # i-th holding pb but not pa, in canonical order, each list with
+            # its own Philox stream (counter word 3: i div 128, + 2^15 for pb)
+            idx = {pa: 0, pb: 0}
             tot = 0.0
             for q, (qa, qb, qs, qc) in enumerate(cands):
                 if q == p:
                     continue
-                if {pa, pb} & {qa, qb}:
-                    key = (pa << 16) | (pb << 1) | (ps < 0)
-                    blk = oracle.philox4x32_10((proc, dw, key, j // 128), (seed & 0xFFFFFFFF, seed >> 32))
-                    coin = (blk[(j % 128) // 32] >> (j % 32)) & 1
-                    tot += (bq / 65536.0) * (qc - 1) if coin else 0.0
-                    j += 1
-                else:
+                shared = pa if pa in (qa, qb) else pb if pb in (qa, qb) else None
+                if shared is None:
                     tot += qc - 1
+                    continue
+                i = idx[shared]
+                idx[shared] += 1
+                key = (pa << 16) | (pb << 1) | (ps < 0)
+                c3 = i // 128 + (0x8000 if shared == pb else 0)
+                blk = oracle.philox4x32_10((proc, dw, key, c3), (seed & 0xFFFFFFFF, seed >> 32))
+                coin = (blk[(i % 128) // 32] >> (i % 32)) & 1
+                tot += (bq / 65536.0) * (qc - 1) if coin else 0.0
             H.append((pc - 1) + (aq / 65536.0) * tot)
         i, _, _ = oracle.select_gi(cands, aq, bq, seed=seed, proc=proc, comp=1, epoch=2, step=step)
         order = sorted(H, reverse=True)
@@ -360,10 +366,12 @@ def test_gr_exploit_rate(oracle):
 
 
 def test_gi_work_tally_independent_count(oracle):
-    """The gi work tally (n_int = sum over p of the candidates intersecting p,
-    n_blk = sum over p of ceil(n_int(p) / 128) coin blocks) against a count
-    written here from the intersection rule (shared variable index, p itself
-    excluded), on candidate sets large enough that some p exceed 128."""
+    """The gi work tally (n_int = sum over p of the candidates intersecting p;
+    n_blk = the coin blocks, ceil(|A_p| / 128) + ceil(|B_p| / 128) per p with
+    A_p the candidates holding p's first variable and B_p those holding only
+    its second) against a count written here from the intersection rule
+    (shared variable index, p itself excluded), on candidate sets large
+    enough that some lists exceed 128."""
     rng = np.random.default_rng(15)
     big = 0
     for trial in range(40):
@@ -380,10 +388,11 @@ def test_gi_work_tally_independent_count(oracle):
             cands.sort(key=lambda t: (t[0], t[1], t[2] < 0))
         n_int = n_blk = 0
         for p, (pa, pb, _, _) in enumerate(cands):
-            k = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and {pa, pb} & {qa, qb})
-            n_int += k
-            n_blk += -(-k // 128)
-            big += k > 128
+            ka = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and pa in (qa, qb))
+            kb = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and pa not in (qa, qb) and pb in (qa, qb))
+            n_int += ka + kb
+            n_blk += -(-ka // 128) - (-kb // 128)
+            big += max(ka, kb) > 128
         _, got_int, got_blk = oracle.select_gi(cands, int(rng.integers(0, 32768)), 40000, seed=trial)
         assert (got_int, got_blk) == (n_int, n_blk)
     assert big > 0
@@ -523,3 +532,64 @@ def test_gp_matches_independent_potential(oracle):
             assert n_cols == m * max(0, live - 2), (case, n_cols)
         assert oracle.select_gp(A, 0)[0] == oracle.select_g(oracle.analyse(A))
 
+
+
+def _strassen():
+    g = read_golden("strassen_2x2x2.txt")
+    U, V, Wt = (_golden_matrix(g[k]) for k in ("U", "V", "Wt"))
+    return U, V, np.ascontiguousarray(Wt.T)
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (2, 3, 4), (3, 3, 3), "strassen"])
+def test_flip_variants_stay_valid_schemes(oracle, shape):
+    """Random flips (Sec. 3.5.3) keep a scheme a valid matrix multiplication
+    algorithm of the same rank: every variant satisfies the Brent equations
+    (checked by the tensor identity in the test helpers), its coefficients
+    stay ternary and no product loses a factor; variant 0 is the input and
+    the others differ from it; the same draws give the same variant."""
+    from cse_helpers import brent_ok, standard_scheme
+    if shape == "strassen":
+        n = m = p = 2
+        U, V, W = _strassen()
+    else:
+        n, m, p = shape
+        U, V, W = standard_scheme(n, m, p)
+    assert brent_ok(U, V, W, n, m, p)
+    changed = 0
+    for it in range(3):
+        for v in range(8):
+            U2, V2, W2, done = oracle.flip_variant(U, V, W, n, m, p, seed=3, variant=v, iteration=it, max_flips=40)
+            assert brent_ok(U2, V2, W2, n, m, p), (v, it)
+            for M in (U2, V2, W2):
+                assert M.min() >= -1 and M.max() <= 1 and (np.abs(M).sum(axis=1) > 0).all()
+            if v == 0 or shape == "strassen":
+                assert done == 0 and np.array_equal(U2, U) and np.array_equal(V2, V) and np.array_equal(W2, W)
+            else:
+                assert 1 <= done <= 40
+                changed += not (np.array_equal(U2, U) and np.array_equal(V2, V) and np.array_equal(W2, W))
+            again = oracle.flip_variant(U, V, W, n, m, p, seed=3, variant=v, iteration=it, max_flips=40)
+            assert all(np.array_equal(a, b) for a, b in zip(again[:3], (U2, V2, W2)))
+    if shape == "strassen":
+        # No two of Strassen's products share a factor up to sign, so no
+        # flip applies and every variant is the scheme itself.
+        for M in (U, V, W):
+            for i in range(7):
+                for j in range(7):
+                    assert i == j or not (np.array_equal(M[i], M[j]) or np.array_equal(M[i], -M[j]))
+    else:
+        assert changed >= 20
+
+
+def test_flip_breaks_when_the_identity_is_broken(oracle):
+    """The Brent check used above rejects a scheme with one coefficient
+    changed, and one where a flip updates only one of the two products."""
+    from cse_helpers import brent_ok, standard_scheme
+    U, V, W = standard_scheme(2, 2, 2)
+    U2, V2, W2, done = oracle.flip_variant(U, V, W, 2, 2, 2, seed=1, variant=1, iteration=0, max_flips=5)
+    assert done >= 1 and brent_ok(U2, V2, W2, 2, 2, 2)
+    bad = V2.copy()
+    bad[0, 0] = 1 - bad[0, 0] if bad[0, 0] != 1 else 0
+    assert not brent_ok(U2, bad, W2, 2, 2, 2)
+    half = V.copy()
+    half[0] = half[0] + half[4]  # products 0 and 4 share U; the matching W update is left out
+    assert not brent_ok(U, half, W, 2, 2, 2)
