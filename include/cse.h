@@ -423,6 +423,42 @@ int32_t cse_flip_program(cse_ctx* ctx, int32_t run_id, int32_t comp, int32_t* tr
 /* Free a flip run's results. */
 int32_t cse_flip_release(cse_ctx* ctx, int32_t run_id);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * system reduced by cfg->n_proc processes exactly as cse_system_load +
+ * cse_launch would (component index `comp` keys the random draws: 0 for a
+ * lone system, 0 / 1 / 2 for U / V / W^T of a scheme, whose units then equal
+ * that component's units of cse_scheme_load + cse_launch), with every
+ * working buffer (the input's bitsets and candidate lists, per-unit state,
+ * the launch table) in a static device array of CSE_STATIC_SCRATCH_BYTES
+ * per GPU instead of allocated memory.  Calls no hipMalloc or hipFree.
+ *   A          device pointer, rows x cols int8 row-major; read on `stream`
+ *              after the work queued there, not kept.  Rules of
+ *              cse_system_load.
+ *   cfg        as for cse_launch, without sharing (share_every, share_src_pm
+ *              or share_max_rounds 0) and not CSE_COUNT_MFMA.
+ *   cost, length
+ *              device int32[n_proc]: each unit's additions and program
+ *              length.
+ *   prog       device uint32[n_proc x prog_cap]: unit p's program at
+ *              prog[p prog_cap ...], entry t = a << 16 | b << 1 | (s < 0)
+ *              (a < b 1-based ids, s the sign; the t-th fresh variable is
+ *              n_x + t + 1 = x_a + s x_b).  Entries past length are unset.
+ *   needed     (may be NULL) receives max(1, floor((nnz - rows) / 2)), the
+ *              smallest prog_cap; a smaller prog_cap gives CSE_ERANGE
+ *              before any unit runs.
+ * CSE_ENOMEM when the working set (about 36 B per process, 6 B per pair
+ * occurrence of the input for its candidate lists, and per-process HBM
+ * state for systems that need it) exceeds CSE_STATIC_SCRATCH_BYTES.  Blocking: returns
+ * once the units are done.  Every call on one GPU uses that GPU's array and
+ * overwrites what the previous call left there; calls that overlap on one
+ * GPU (from several threads or contexts) race and must be serialised by the
+ * caller. */
+#define CSE_STATIC_SCRATCH_BYTES (64u << 20)
+int32_t cse_reduce_static(cse_ctx* ctx, const int8_t* A, int32_t rows, int32_t cols, int32_t comp,
+                          const cse_run_cfg* cfg, void* stream, int32_t* cost, int32_t* length, uint32_t* prog,
+                          int32_t prog_cap, int32_t* needed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,7 @@ EXPORTS = ("cse_version", "cse_ctx_create", "cse_ctx_destroy", "cse_last_error",
            "cse_server_tick", "cse_server_job_info", "cse_server_release", "cse_server_destroy",
            "cse_run_driver", "cse_driver_best", "cse_driver_totals", "cse_hybrid_best", "cse_ctx_set_timing",
            "cse_kernel_times", "cse_flip_variants", "cse_run_flips", "cse_flip_best", "cse_flip_program",
-           "cse_flip_release")
+           "cse_flip_release", "cse_reduce_static")
 CSE_JOB_QUEUED, CSE_JOB_RUNNING, CSE_JOB_DONE, CSE_JOB_FAILED = 0, 1, 2, 3
 
 
@@ -184,6 +184,8 @@ def load_library(path: str = LIB_PATH):
     L.cse_driver_totals.restype = i32
     L.cse_hybrid_best.argtypes = [vp, P(i32), i32, P(i32), P(i32), P(i32)]
     L.cse_hybrid_best.restype = i32
+    L.cse_reduce_static.argtypes = [vp, vp, i32, i32, i32, P(CseRunCfg), vp, vp, vp, vp, i32, P(i32)]
+    L.cse_reduce_static.restype = i32
     _lib = L
     return L
 
@@ -589,3 +591,40 @@ def cse_server_release(server: CseServer, job_id):
 
 def cse_server_destroy(server: CseServer):
     load_library().cse_server_destroy(server.handle)
+
+
+def _dev_i32(t, shape, name):
+    torch = __import__("torch")
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous int32 GPU tensor of shape {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cse_reduce_static_needed(ctx, A, cfg: CseRunCfg, comp=0, stream=None) -> int:
+    """Program entries per process that cse_reduce_static needs for A."""
+    if A.dtype != __import__("torch").int8 or not A.is_cuda or not A.is_contiguous() or A.dim() != 2:
+        raise ValueError("A must be a contiguous 2-D int8 GPU tensor")
+    need = ctypes.c_int32(0)
+    rc = load_library().cse_reduce_static(ctx, ctypes.c_void_p(A.data_ptr()), A.shape[0], A.shape[1], comp,
+                                          ctypes.byref(cfg), _stream_ptr(stream), None, None, None, 0,
+                                          ctypes.byref(need))
+    if rc not in (0, -3):
+        _check(ctx, rc)
+    return need.value
+
+
+def cse_reduce_static(ctx, A, cfg: CseRunCfg, cost, length, prog, comp=0, stream=None):
+    """Reduce A (int8 GPU tensor) with no device allocation; cost and length
+    are int32 GPU tensors of n_proc entries, prog an int32 GPU tensor of
+    n_proc x cap program keys (a << 16 | b << 1 | (s < 0))."""
+    if A.dtype != __import__("torch").int8 or not A.is_cuda or not A.is_contiguous() or A.dim() != 2:
+        raise ValueError("A must be a contiguous 2-D int8 GPU tensor")
+    n = cfg.n_proc
+    if prog.dim() != 2:
+        raise ValueError("prog must be n_proc x cap")
+    cap = prog.shape[1]
+    need = ctypes.c_int32(0)
+    _check(ctx, load_library().cse_reduce_static(
+        ctx, ctypes.c_void_p(A.data_ptr()), A.shape[0], A.shape[1], comp, ctypes.byref(cfg), _stream_ptr(stream),
+        _dev_i32(cost, (n,), "cost"), _dev_i32(length, (n,), "length"), _dev_i32(prog, (n, cap), "prog"), cap,
+        ctypes.byref(need)))

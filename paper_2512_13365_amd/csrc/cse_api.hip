@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,18 @@
 #include "cse_input.hpp"
 #include "cse_kernels.hpp"
 #include "cse_share.hpp"
+
+// Working memory of cse_reduce_static, for callers that cannot allocate:
+// a file-scope device array, one copy per GPU, kept until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returned for the current device, recorded once per
+// device by cse_ctx_create.
+static constexpr size_t kStaticScratchBytes = CSE_STATIC_SCRATCH_BYTES;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
 
 namespace {
 
@@ -344,50 +357,30 @@ void set_layout(DevComp& c, int layout) {
     c.tl = (layout & CSE_LAYOUT_LDS_TABLES) != 0;
 }
 
-// A component from an input already copied to c->d_A (rows x cols int8)
-// and its sizes: nonzeros, pair occurrences and naive count (Sec. 3.2.1).
-// Builds the bitsets, analyses the input and picks the layout; frees the
-// component on error.
-int finish_component(cse_ctx* ctx, DevComp& c, long long nnz, long long occ, long long naive, DevComp* out) {
+// Sizes of a component from its nonzeros, pair occurrences and naive count
+// (Sec. 3.2.1); n_e and n_x are set.  Host arithmetic only.
+int size_component(cse_ctx* ctx, DevComp& c, long long nnz, long long occ, long long naive) {
     const int rows = c.n_e, cols = c.n_x;
     // Each substitution removes c >= 2 nonzeros and no row empties, so at
     // most floor((nnz - n_e) / 2) fresh variables; every candidate uses at
     // least two of the pair occurrences, whose number never grows.
     c.n_fmax = (int)((nnz - rows) / 2);
-    if ((long long)cols + c.n_fmax > kMaxVars) {
-        free_component(c);
+    if ((long long)cols + c.n_fmax > kMaxVars)
         return fail(ctx, CSE_EINVAL, "variables %lld exceed %d", (long long)cols + c.n_fmax, kMaxVars);
-    }
     c.W = (rows + 63) / 64;
     c.occ0 = occ;
     // The range form of gi packs candidate indices in 23 bits.
-    if (occ / 2 >= (1ll << 23)) {
-        free_component(c);
-        return fail(ctx, CSE_EINVAL, "%lld candidates exceed 2^23", occ / 2);
-    }
+    if (occ / 2 >= (1ll << 23)) return fail(ctx, CSE_EINVAL, "%lld candidates exceed 2^23", occ / 2);
     c.m_cap = (int)std::max<long long>(1, occ / 2);
     c.kbits = csek::weight_bits(rows);
     c.naive0 = (int)naive;
-    const int n_vmax = cols + c.n_fmax;
-    c.newc_cap = std::max(1, std::min(c.m_cap, 2 * n_vmax));
-    const size_t col_bytes = (size_t)cols * c.W * 8;
-    hipError_t e = hipMalloc(&c.d_P, col_bytes);
-    if (e == hipSuccess) e = hipMalloc(&c.d_N, col_bytes);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(csek::input_columns_kernel, dim3((cols * c.W + 255) / 256), dim3(256), 0, nullptr,
-                           c.d_A, rows, cols, c.W, c.d_P, c.d_N);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) {
-        free_component(c);
-        return fail(ctx, CSE_EHIP, "loading a %d x %d system: %s", rows, cols, hipGetErrorString(e));
-    }
-    // The input's candidates, shared by every unit at its first step.
-    int rc = analyse_input(ctx, c, false, &c.d_cand0, &c.d_tl0, &c.m0);
-    if (rc) {
-        free_component(c);
-        return rc;
-    }
+    c.newc_cap = std::max(1, std::min(c.m_cap, 2 * (cols + c.n_fmax)));
+    return CSE_OK;
+}
+
+// Layout of a component once the input's candidate count c.m0 is known.
+int pick_layout(cse_ctx* ctx, DevComp& c) {
+    const int cols = c.n_x, n_vmax = c.n_x + c.n_fmax;
     // Large candidate sets walk per-variable ranges in gi instead of masks.
     c.adj = (long long)cols * ((c.m0 + 63) / 64) > kMaskBudgetWords * 3 / 4;
     // Mask capacity: twice the input's need (live variables x 32-bit words of
@@ -401,11 +394,41 @@ int finish_component(cse_ctx* ctx, DevComp& c, long long nnz, long long occ, lon
     // touches far less of that state per step than building masks does.
     if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
     // Every layout keeps the variable lists in LDS.
-    if (csek::list_bytes(n_vmax) > ctx->lds_max) {
-        const size_t need = csek::list_bytes(n_vmax);
+    if (csek::list_bytes(n_vmax) > ctx->lds_max)
+        return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax,
+                    csek::list_bytes(n_vmax), ctx->lds_max);
+    return CSE_OK;
+}
+
+// A component from an input already copied to c->d_A (rows x cols int8)
+// and its sizes: nonzeros, pair occurrences and naive count (Sec. 3.2.1).
+// Builds the bitsets, analyses the input and picks the layout; frees the
+// component on error.
+int finish_component(cse_ctx* ctx, DevComp& c, long long nnz, long long occ, long long naive, DevComp* out) {
+    const int rows = c.n_e, cols = c.n_x;
+    int rc = size_component(ctx, c, nnz, occ, naive);
+    if (rc) {
         free_component(c);
-        return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax, need,
-                    ctx->lds_max);
+        return rc;
+    }
+    const size_t col_bytes = (size_t)cols * c.W * 8;
+    hipError_t e = hipMalloc(&c.d_P, col_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c.d_N, col_bytes);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(csek::input_columns_kernel, dim3((cols * c.W + 255) / 256), dim3(256), 0, nullptr,
+                           c.d_A, rows, cols, c.W, c.d_P, c.d_N);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        free_component(c);
+        return fail(ctx, CSE_EHIP, "loading a %d x %d system: %s", rows, cols, hipGetErrorString(e));
+    }
+    // The input's candidates, shared by every unit at its first step.
+    rc = analyse_input(ctx, c, false, &c.d_cand0, &c.d_tl0, &c.m0);
+    if (rc == CSE_OK) rc = pick_layout(ctx, c);
+    if (rc) {
+        free_component(c);
+        return rc;
     }
     *out = c;
     return CSE_OK;
@@ -1174,6 +1197,18 @@ int32_t cse_ctx_create(int32_t device, cse_ctx** out) {
     cse_ctx* ctx = new (std::nothrow) cse_ctx();
     if (!ctx) return CSE_ENOMEM;
     ctx->device = device;
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            // On failure the address stays unset and cse_reduce_static
+            // reports it; every other entry point works without the array.
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+                g_scratch_ptr[device] = ptr;
+            else
+                (void)hipGetLastError();
+        }
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess)
         ctx->lds_max = std::max<size_t>(prop.sharedMemPerBlock, 65536);
@@ -2475,3 +2510,172 @@ int32_t cse_flip_release(cse_ctx* ctx, int32_t run_id) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// Bump allocation inside the static scratch array (256-byte aligned pieces).
+struct ScratchCarve {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t bytes) {
+        T* p = (T*)(base + off);
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t cse_reduce_static(cse_ctx* ctx, const int8_t* A, int32_t rows, int32_t cols, int32_t comp,
+                          const cse_run_cfg* cfg, void* stream, int32_t* cost, int32_t* length, uint32_t* prog,
+                          int32_t prog_cap, int32_t* needed) {
+    if (!ctx) return CSE_EINVAL;
+    if (!A || rows < 1 || cols < 1) return fail(ctx, CSE_EINVAL, "empty system (%d x %d)", rows, cols);
+    if (rows > kMaxRows) return fail(ctx, CSE_EINVAL, "rows %d exceed %d", rows, kMaxRows);
+    if (comp < 0 || comp > 2) return fail(ctx, CSE_EINVAL, "component %d out of range", comp);
+    int rc = validate_cfg(ctx, cfg);
+    if (rc) return rc;
+    if (shares(*cfg)) return fail(ctx, CSE_EINVAL, "cse_reduce_static runs without sharing rounds");
+    if (cfg->count_path == CSE_COUNT_MFMA)
+        return fail(ctx, CSE_EINVAL, "cse_reduce_static counts the input by popcounts only");
+    if (ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device])
+        return fail(ctx, CSE_EHIP, "no static scratch address for device %d", ctx->device);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const hipStream_t s = (hipStream_t)stream;
+    const uint32_t n = cfg->n_proc;
+    ScratchCarve sc{(char*)g_scratch_ptr[ctx->device]};
+    unsigned long long* d_st = sc.take<unsigned long long>(64);
+    int* d_err = sc.take<int>(64);
+    unsigned long long* d_t0 = sc.take<unsigned long long>(64);  // start stamp (8 B), round counter (4 B)
+    csek::Segment* d_seg = sc.take<csek::Segment>(sizeof(csek::Segment));
+
+    // Validation and sizes on the device (Sec. 3.2.1).
+    unsigned long long st[5] = {0, 0, 0, 0, 0};
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t*)d_st, 10, 0);
+    hipLaunchKernelGGL(csek::input_stats_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, A, rows, cols, d_st);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(st, d_st, sizeof st, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (st[3] || st[4])
+        return fail(ctx, CSE_EINVAL, "system %d x %d: %llu entries not ternary, %llu all-zero rows", rows, cols, st[3],
+                    st[4]);
+    DevComp c;
+    c.n_e = rows;
+    c.n_x = cols;
+    rc = size_component(ctx, c, (long long)st[0], (long long)st[1], (long long)st[2]);
+    if (rc) return rc;
+    const int pstride = std::max(1, c.n_fmax);
+    if (needed) *needed = pstride;
+    if (prog_cap < pstride || !cost || !length || !prog)
+        return fail(ctx, CSE_ERANGE, "programs need %d entries per process (cap %d) and non-null outputs", pstride,
+                    prog_cap);
+
+    // The input's column bitsets and candidate lists (the pieces every unit
+    // starts from), then the per-unit arrays the caller does not hold.
+    const size_t col_bytes = (size_t)cols * c.W * 8;
+    c.d_P = sc.take<uint64_t>(col_bytes);
+    c.d_N = sc.take<uint64_t>(col_bytes);
+    int32_t* buf = sc.take<int32_t>(((size_t)4 * cols + 4) * 4);
+    c.d_cand0 = sc.take<uint64_t>((size_t)c.m_cap * 8);
+    c.d_tl0 = sc.take<uint32_t>((size_t)c.m_cap * 4);
+    if (sc.off > kStaticScratchBytes)
+        return fail(ctx, CSE_ENOMEM, "%u processes of a %d x %d system need %zu B of scratch (max %zu)", n, rows,
+                    cols, sc.off, kStaticScratchBytes);
+    hipLaunchKernelGGL(csek::input_columns_kernel, dim3((cols * c.W + 255) / 256), dim3(256), 0, s, A, rows, cols,
+                       c.W, c.d_P, c.d_N);
+    const int nx = cols;
+    int32_t* row_n = buf;
+    int32_t* col_n = buf + nx;
+    int32_t* row_off = buf + 2 * nx;
+    int32_t* col_off = buf + 3 * nx + 1;
+    int32_t* d_tot = buf + 4 * nx + 2;
+    csek::PairSource src{c.d_P, c.d_N, c.W, nullptr, 0, nx};
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3((2 * nx + 255) / 256), dim3(256), 0, s, buf, 2 * nx, 0);
+    hipLaunchKernelGGL(csek::input_count_kernel, dim3(nx), dim3(csek::kInputBlock), 0, s, src, row_n, col_n);
+    hipLaunchKernelGGL(csek::input_scan_kernel, dim3(1), dim3(csek::kInputBlock), 0, s, row_n, col_n, nx, row_off,
+                       col_off, d_tot);
+    HIP_TRY(ctx, hipGetLastError());
+    int32_t tot[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (tot[0] != tot[1] || tot[0] < 0 || tot[0] > c.m_cap)
+        return fail(ctx, CSE_EHIP, "input analysis: %d candidates by first variable, %d by second (bound %d)", tot[0],
+                    tot[1], c.m_cap);
+    hipLaunchKernelGGL(csek::input_rows_kernel, dim3(nx), dim3(csek::kInputBlock), 0, s, src, row_off, c.d_cand0);
+    hipLaunchKernelGGL(csek::input_cols_kernel, dim3(nx), dim3(csek::kInputBlock), 0, s, src, row_off, col_off,
+                       c.d_cand0, c.d_tl0);
+    HIP_TRY(ctx, hipGetLastError());
+    c.m0 = tot[0];
+    rc = pick_layout(ctx, c);
+    if (rc) return rc;
+
+    csek::UnitState S{};
+    S.ops = sc.take<unsigned long long>((size_t)n * 8);
+    S.finish = sc.take<unsigned long long>((size_t)n * 8);
+    S.executed = sc.take<int32_t>((size_t)n * 4);
+    S.epoch = sc.take<int32_t>((size_t)n * 4);
+    S.k0 = sc.take<int32_t>((size_t)n * 4);
+    S.active = sc.take<int32_t>((size_t)n * 4);
+    S.strat = sc.take<int32_t>((size_t)n * 4);
+    S.prog = prog;
+    S.t = length;
+    S.cost = cost;
+    S.t0 = d_t0;
+    S.round = (int32_t*)((char*)d_t0 + 8);
+    if (sc.off > kStaticScratchBytes)
+        return fail(ctx, CSE_ENOMEM, "%u processes need %zu B of scratch (max %zu)", n, sc.off, kStaticScratchBytes);
+    if (c.gs) {
+        const size_t slots = (size_t)n * slot_bytes(c);
+        if (slots > kStaticScratchBytes - sc.off)
+            return fail(ctx, CSE_ENOMEM, "%u processes need %zu B of HBM unit state beside %zu B (scratch max %zu)", n,
+                        slots, sc.off, kStaticScratchBytes);
+        S.gs_stride = slot_bytes(c);
+        S.gs_base = sc.take<char>(slots);
+    }
+
+    JobRec J;
+    J.cfg = *cfg;
+    J.budget = -1;
+    csek::Segment sg{};
+    sg.C = comp_args(c, comp, false);
+    sg.C.prog_stride = prog_cap;
+    sg.R = run_args(ctx, J);
+    sg.S = S;
+    sg.unit_begin = 0;
+    LaunchGroup G;
+    G.W = c.W;
+    G.gs = c.gs;
+    G.adj = c.adj;
+    G.tl = false;
+    G.gp = cfg->weights[CSE_STRAT_GP] != 0;
+    G.n_grid = n;
+    G.lds = lds_bytes(c);
+    G.seg_begin = 0;
+    G.n_segs = 1;
+    G.order_begin = 0;
+    rc = set_lds_limit(ctx, G);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(d_seg, &sg, sizeof sg, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, s, d_err, 1, 0);
+    hipLaunchKernelGGL(csek::init_units_kernel, dim3((n + 255) / 256), dim3(256), 0, s, S, n, 1);
+    HIP_TRY(ctx, hipGetLastError());
+    if (G.gs && G.adj)
+        rc = launch_group_gs<true, true, false>(ctx, G, d_seg, nullptr, d_err, s);
+    else if (G.gs)
+        rc = launch_group_gs<true, false, false>(ctx, G, d_seg, nullptr, d_err, s);
+    else
+        rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, d_seg, nullptr, d_err, s)
+                   : launch_group_gs<false, false, false>(ctx, G, d_seg, nullptr, d_err, s);
+    if (rc) return rc;
+    int herr = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (herr) return fail(ctx, CSE_EHIP, "device consistency check failed (flags 0x%x)", herr);
+    return CSE_OK;
+}
+
+}  // extern "C"
+
