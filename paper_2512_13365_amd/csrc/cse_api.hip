@@ -929,7 +929,8 @@ int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_se
                    int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid), dim3(csek::kWave), G.lds, s,
+    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid),
+                       dim3(csek::kWave * csek::UnitWaves<GS, ADJ>::value), G.lds, s,
                        d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err, G.gp ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());
     return CSE_OK;

@@ -1138,6 +1138,593 @@ __device__ int select_gp(const uint64_t* cand, int m, const uint64_t* colP, cons
     return gi_argmax(best_h, best_p);
 }
 
+// ---------------------------------------------------------------------------
+// Units of NW > 1 waves (one workgroup of 64 NW lanes per unit).  Systems
+// whose state lives in HBM slots have thousands of candidates; spreading a
+// unit's loops over several waves puts that many more independent memory
+// accesses in flight per unit (their steps wait on memory) and shortens the
+// rounds that only the largest units still run.  Every loop strides over 64
+// NW entries; wave results meet in small shared arrays: a wave's ballot count
+// becomes its offset among the waves (compaction), wave reductions become
+// group reductions.  Values that steer control flow (counts, picks) are the
+// same in every wave, so the waves take the same branches and barriers.
+// The single-wave kernels keep the functions above.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int grp_tid() { return (int)threadIdx.x; }
+__device__ __forceinline__ int grp_lane() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int grp_wave() { return (int)(threadIdx.x >> 6); }
+
+// Every wave passes one wave-uniform value; all receive the NW values.
+template <int NW, class T>
+__device__ __forceinline__ void grp_exchange(T v, T (&all)[NW]) {
+    __shared__ T slot[NW];
+    if (grp_lane() == 0) slot[grp_wave()] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) all[w] = slot[w];
+    __syncthreads();
+}
+// Offset of this wave's wave-uniform count among the waves (lower waves
+// first); *total receives the sum.
+template <int NW>
+__device__ __forceinline__ int grp_offset(int count, int* total) {
+    int all[NW];
+    grp_exchange<NW>(count, all);
+    int off = 0, tot = 0;
+    const int me = grp_wave();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        off += w < me ? all[w] : 0;
+        tot += all[w];
+    }
+    *total = tot;
+    return off;
+}
+template <int NW>
+__device__ __forceinline__ int grp_sum(int v) {
+    int all[NW];
+    grp_exchange<NW>(wave_sum(v), all);
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += all[w];
+    return s;
+}
+template <int NW>
+__device__ __forceinline__ int grp_max(int v) {
+    int all[NW];
+    grp_exchange<NW>(wave_max(v), all);
+    int s = all[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = all[w] > s ? all[w] : s;
+    return s;
+}
+template <int NW>
+__device__ __forceinline__ int grp_min(int v) {
+    int all[NW];
+    grp_exchange<NW>(wave_min(v), all);
+    int s = all[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = all[w] < s ? all[w] : s;
+    return s;
+}
+template <int NW>
+__device__ __forceinline__ long long grp_max64(long long v) {
+    long long all[NW];
+    grp_exchange<NW>(wave_max64(v), all);
+    long long s = all[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = all[w] > s ? all[w] : s;
+    return s;
+}
+template <int NW>
+__device__ __forceinline__ unsigned long long grp_max_u64(unsigned long long v) {
+    unsigned long long all[NW];
+    grp_exchange<NW>(wave_max_u64(v), all);
+    unsigned long long s = all[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = all[w] > s ? all[w] : s;
+    return s;
+}
+template <int NW>
+__device__ __forceinline__ unsigned grp_or(unsigned v) {
+    unsigned all[NW];
+    grp_exchange<NW>(__ockl_wfred_or_u32(v), all);
+    unsigned s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s |= all[w];
+    return s;
+}
+
+// Substitution (as substitute): every wave reads the two columns and
+// computes c and the dead flags; after a barrier wave 0 writes.
+template <int W, int NW>
+__device__ __forceinline__ int substitute_grp(uint64_t* colP, uint64_t* colN, uint32_t key, int vk, int* dead) {
+    const int l = grp_lane();
+    const int va = key_a(key) - 1, vb = key_b(key) - 1;
+    const bool neg = key & 1u;
+    int c = 0;
+    bool alive_a = false, alive_b = false;
+    uint64_t Pa = 0, Na = 0, Pb = 0, Nb = 0, R = 0;
+    if (l < W) {
+        Pa = colP[va * W + l];
+        Na = colN[va * W + l];
+        Pb = colP[vb * W + l];
+        Nb = colN[vb * W + l];
+        R = neg ? ((Pa & Nb) | (Na & Pb)) : ((Pa & Pb) | (Na & Nb));
+        c = popc64(R);
+        alive_a = ((Pa | Na) & ~R) != 0;
+        alive_b = ((Pb | Nb) & ~R) != 0;
+    }
+    c = wave_sum(c);
+    *dead = (ballot(alive_a) == 0 ? 1 : 0) | (ballot(alive_b) == 0 ? 2 : 0);
+    __syncthreads();
+    if (l < W && grp_wave() == 0) {
+        colP[vk * W + l] = Pa & R;
+        colN[vk * W + l] = Na & R;
+        colP[va * W + l] = Pa & ~R;
+        colN[va * W + l] = Na & ~R;
+        colP[vb * W + l] = Pb & ~R;
+        colN[vb * W + l] = Nb & ~R;
+    }
+    __syncthreads();
+    return c;
+}
+
+template <int NW>
+__device__ __forceinline__ int update_live_grp(uint32_t* live, int32_t* vpos, int n_live, int a, int b, int dead,
+                                               int k) {
+    const int t = grp_tid();
+    int n = n_live;
+    if (dead) {
+        int out = 0;
+        for (int base = 0; base < n_live; base += kWave * NW) {
+            const int i = base + t;
+            const uint32_t x = i < n_live ? live[i] : 0u;
+            const bool keep = i < n_live && !((dead & 1) && (int)x == a) && !((dead & 2) && (int)x == b);
+            const uint64_t m = ballot(keep);
+            int tot;
+            const int off = grp_offset<NW>(popc64(m), &tot);
+            if (keep) {
+                const int p = out + off + lanes_below(m);
+                live[p] = x;
+                vpos[x - 1] = p;
+            }
+            out += tot;
+            __syncthreads();
+        }
+        n = out;
+    }
+    if (t == 0) {
+        live[n] = (uint32_t)k;
+        vpos[k - 1] = n;
+    }
+    __syncthreads();
+    return n + 1;
+}
+
+// Live list of the first n_v variables from their columns (ascending).
+template <int W, int NW>
+__device__ __forceinline__ int build_live_grp(const uint64_t* colP, const uint64_t* colN, int n_v, uint32_t* live,
+                                              int32_t* vpos) {
+    int n_live = 0;
+    for (int b0 = 0; b0 < n_v; b0 += kWave * NW) {
+        const int v = b0 + grp_tid();
+        bool nz = false;
+        if (v < n_v) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) nz |= (colP[v * W + w] | colN[v * W + w]) != 0;
+        }
+        const uint64_t mk = ballot(nz);
+        int tot;
+        const int off = grp_offset<NW>(popc64(mk), &tot);
+        if (nz) {
+            const int p = n_live + off + lanes_below(mk);
+            live[p] = (uint32_t)(v + 1);
+            vpos[v] = p;
+        }
+        n_live += tot;
+    }
+    __syncthreads();
+    return n_live;
+}
+
+template <int W, int NW>
+__device__ int analyse_full_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                                uint64_t* cand, int m_cap, int* err_flags) {
+    const int t = grp_tid();
+    int m = 0;
+    for (int i = 0; i + 1 < n_live; ++i) {
+        const int a = (int)live[i];
+        for (int jb = i + 1; jb < n_live; jb += kWave * NW) {
+            const int j = jb + t;
+            const bool valid = j < n_live;
+            const int b = valid ? (int)live[j] : a;
+            const int2 c = valid ? pair_counts<W>(colP, colN, a - 1, b - 1) : make_int2(0, 0);
+            const bool hp = c.x >= 2, hm = c.y >= 2;
+            const uint64_t bp = ballot(hp), bm = ballot(hm);
+            int tot;
+            const int off = grp_offset<NW>(popc64(bp) + popc64(bm), &tot);
+            const int pos = m + off + lanes_below(bp) + lanes_below(bm);
+            if (hp) {
+                if (pos < m_cap) cand[pos] = pair_key(a, b, 0) | ((uint64_t)c.x << 32);
+                else *err_flags |= ERR_CAND_OVERFLOW;
+            }
+            if (hm) {
+                const int q = pos + (hp ? 1 : 0);
+                if (q < m_cap) cand[q] = pair_key(a, b, 1) | ((uint64_t)c.y << 32);
+                else *err_flags |= ERR_CAND_OVERFLOW;
+            }
+            m += tot;
+        }
+    }
+    __syncthreads();
+    return m < m_cap ? m : m_cap;
+}
+
+template <int W, int NW>
+__device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                                        const uint64_t* src, int m, uint64_t* dst, uint64_t* newc, int newc_cap,
+                                        int m_cap, int32_t* remap, int32_t* kpre, int a, int b, int k,
+                                        int* n_new_out, int* err_flags) {
+    const int t = grp_tid();
+    int n_new = 0;
+    for (int base = 0; base < n_live - 1; base += kWave * NW) {
+        const int i = base + t;
+        const bool valid = i < n_live - 1;
+        const int x = valid ? (int)live[i] : k;
+        const int2 c = valid ? pair_counts<W>(colP, colN, x - 1, k - 1) : make_int2(0, 0);
+        const bool hp = c.x >= 2, hm = c.y >= 2;
+        const uint64_t bp = ballot(hp), bm = ballot(hm);
+        int tot;
+        const int off = grp_offset<NW>(popc64(bp) + popc64(bm), &tot);
+        const int pos = n_new + off + lanes_below(bp) + lanes_below(bm);
+        if (hp) {
+            if (pos < newc_cap) newc[pos] = pair_key(x, k, 0) | ((uint64_t)c.x << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        if (hm) {
+            const int q = pos + (hp ? 1 : 0);
+            if (q < newc_cap) newc[q] = pair_key(x, k, 1) | ((uint64_t)c.y << 32);
+            else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        n_new += tot;
+    }
+    if (n_new > newc_cap) n_new = newc_cap;
+    __syncthreads();
+    int mf = 0;
+    for (int base = 0; base < m; base += kWave * NW) {
+        const int i = base + t;
+        const bool valid = i < m;
+        uint64_t e = valid ? src[i] : 0ull;
+        const uint32_t key = (uint32_t)e;
+        const int qa = key_a(key), qb = key_b(key);
+        int c = entry_c(e);
+        if (valid && (qa == a || qa == b || qb == a || qb == b)) {
+            const int2 cc = pair_counts<W>(colP, colN, qa - 1, qb - 1);
+            c = (key & 1u) ? cc.y : cc.x;
+            e = (uint64_t)key | ((uint64_t)c << 32);
+        }
+        const bool keep = valid && c >= 2;
+        const uint64_t bk = ballot(keep);
+        int tot;
+        const int off = grp_offset<NW>(popc64(bk), &tot);
+        const int kept = mf + off + lanes_below(bk);
+        if (valid) {
+            int lo = 0, hi = n_new;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)newc[mid]) < qa) lo = mid + 1; else hi = mid;
+            }
+            const int dest = kept + lo;
+            kpre[i] = kept;
+            if (keep) {
+                if (dest < m_cap) dst[dest] = e;
+                else *err_flags |= ERR_CAND_OVERFLOW;
+            }
+            remap[i] = keep ? dest : -1;
+        }
+        mf += tot;
+    }
+    if (t == 0) kpre[m] = mf;
+    if (mf + n_new > m_cap) { *err_flags |= ERR_CAND_OVERFLOW; n_new = m_cap > mf ? m_cap - mf : 0; }
+    __syncthreads();
+    for (int base = 0; base < n_new; base += kWave * NW) {
+        const int e = base + t;
+        if (e < n_new) {
+            const uint64_t v = newc[e] & ((1ull << 42) - 1);
+            const int x = key_a((uint32_t)v);
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_a((uint32_t)src[mid]) <= x) lo = mid + 1; else hi = mid;
+            }
+            const int dest = e + kpre[lo];
+            dst[dest] = v;
+            newc[e] = v | ((uint64_t)dest << 42);
+        }
+    }
+    __syncthreads();
+    *n_new_out = n_new;
+    return mf + n_new;
+}
+
+template <int NW>
+__device__ void update_tl_grp(uint32_t* tl, int m_old, const int32_t* remap, const uint64_t* newc, int n_new) {
+    const int t = grp_tid();
+    int mt = 0;
+    for (int base = 0; base < m_old; base += kWave * NW) {
+        const int i = base + t;
+        const int v = i < m_old ? remap[tl[i]] : -1;
+        const bool keep = v >= 0;
+        const uint64_t bk = ballot(keep);
+        int tot;
+        const int off = grp_offset<NW>(popc64(bk), &tot);
+        if (keep) tl[mt + off + lanes_below(bk)] = (uint32_t)v;
+        mt += tot;
+    }
+    __syncthreads();
+    for (int base = 0; base < n_new; base += kWave * NW) {
+        const int e = base + t;
+        if (e < n_new) tl[mt + e] = (uint32_t)(newc[e] >> 42);
+    }
+    __syncthreads();
+}
+
+template <int W, int NW>
+__device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+                             const uint64_t* cand, int m, uint32_t* tl) {
+    const int t = grp_tid();
+    int mt = 0;
+    for (int j = 1; j < n_live; ++j) {
+        const int b = (int)live[j];
+        for (int ib = 0; ib < j; ib += kWave * NW) {
+            const int i = ib + t;
+            const bool valid = i < j;
+            const int a = valid ? (int)live[i] : b;
+            const int2 c = valid ? pair_counts<W>(colP, colN, a - 1, b - 1) : make_int2(0, 0);
+            const bool hp = c.x >= 2, hm = c.y >= 2;
+            const uint64_t bp = ballot(hp), bm = ballot(hm);
+            int tot;
+            const int off = grp_offset<NW>(popc64(bp) + popc64(bm), &tot);
+            const int pos = mt + off + lanes_below(bp) + lanes_below(bm);
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const bool has = sgn ? hm : hp;
+                if (!has) continue;
+                const uint32_t key = pair_key(a, b, sgn);
+                int lo = 0, hi = m;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((uint32_t)cand[mid] < key) lo = mid + 1; else hi = mid;
+                }
+                const int q = pos + (sgn && hp ? 1 : 0);
+                if (q < m) tl[q] = (uint32_t)lo;
+            }
+            mt += tot;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NW>
+__device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
+                              int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits) {
+    const int l = grp_lane();
+    for (int i = grp_tid(); i < 4 * n_live; i += kWave * NW) rng[i] = 0;
+    __syncthreads();
+    int wmax = 0;
+    for (int base = 0; base < m; base += kWave * NW) {
+        const int cb = base + kWave * grp_wave();  // this wave's chunk
+        if (cb >= m) continue;
+        const int i = cb + l;
+        const bool valid = i < m;
+        const uint64_t e = valid ? cand[i] : 0ull;
+        const uint32_t q = valid ? tl[i] : 0u;
+        const uint64_t eq = valid ? cand[q] : 0ull;
+        const int w = valid ? entry_c(e) - 1 : 0;
+        const int wq = valid ? entry_c(eq) - 1 : 0;
+        const int a = key_a((uint32_t)e), b = key_b((uint32_t)eq);
+        int pa = __shfl_up(a, 1), na = __shfl_down(a, 1);
+        int pb = __shfl_up(b, 1), nb = __shfl_down(b, 1);
+        if (l == 0) {
+            pa = i > 0 && valid ? key_a((uint32_t)cand[i - 1]) : -1;
+            pb = i > 0 && valid ? key_b((uint32_t)cand[tl[i - 1]]) : -1;
+        }
+        if (l == kWave - 1 || i + 1 >= m) {
+            na = i + 1 < m ? key_a((uint32_t)cand[i + 1]) : -1;
+            nb = i + 1 < m ? key_b((uint32_t)cand[tl[i + 1]]) : -1;
+        }
+        if (valid) {
+            const int va = vpos[a - 1], vb = vpos[b - 1];
+            if (a != pa) rng[4 * va + 0] = i;
+            if (a != na) rng[4 * va + 1] = i + 1;
+            if (b != pb) rng[4 * vb + 2] = i;
+            if (b != nb) rng[4 * vb + 3] = i + 1;
+            tinv[q] = i;
+        }
+        wmax = w > wmax ? w : wmax;
+        const int word = 2 * (cb / kWave);
+        for (int k = 0; k < kbits; ++k) {
+            const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
+            if (l < 2) {
+                pl[k * pw + word + l] = (uint32_t)(l ? bc >> 32 : bc);
+                pl[(kbits + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
+            }
+        }
+    }
+    __syncthreads();
+    wmax = grp_max<NW>(wmax);
+    int K = 0;
+    while (K < kbits && (wmax >> K) != 0) ++K;
+    return K;
+}
+
+template <int NW>
+__device__ __forceinline__ int total_profit_grp(const uint64_t* cand, int m) {
+    int tot = 0;
+    for (int q = grp_tid(); q < m; q += kWave * NW) tot += entry_c(cand[q]) - 1;
+    return grp_sum<NW>(tot);
+}
+
+template <int NW>
+__device__ __forceinline__ int gi_argmax_grp(long long best_h, int best_p) {
+    const long long hmax = grp_max64<NW>(best_h);
+    return grp_min<NW>(best_h == hmax ? best_p : 0x7FFFFFFF);
+}
+
+template <int NW>
+__device__ int select_gi_planes_grp(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
+                                    const int32_t* tinv, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
+                                    uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
+                                    long long* n_int, long long* n_blk) {
+    const int T = total_profit_grp<NW>(cand, m);
+    const uint32_t* plc = pl;
+    const uint32_t* plt = pl + kbits * pw;
+    long long best_h = -1;
+    int best_p = 0x7FFFFFFF;
+    int my_int = 0, my_blk = 0;
+    for (int p = grp_tid(); p < m; p += kWave * NW) {
+        const uint64_t ep = cand[p];
+        const uint32_t kp = (uint32_t)ep;
+        const int va = vpos[key_a(kp) - 1], vb = vpos[key_b(kp) - 1];
+        const int4 ra = *(const int4*)(rng + 4 * va);
+        const int4 rb = *(const int4*)(rng + 4 * vb);
+        const bool tprev = p > 0 && ((uint32_t)cand[p - 1] >> 1) == (kp >> 1);
+        const bool tnext = p + 1 < m && ((uint32_t)cand[p + 1] >> 1) == (kp >> 1);
+        const int q_lo = tprev ? p - 1 : p;
+        const int n_ab = (tprev || tnext) ? 2 : 1;
+        const int t_ab = tinv[q_lo];
+        int I = 0, X = 0, ja = 0, jb = 0;
+        CoinStream co;
+        co.init(proc, dw, kp, eh, k0, k1);
+        plane_window(plt, pw, K, ra.z, ra.w, ja, co, I, X);
+        plane_window(plc, pw, K, ra.x, p, ja, co, I, X);
+        plane_window(plc, pw, K, p + 1, ra.y, ja, co, I, X);
+        co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
+        plane_window(plt, pw, K, rb.z, t_ab, jb, co, I, X);
+        plane_window(plt, pw, K, t_ab + n_ab, rb.w, jb, co, I, X);
+        plane_window(plc, pw, K, rb.x, rb.y, jb, co, I, X);
+        const long long wp = (long long)entry_c(ep) - 1;
+        const long long D = (long long)T - wp - I;
+        const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
+        if (hsc > best_h) { best_h = hsc; best_p = p; }
+        my_int += ja + jb;
+        my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
+    }
+    *n_int = grp_sum<NW>(my_int);
+    *n_blk = grp_sum<NW>(my_blk);
+    return gi_argmax_grp<NW>(best_h, best_p);
+}
+
+template <int NW>
+__device__ __forceinline__ int select_g_grp(const uint64_t* cand, int m) {
+    unsigned long long best = 0;
+    for (int q = grp_tid(); q < m; q += kWave * NW) {
+        const unsigned long long key = ((unsigned long long)entry_c(cand[q]) << 32) | (0xFFFFFFFFull - (unsigned)q);
+        best = key > best ? key : best;
+    }
+    best = grp_max_u64<NW>(best);
+    return (int)(0xFFFFFFFFull - (best & 0xFFFFFFFFull));
+}
+
+template <int NW>
+__device__ __forceinline__ int select_ga_grp(const uint64_t* cand, int m, uint32_t u) {
+    const int t = grp_tid();
+    int cmax = 0;
+    for (int q = t; q < m; q += kWave * NW) {
+        const int c = entry_c(cand[q]);
+        cmax = c > cmax ? c : cmax;
+    }
+    cmax = grp_max<NW>(cmax);
+    int mine = 0;
+    for (int q = t; q < m; q += kWave * NW) mine += entry_c(cand[q]) == cmax;
+    const int ties = grp_sum<NW>(mine);
+    uint32_t want = scale_u32(u, (uint32_t)ties);
+    for (int base = 0; base < m; base += kWave * NW) {
+        const int q = base + t;
+        const bool tie = q < m && entry_c(cand[q]) == cmax;
+        const uint64_t bt = ballot(tie);
+        const int cnt = popc64(bt);
+        int tot;
+        const int off = grp_offset<NW>(cnt, &tot);
+        if (want < (uint32_t)tot) {
+            int found = -1;
+            const uint32_t rel = want - (uint32_t)off;
+            if (want >= (uint32_t)off && rel < (uint32_t)cnt) {
+                const uint64_t hit = ballot(tie && (uint32_t)lanes_below(bt) == rel);
+                found = base + kWave * grp_wave() + ctz64(hit);
+            }
+            return grp_max<NW>(found);
+        }
+        want -= (uint32_t)tot;
+    }
+    return -1;
+}
+
+template <int NW>
+__device__ __forceinline__ int select_wr_grp(const uint64_t* cand, int m, uint32_t u) {
+    const int t = grp_tid();
+    const int tot = total_profit_grp<NW>(cand, m);
+    const uint32_t x = scale_u32(u, (uint32_t)tot);
+    uint32_t run = 0;
+    for (int base = 0; base < m; base += kWave * NW) {
+        const int q = base + t;
+        const int w = q < m ? entry_c(cand[q]) - 1 : 0;
+        const uint32_t incl = (uint32_t)wave_scan(w);
+        const int wtot = __builtin_amdgcn_readlane((int)incl, kWave - 1);
+        int gtot;
+        const int off = grp_offset<NW>(wtot, &gtot);
+        const uint64_t hit = ballot(q < m && run + (uint32_t)off + incl > x);
+        const int found = grp_min<NW>(hit ? base + kWave * grp_wave() + ctz64(hit) : 0x7FFFFFFF);
+        if (found != 0x7FFFFFFF) return found;
+        run += (uint32_t)gtot;
+    }
+    return -1;
+}
+
+template <int W, int NW>
+__device__ int select_gp_grp(const uint64_t* cand, int m, const uint64_t* colP, const uint64_t* colN,
+                             const uint32_t* live, int n_live, uint32_t alpha_q, long long* n_cols) {
+    long long best_h = -1;
+    int best_p = 0x7FFFFFFF;
+    for (int base = 0; base < m; base += kWave * NW) {
+        const int q = base + grp_tid();
+        const uint64_t e = cand[q < m ? q : 0];
+        const uint32_t key = (uint32_t)e;
+        const int a = key_a(key), b = key_b(key);
+        const bool neg = key & 1u;
+        uint64_t Pk[W], Nk[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t Pa = colP[(a - 1) * W + w], Na = colN[(a - 1) * W + w];
+            const uint64_t Pb = colP[(b - 1) * W + w], Nb = colN[(b - 1) * W + w];
+            const uint64_t R = neg ? ((Pa & Nb) | (Na & Pb)) : ((Pa & Pb) | (Na & Nb));
+            Pk[w] = Pa & R;
+            Nk[w] = Na & R;
+        }
+        int n_new = 0;
+        for (int i = 0; i < n_live; ++i) {
+            const int x = (int)live[i];
+            int same = 0, opp = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t Px = colP[(x - 1) * W + w], Nx = colN[(x - 1) * W + w];
+                same += popc64((Px & Pk[w]) | (Nx & Nk[w]));
+                opp += popc64((Px & Nk[w]) | (Nx & Pk[w]));
+            }
+            n_new += (x == a || x == b) ? 0 : (same >= 2) + (opp >= 2);
+        }
+        if (q < m) {
+            const long long h = ((long long)(entry_c(e) - 1) << 16) + (long long)alpha_q * n_new;
+            if (h > best_h) {
+                best_h = h;
+                best_p = q;
+            }
+        }
+    }
+    *n_cols = (long long)m * (n_live > 2 ? n_live - 2 : 0);
+    return gi_argmax_grp<NW>(best_h, best_p);
+}
+
 // Algorithmic work of a step in 32-bit integer lane operations (the same
 // cost model the oracle tallies): 98 per Philox block of the step draw;
 // selection 2 n_int + 98 n_blk + 10 m for gi, 10 w m + 8 w n_cols + 2 m for
@@ -1202,11 +1789,21 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // other unit runs in the body without it).  Each (W, GS, ADJ, TL) is its own
 // kernel, so a launch carries only the code its units run and every
 // pointer's memory is known.
+// Waves per unit: units whose state lives in HBM slots and whose gi walks
+// ranges (the large systems) run on kGsWaves waves, the others on one.
+constexpr int kGsWaves = 4;
+template <bool GS, bool ADJ>
+struct UnitWaves {
+    static constexpr int value = (GS && ADJ) ? kGsWaves : 1;
+};
+
 template <int W, bool GS, bool ADJ, bool TL, bool GP>
 __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int n_segs,
                                           const uint32_t* __restrict__ order, uint32_t n_grid, int* err) {
     extern __shared__ uint64_t smem[];
-    const int l = lane_id();
+    constexpr int NW = UnitWaves<GS, ADJ>::value;
+    constexpr int NT = kWave * NW;  // lanes of the unit
+    const int l = (int)threadIdx.x;
     if (blockIdx.x >= n_grid) return;
     // Dispatch order: the host lists grid units longest expected work first.
     const uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
@@ -1257,7 +1854,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     const bool need_tl = ADJ && (strat == S_GI || strat == S_MIX);
 
     if constexpr (!GS) {
-        for (int i = l; i < n_vmax * W; i += kWave) {
+        for (int i = l; i < n_vmax * W; i += NT) {
             const bool in = i < C.n_x * W;
             colP[i] = in ? C.P0[i] : 0ull;
             colN[i] = in ? C.N0[i] : 0ull;
@@ -1296,7 +1893,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
                 }
             }
         } else {
-            for (int i = l; i < n_vmax * W; i += kWave) {
+            for (int i = l; i < n_vmax * W; i += NT) {
                 const bool in = i < C.n_x * W;
                 colP[i] = in ? C.P0[i] : 0ull;
                 colN[i] = in ? C.N0[i] : 0ull;
@@ -1309,14 +1906,18 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     if (!resumed) {
         for (int i = 0; i < t; ++i) {
             int dead;
-            const int c = substitute<W>(colP, colN, prog[i], C.n_x + i, &dead);
+            int c;
+            if constexpr (NW > 1) c = substitute_grp<W, NW>(colP, colN, prog[i], C.n_x + i, &dead);
+            else c = substitute<W>(colP, colN, prog[i], C.n_x + i, &dead);
             cost -= c - 1;
         }
     }
 
     // Live list: variables with a nonzero column, ascending.
     int n_live = 0;
-    {
+    if constexpr (NW > 1) {
+        n_live = build_live_grp<W, NW>(colP, colN, C.n_x + t, live, vpos);
+    } else {
         const int n_v = C.n_x + t;
         for (int b0 = 0; b0 < n_v; b0 += kWave) {
             const int v = b0 + l;
@@ -1344,10 +1945,13 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         // Every unit of a component starts from the same input: its
         // candidates (and second ordering) were counted once, on load.
         m = C.m0;
-        for (int i = l; i < m; i += kWave) cand[i] = C.cand0[i];
+        for (int i = l; i < m; i += NT) cand[i] = C.cand0[i];
         if (need_tl)
-            for (int i = l; i < m; i += kWave) tl[i] = C.tl0[i];
+            for (int i = l; i < m; i += NT) tl[i] = C.tl0[i];
         __syncthreads();
+    } else if constexpr (NW > 1) {
+        m = analyse_full_grp<W, NW>(colP, colN, live, n_live, cand, C.m_cap, &err_flags);
+        if (need_tl) build_tl_grp<W, NW>(colP, colN, live, n_live, cand, m, tl);
     } else {
         m = analyse_full<W>(colP, colN, live, n_live, cand, C.m_cap, &err_flags);
         if (need_tl) build_tl<W>(colP, colN, live, n_live, cand, m, tl);
@@ -1358,9 +1962,21 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         if (R.budget >= 0 && done >= R.budget) break;
         // Cancellation is checked every 256 steps (a read of host memory);
         // the unit keeps its prefix.
-        if ((done & 255) == 255 && R.cancel &&
-            __builtin_amdgcn_readfirstlane(__hip_atomic_load(R.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
-            break;
+        if ((done & 255) == 255 && R.cancel) {
+            int flag;
+            if constexpr (NW > 1) {
+                // One read for the whole unit, so every wave leaves together.
+                __shared__ int cflag;
+                if (l == 0) cflag = __hip_atomic_load(R.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __syncthreads();
+                flag = cflag;
+                __syncthreads();
+            } else {
+                flag = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(R.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+            }
+            if (flag) break;
+        }
 
         // The step draw is consumed by ga, wr, gr and mix only.
         U4 su = {0u, 0u, 0u, 0u};
@@ -1376,18 +1992,27 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 
         long long n_int = 0, n_blk = 0;
         int pick;
-        if constexpr (GP) {
+        if constexpr (GP && NW > 1) {
+            pick = select_gp_grp<W, NW>(cand, m, colP, colN, live, n_live, alpha_q, &n_int);
+        } else if constexpr (GP) {
             pick = select_gp<W>(cand, m, colP, colN, live, n_live, alpha_q, &n_int);
         } else if (s == S_G) {
-            pick = select_g(cand, m);
+            if constexpr (NW > 1) pick = select_g_grp<NW>(cand, m);
+            else pick = select_g(cand, m);
         } else if (s == S_GA) {
-            pick = select_ga(cand, m, su.z);
+            if constexpr (NW > 1) pick = select_ga_grp<NW>(cand, m, su.z);
+            else pick = select_ga(cand, m, su.z);
         } else if (s == S_WR) {
-            pick = select_wr(cand, m, su.z);
+            if constexpr (NW > 1) pick = select_wr_grp<NW>(cand, m, su.z);
+            else pick = select_wr(cand, m, su.z);
         } else {
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             const uint32_t eh = epoch_high((uint32_t)epoch);
-            if constexpr (ADJ) {
+            if constexpr (ADJ && NW > 1) {
+                const int K = gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
+                pick = select_gi_planes_grp<NW>(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0,
+                                                k1, proc, dw, eh, &n_int, &n_blk);
+            } else if constexpr (ADJ) {
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
                                         dw, eh, &n_int, &n_blk);
@@ -1405,9 +2030,15 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         __syncthreads();
         int dead;
         const int k = C.n_x + t + 1;
-        const int c = substitute<W>(colP, colN, key, k - 1, &dead);
+        int c;
+        if constexpr (NW > 1) {
+            c = substitute_grp<W, NW>(colP, colN, key, k - 1, &dead);
+            n_live = update_live_grp<NW>(live, vpos, n_live, key_a(key), key_b(key), dead, k);
+        } else {
+            c = substitute<W>(colP, colN, key, k - 1, &dead);
+            n_live = update_live(live, vpos, n_live, key_a(key), key_b(key), dead, k);
+        }
         if (c != csel) err_flags |= ERR_COUNT_MISMATCH;
-        n_live = update_live(live, vpos, n_live, key_a(key), key_b(key), dead, k);
         if (l == 0) prog[t] = key;
         ++t;
         cost -= c - 1;
@@ -1416,18 +2047,28 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         if constexpr (ADJ) {
             int n_new = 0;
             const int m_old = m;
-            m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
-                                        remap, kpre, key_a(key), key_b(key), k, &n_new, &err_flags);
+            if constexpr (NW > 1)
+                m = update_candidates_db_grp<W, NW>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap,
+                                                    C.m_cap, remap, kpre, key_a(key), key_b(key), k, &n_new,
+                                                    &err_flags);
+            else
+                m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
+                                            remap, kpre, key_a(key), key_b(key), k, &n_new, &err_flags);
             uint64_t* sw = cand;
             cand = cand2;
             cand2 = sw;
-            if (need_tl) update_tl(tl, m_old, remap, newc, n_new);
+            if (need_tl) {
+                if constexpr (NW > 1) update_tl_grp<NW>(tl, m_old, remap, newc, n_new);
+                else update_tl(tl, m_old, remap, newc, n_new);
+            }
         } else {
             m = update_candidates<W>(colP, colN, live, vpos, n_live, cand, m, newc, C.newc_cap, C.m_cap, key_a(key),
                                      key_b(key), k, &err_flags);
         }
     }
-    const unsigned any_err = __ockl_wfred_or_u32((unsigned)err_flags);
+    unsigned any_err;
+    if constexpr (NW > 1) any_err = grp_or<NW>((unsigned)err_flags);
+    else any_err = __ockl_wfred_or_u32((unsigned)err_flags);
     if (any_err && l == 0) atomicOr(err, (int)any_err);
 
     if (l == 0) {
@@ -1450,7 +2091,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 // thus share the launch with the others, while each body is compiled on its
 // own.
 template <int W, bool GS, bool ADJ, bool TL>
-__global__ __launch_bounds__(kWave) void step_kernel(const Segment* __restrict__ segs, int n_segs,
+__global__ __launch_bounds__((kWave * UnitWaves<GS, ADJ>::value)) void step_kernel(const Segment* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ order, uint32_t n_grid,
                                                      int* err, int any_gp) {
     step_body<W, GS, ADJ, TL, false>(segs, n_segs, order, n_grid, err);
