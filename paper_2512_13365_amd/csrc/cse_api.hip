@@ -167,6 +167,12 @@ struct BatchRec {
     size_t dpools_cap = 0;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_order = nullptr;
+    // The groups of a launch run side by side: group g > 0 on side[g - 1],
+    // forked from the launching stream by ev_fork and joined back by
+    // ev_join[g - 1] (also inside a captured round, where they become edges).
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
     hipGraphExec_t gexec = nullptr;
     uint32_t pool_grid_x = 1;
     // Kernel timing (context switch): two events per launch group, the
@@ -666,6 +672,14 @@ void free_batch_device(BatchRec& B) {
     if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
     if (B.gstream) (void)hipStreamDestroy(B.gstream);
     if (B.ev_order) (void)hipEventDestroy(B.ev_order);
+    for (hipStream_t x : B.side)
+        if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : B.ev_join)
+        if (x) (void)hipEventDestroy(x);
+    if (B.ev_fork) (void)hipEventDestroy(B.ev_fork);
+    B.side.clear();
+    B.ev_join.clear();
+    B.ev_fork = nullptr;
     if (B.d_pools) (void)hipFree(B.d_pools);
     B.gexec = nullptr;
     B.gstream = nullptr;
@@ -968,11 +982,15 @@ int collect_times(cse_ctx* ctx, BatchRec& B) {
     return CSE_OK;
 }
 
+// Every group's launch.  Groups hold disjoint units, so they run side by
+// side: the first on s, the others on the batch's side streams, forked from
+// s before and joined back into s after (a round's tail of long units in one
+// class then overlaps the other classes).
 int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s, bool timed = false) {
     if (timed && !B.t_pending.empty()) {
         // Launches of an earlier run not read yet (a relaunch queued behind
         // it on the same stream): read them before their events are reused.
-        HIP_TRY(ctx, hipEventSynchronize(B.tev[2 * B.t_pending.back() + 1]));
+        for (int g : B.t_pending) HIP_TRY(ctx, hipEventSynchronize(B.tev[2 * g + 1]));
         int rc = collect_times(ctx, B);
         if (rc) return rc;
     }
@@ -981,23 +999,42 @@ int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s, bool timed = false) 
         B.tev.resize(2 * B.groups.size(), nullptr);
         for (size_t i = have; i < B.tev.size(); ++i) HIP_TRY(ctx, hipEventCreate(&B.tev[i]));
     }
+    const size_t n_side = B.groups.empty() ? 0 : B.groups.size() - 1;
+    while (B.side.size() < n_side) {
+        hipStream_t x = nullptr;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        B.side.push_back(x);
+        hipEvent_t ev = nullptr;
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        B.ev_join.push_back(ev);
+    }
+    if (n_side) {
+        if (!B.ev_fork) HIP_TRY(ctx, hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventRecord(B.ev_fork, s));
+        for (size_t i = 0; i < n_side; ++i) HIP_TRY(ctx, hipStreamWaitEvent(B.side[i], B.ev_fork, 0));
+    }
     for (size_t gi = 0; gi < B.groups.size(); ++gi) {
         const LaunchGroup& G = B.groups[gi];
-        if (timed) HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi], s));
+        const hipStream_t gs = gi == 0 ? s : B.side[gi - 1];
+        if (timed) HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi], gs));
         int rc;
         if (G.gs && G.adj)
-            rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                      : launch_group_gs<true, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+            rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, gs)
+                      : launch_group_gs<true, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
         else if (G.gs)
-            rc = launch_group_gs<true, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+            rc = launch_group_gs<true, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
         else
-            rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s)
-                       : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, s);
+            rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs)
+                       : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
         if (rc) return rc;
         if (timed) {
-            HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi + 1], s));
+            HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi + 1], gs));
             B.t_pending.push_back((int)gi);
         }
+    }
+    for (size_t i = 0; i < n_side; ++i) {
+        HIP_TRY(ctx, hipEventRecord(B.ev_join[i], B.side[i]));
+        HIP_TRY(ctx, hipStreamWaitEvent(s, B.ev_join[i], 0));
     }
     return CSE_OK;
 }
