@@ -248,8 +248,11 @@ size_t bulk_bytes(const DevComp& c) {
     return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0, c.kbits).bytes;
 }
 size_t lds_bytes(const DevComp& c) {
-    if (c.gs && c.tl) return csek::table_layout(c.n_x + c.n_fmax, c.m_cap, c.kbits).bytes;
-    return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(c.n_x + c.n_fmax);
+    const int n_vmax = c.n_x + c.n_fmax;
+    if (c.gs && c.tl) return csek::table_layout(n_vmax, c.m_cap, c.kbits).bytes;
+    // HBM state with ranges (units of several waves): lists and new-pair table.
+    if (c.gs && c.adj) return csek::list_bytes(n_vmax) + csek::newpair_table_bytes(n_vmax);
+    return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(n_vmax);
 }
 
 void free_component(DevComp& c) {
@@ -400,9 +403,9 @@ int pick_layout(cse_ctx* ctx, DevComp& c) {
     // touches far less of that state per step than building masks does.
     if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
     // Every layout keeps the variable lists in LDS.
-    if (csek::list_bytes(n_vmax) > ctx->lds_max)
+    if (lds_bytes(c) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax,
-                    csek::list_bytes(n_vmax), ctx->lds_max);
+                    lds_bytes(c), ctx->lds_max);
     return CSE_OK;
 }
 
@@ -1442,7 +1445,7 @@ int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t
     if (scheme_busy(ctx, scheme_id)) return fail(ctx, CSE_EBUSY, "scheme %d has jobs; release them first", scheme_id);
     DevComp probe = dc;
     set_layout(probe, layout);
-    if ((!probe.gs || probe.tl) && lds_bytes(probe) > ctx->lds_max)
+    if (lds_bytes(probe) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "layout %d needs %zu B of LDS per unit (max %zu)", layout, lds_bytes(probe),
                     ctx->lds_max);
     set_layout(dc, layout);
@@ -1476,7 +1479,7 @@ int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, vo
         for (int lay = 0; lay <= (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE); ++lay) {
             DevComp probe = dc;
             set_layout(probe, lay);
-            if ((!probe.gs || probe.tl) && lds_bytes(probe) > ctx->lds_max) continue;
+            if (lds_bytes(probe) > ctx->lds_max) continue;
             if (!probe.adj && !masks_fit) continue;
             float ms = 0.f;
             rc = probe_layout(ctx, probe, pc, (hipStream_t)stream, best_ms, &ms);

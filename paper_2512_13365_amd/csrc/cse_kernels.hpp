@@ -240,6 +240,11 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
 }
 // live and vpos: n_vmax int32 each.
 __host__ __device__ inline size_t list_bytes(int n_vmax) { return ((size_t)n_vmax * 8 + 15) & ~size_t(15); }
+// Units of several waves (HBM state, gi over ranges) keep the new-pair table
+// of the candidate update after the lists: per 64 live positions, the
+// ballots of the fresh variable's '+' and '-' pairs (u64 each) and the number
+// of new pairs before them (i32).
+__host__ __device__ inline size_t newpair_table_bytes(int n_vmax) { return (size_t)((n_vmax + 63) / 64) * 24; }
 
 // Units with state in HBM slots may keep the per-step tables of the range
 // form of gi (ranges, places in the second ordering, weight bit-planes) in
@@ -250,7 +255,7 @@ struct TableLayout {
 };
 __host__ __device__ inline TableLayout table_layout(int n_vmax, int m_cap, int kbits) {
     TableLayout T;
-    size_t o = list_bytes(n_vmax);
+    size_t o = list_bytes(n_vmax) + newpair_table_bytes(n_vmax);  // HBM state with ranges: several waves
     T.rng = o;  o += (size_t)n_vmax * 16;
     T.tinv = o; o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
     T.pl = o;   o += (size_t)2 * kbits * plane_words(m_cap) * 4;
@@ -1364,8 +1369,9 @@ __device__ int analyse_full_grp(const uint64_t* colP, const uint64_t* colN, cons
 template <int W, int NW>
 __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
                                         const uint64_t* src, int m, uint64_t* dst, uint64_t* newc, int newc_cap,
-                                        int m_cap, int32_t* remap, int32_t* kpre, int a, int b, int k,
-                                        int* n_new_out, int* err_flags) {
+                                        int m_cap, int32_t* remap, int32_t* kpre, const int32_t* vpos,
+                                        uint64_t* npm, int32_t* npb, int a, int b, int k, int* n_new_out,
+                                        int* err_flags) {
     const int t = grp_tid();
     int n_new = 0;
     for (int base = 0; base < n_live - 1; base += kWave * NW) {
@@ -1386,6 +1392,14 @@ __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* co
             const int q = pos + (hp ? 1 : 0);
             if (q < newc_cap) newc[q] = pair_key(x, k, 1) | ((uint64_t)c.y << 32);
             else *err_flags |= ERR_NEW_OVERFLOW;
+        }
+        // This wave's 64 live positions: which have new pairs, and how many
+        // new pairs come before them.
+        const int cb = base + kWave * grp_wave();
+        if (grp_lane() == 0 && cb < n_live - 1) {
+            npm[2 * (cb / kWave)] = bp;
+            npm[2 * (cb / kWave) + 1] = bm;
+            npb[cb / kWave] = n_new + off;
         }
         n_new += tot;
     }
@@ -1410,10 +1424,14 @@ __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* co
         const int off = grp_offset<NW>(popc64(bk), &tot);
         const int kept = mf + off + lanes_below(bk);
         if (valid) {
-            int lo = 0, hi = n_new;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (key_a((uint32_t)newc[mid]) < qa) lo = mid + 1; else hi = mid;
+            // New pairs (x, k) with x < qa: those from the live positions
+            // below qa's (a kept pair's first variable is live).
+            int lo = 0;
+            if (keep) {
+                const int pv = vpos[qa - 1];
+                const int cw = pv / kWave;
+                const uint64_t below = (1ull << (pv % kWave)) - 1ull;
+                lo = npb[cw] + popc64(npm[2 * cw] & below) + popc64(npm[2 * cw + 1] & below);
             }
             const int dest = kept + lo;
             kpre[i] = kept;
@@ -1505,13 +1523,14 @@ __device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const u
     __syncthreads();
 }
 
+// As gi_prepare; *T receives the total profit sum (c - 1) over the candidates.
 template <int NW>
 __device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
-                              int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits) {
+                              int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits, int* T) {
     const int l = grp_lane();
     for (int i = grp_tid(); i < 4 * n_live; i += kWave * NW) rng[i] = 0;
     __syncthreads();
-    int wmax = 0;
+    int wmax = 0, wsum = 0;
     for (int base = 0; base < m; base += kWave * NW) {
         const int cb = base + kWave * grp_wave();  // this wave's chunk
         if (cb >= m) continue;
@@ -1542,6 +1561,7 @@ __device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, c
             tinv[q] = i;
         }
         wmax = w > wmax ? w : wmax;
+        wsum += w;
         const int word = 2 * (cb / kWave);
         for (int k = 0; k < kbits; ++k) {
             const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
@@ -1553,6 +1573,7 @@ __device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, c
     }
     __syncthreads();
     wmax = grp_max<NW>(wmax);
+    *T = grp_sum<NW>(wsum);
     int K = 0;
     while (K < kbits && (wmax >> K) != 0) ++K;
     return K;
@@ -1572,11 +1593,10 @@ __device__ __forceinline__ int gi_argmax_grp(long long best_h, int best_p) {
 }
 
 template <int NW>
-__device__ int select_gi_planes_grp(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
+__device__ int select_gi_planes_grp(const uint64_t* cand, int m, int T, const int32_t* vpos, const int32_t* rng,
                                     const int32_t* tinv, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
                                     uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
                                     long long* n_int, long long* n_blk) {
-    const int T = total_profit_grp<NW>(cand, m);
     const uint32_t* plc = pl;
     const uint32_t* plt = pl + kbits * pw;
     long long best_h = -1;
@@ -1840,6 +1860,9 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     const int pw = plane_words(C.m_cap);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
+    // New-pair table of units of several waves (after the lists).
+    uint64_t* npm = (uint64_t*)(lists + list_bytes(n_vmax));
+    int32_t* npb = (int32_t*)(npm + 2 * ((n_vmax + 63) / 64));
 
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
 
@@ -2009,9 +2032,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             const uint32_t eh = epoch_high((uint32_t)epoch);
             if constexpr (ADJ && NW > 1) {
-                const int K = gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
-                pick = select_gi_planes_grp<NW>(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0,
-                                                k1, proc, dw, eh, &n_int, &n_blk);
+                int T;
+                const int K = gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits, &T);
+                pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q,
+                                                k0, k1, proc, dw, eh, &n_int, &n_blk);
             } else if constexpr (ADJ) {
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
@@ -2049,8 +2073,8 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             const int m_old = m;
             if constexpr (NW > 1)
                 m = update_candidates_db_grp<W, NW>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap,
-                                                    C.m_cap, remap, kpre, key_a(key), key_b(key), k, &n_new,
-                                                    &err_flags);
+                                                    C.m_cap, remap, kpre, vpos, npm, npb, key_a(key), key_b(key), k,
+                                                    &n_new, &err_flags);
             else
                 m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
                                             remap, kpre, key_a(key), key_b(key), k, &n_new, &err_flags);
