@@ -28,10 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CSE substitution steps/s and time-to-best additions; batched vs plain, 1 GPU"
-# int32 VALU lane operations per second of MI355X: 256 CUs x 4 SIMDs x 16
-# lanes x 2.4 GHz (the 157.3 TFLOP/s fp32 vector peak counts an FMA as two
-# flops and packed fp32 as two lanes).
-PEAK_ALU_OPS = 256 * 4 * 16 * 2.4e9
+# int32 VALU lane operations per second of MI355X: 256 CUs x 4 SIMDs x 32
+# lanes per clock x 2.4 GHz = 78.6 T, the rate behind the published 157.3
+# TFLOP/s fp32 vector peak (an FMA counts as two flops).  32-bit integer
+# adds issue at that rate: the VALU microbenchmark (csrc/cse_calib.hip)
+# measures 69.4 T lane-op/s, one wave64 v_add_u32 per 2.2 clocks per SIMD.
+PEAK_ALU_OPS = 256 * 4 * 32 * 2.4e9
 
 
 def measured_traffic(kernel, workload):
@@ -59,6 +61,36 @@ def measured_traffic(kernel, workload):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def calibrate():
+    """Measured on-chip peaks: 32-bit integer VALU issue (a full-occupancy
+    grid of independent v_add_u32 chains, 128 per wave and iteration) and LDS
+    read bandwidth (conflict-free ds_read_b128), from the microbenchmarks in
+    csrc/cse_calib.hip, timed with HIP events."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2512_13365_amd", "libcse_calib.so")
+    L = ctypes.CDLL(path)
+    L.cse_calib_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_double)]
+    L.cse_calib_run.restype = ctypes.c_int
+    ms, work = ctypes.c_float(), ctypes.c_double()
+    # VALU: 8 workgroups of 4 waves per CU (32 waves, the most a CU holds).
+    blocks, iters = 256 * 8, 20000
+    rc = L.cse_calib_run(0, blocks, iters, ctypes.byref(ms), ctypes.byref(work))
+    if rc:
+        raise RuntimeError(f"VALU microbenchmark failed: HIP error {rc}")
+    valu_instr_s = blocks * 4 * work.value / (ms.value * 1e-3)
+    valu = {"lane_ops_per_s": valu_instr_s * 64, "wave_instructions_per_s": valu_instr_s, "ms": ms.value,
+            "grid": f"{blocks} x 256 lanes, {iters} iterations of 128 independent v_add_u32 per wave"}
+    # LDS: 2 workgroups of 64 KiB per CU.
+    blocks, iters = 256 * 2, 100000
+    rc = L.cse_calib_run(1, blocks, iters, ctypes.byref(ms), ctypes.byref(work))
+    if rc:
+        raise RuntimeError(f"LDS microbenchmark failed: HIP error {rc}")
+    lds = {"bytes_per_s": work.value / (ms.value * 1e-3), "ms": ms.value,
+           "grid": f"{blocks} x 256 lanes, {iters} iterations of 8 ds_read_b128 per lane"}
+    return {"valu": valu, "lds": lds}
 
 
 def time_to_best(res, tick_hz):
@@ -542,6 +574,8 @@ def main():
                     help="4x4x4 / 6x6x6: how the input's pair counts are computed (same results)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
     ap.add_argument("--serve-budget-gib", type=int, default=96, help="serving: device state budget")
+    ap.add_argument("--calibrate-only", action="store_true",
+                    help="only run the VALU and LDS microbenchmarks and print their line")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -566,6 +600,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_calibrate} MiB read + {args.copy_calibrate} MiB written")
         del src, dst
+    if args.calibrate_only:
+        print(json.dumps({"measured_peaks": calibrate()}), flush=True)
+        return
     ctx = cse.cse_ctx_create(0)
     try:
         if args.workload == "batch":
@@ -589,6 +626,11 @@ def main():
             out = run_driver(args, cse, workloads, torch, ctx, stream)
         else:
             out = run_serve(args, cse, workloads, torch, ctx, stream)
+        if "roofline" in out:
+            # Peaks measured on this GPU beside the derived ones (context).
+            out["roofline"]["measured_peaks"] = calibrate()
+            out["roofline"]["frac_of_measured_valu"] = (
+                out["roofline"]["achieved"] * 1e12 / out["roofline"]["measured_peaks"]["valu"]["lane_ops_per_s"])
     finally:
         cse.cse_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
