@@ -250,8 +250,9 @@ size_t bulk_bytes(const DevComp& c) {
 size_t lds_bytes(const DevComp& c) {
     const int n_vmax = c.n_x + c.n_fmax;
     if (c.gs && c.tl) return csek::table_layout(n_vmax, c.m_cap, c.kbits).bytes;
-    // HBM state with ranges (units of several waves): lists and new-pair table.
-    if (c.gs && c.adj) return csek::list_bytes(n_vmax) + csek::newpair_table_bytes(n_vmax);
+    // HBM state with ranges (units of several waves): lists, new-pair table
+    // and the LDS budget for gi's per-step tables.
+    if (c.gs && c.adj) return csek::list_bytes(n_vmax) + csek::newpair_table_bytes(n_vmax) + csek::kGsTableBudget;
     return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(n_vmax);
 }
 

@@ -244,7 +244,13 @@ __host__ __device__ inline size_t list_bytes(int n_vmax) { return ((size_t)n_vma
 // of the candidate update after the lists: per 64 live positions, the
 // ballots of the fresh variable's '+' and '-' pairs (u64 each) and the number
 // of new pairs before them (i32).
-__host__ __device__ inline size_t newpair_table_bytes(int n_vmax) { return (size_t)((n_vmax + 63) / 64) * 24; }
+__host__ __device__ inline size_t newpair_table_bytes(int n_vmax) {
+    return ((size_t)((n_vmax + 63) / 64) * 24 + 15) & ~size_t(15);
+}
+// After that table they keep a fixed LDS budget for gi's per-step tables
+// (ranges and weight planes), used at every step whose tables fit it; steps
+// whose tables do not fit use the copies in the HBM slot.
+constexpr int kGsTableBudget = 12 * 1024;
 
 // Units with state in HBM slots may keep the per-step tables of the range
 // form of gi (ranges, places in the second ordering, weight bit-planes) in
@@ -1523,14 +1529,32 @@ __device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const u
     __syncthreads();
 }
 
-// As gi_prepare; *T receives the total profit sum (c - 1) over the candidates.
+// Total profit T = sum (c - 1) over the candidates and the number K of
+// weight bit-planes (bit length of the largest c - 1, at most kbits).
 template <int NW>
-__device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
-                              int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits, int* T) {
+__device__ __forceinline__ void gi_totals_grp(const uint64_t* cand, int m, int kbits, int* T, int* K) {
+    int tot = 0, wmax = 0;
+    for (int q = grp_tid(); q < m; q += kWave * NW) {
+        const int w = entry_c(cand[q]) - 1;
+        tot += w;
+        wmax = w > wmax ? w : wmax;
+    }
+    *T = grp_sum<NW>(tot);
+    wmax = grp_max<NW>(wmax);
+    int k = 0;
+    while (k < kbits && (wmax >> k) != 0) ++k;
+    *K = k;
+}
+
+// As gi_prepare, with the K planes of each ordering (the canonical
+// ordering's at pl, the second ordering's at pl + K pw).
+template <int NW>
+__device__ __forceinline__ void gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m,
+                                               const int32_t* vpos, int n_live, int32_t* rng, int32_t* tinv,
+                                               uint32_t* pl, int pw, int K) {
     const int l = grp_lane();
     for (int i = grp_tid(); i < 4 * n_live; i += kWave * NW) rng[i] = 0;
     __syncthreads();
-    int wmax = 0, wsum = 0;
     for (int base = 0; base < m; base += kWave * NW) {
         const int cb = base + kWave * grp_wave();  // this wave's chunk
         if (cb >= m) continue;
@@ -1560,23 +1584,16 @@ __device__ int gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m, c
             if (b != nb) rng[4 * vb + 3] = i + 1;
             tinv[q] = i;
         }
-        wmax = w > wmax ? w : wmax;
-        wsum += w;
         const int word = 2 * (cb / kWave);
-        for (int k = 0; k < kbits; ++k) {
+        for (int k = 0; k < K; ++k) {
             const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
             if (l < 2) {
                 pl[k * pw + word + l] = (uint32_t)(l ? bc >> 32 : bc);
-                pl[(kbits + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
+                pl[(K + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
             }
         }
     }
     __syncthreads();
-    wmax = grp_max<NW>(wmax);
-    *T = grp_sum<NW>(wsum);
-    int K = 0;
-    while (K < kbits && (wmax >> K) != 0) ++K;
-    return K;
 }
 
 template <int NW>
@@ -1592,13 +1609,15 @@ __device__ __forceinline__ int gi_argmax_grp(long long best_h, int best_p) {
     return grp_min<NW>(best_h == hmax ? best_p : 0x7FFFFFFF);
 }
 
+// As select_gi_planes over the tables of gi_prepare_grp.
 template <int NW>
-__device__ int select_gi_planes_grp(const uint64_t* cand, int m, int T, const int32_t* vpos, const int32_t* rng,
-                                    const int32_t* tinv, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
-                                    uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
-                                    long long* n_int, long long* n_blk) {
+__device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m, int T, const int32_t* vpos,
+                                                    const int32_t* rng, const int32_t* tinv, const uint32_t* pl,
+                                                    int pw, int K, uint32_t aq, uint32_t bq, uint32_t k0,
+                                                    uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
+                                                    long long* n_int, long long* n_blk) {
     const uint32_t* plc = pl;
-    const uint32_t* plt = pl + kbits * pw;
+    const uint32_t* plt = pl + K * pw;
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
@@ -1860,9 +1879,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     const int pw = plane_words(C.m_cap);
     uint32_t* live = (uint32_t*)lists;
     int32_t* vpos = (int32_t*)(lists + (size_t)n_vmax * 4);
-    // New-pair table of units of several waves (after the lists).
+    // New-pair table and gi table budget of units of several waves (after the lists).
     uint64_t* npm = (uint64_t*)(lists + list_bytes(n_vmax));
     int32_t* npb = (int32_t*)(npm + 2 * ((n_vmax + 63) / 64));
+    char* gtab = lists + list_bytes(n_vmax) + newpair_table_bytes(n_vmax);
 
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
 
@@ -2032,10 +2052,22 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             const uint32_t dw = domain(TAG_COIN, C.comp, (uint32_t)epoch, (uint32_t)t);
             const uint32_t eh = epoch_high((uint32_t)epoch);
             if constexpr (ADJ && NW > 1) {
-                int T;
-                const int K = gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits, &T);
-                pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q,
-                                                k0, k1, proc, dw, eh, &n_int, &n_blk);
+                int T, K;
+                gi_totals_grp<NW>(cand, m, C.kbits, &T, &K);
+                // The ranges and planes go to the unit's LDS budget when they
+                // fit it (the range tables of TL units are in LDS anyway).
+                const int pw_m = plane_words(m);
+                if (!TL && 16 * n_live + 8 * K * pw_m <= kGsTableBudget) {
+                    int32_t* rng_l = (int32_t*)gtab;
+                    uint32_t* pl_l = (uint32_t*)(gtab + 16 * (size_t)n_live);
+                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng_l, tinv, pl_l, pw_m, K);
+                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng_l, tinv, pl_l, pw_m, K, alpha_q, beta_q,
+                                                    k0, k1, proc, dw, eh, &n_int, &n_blk);
+                } else {
+                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, K);
+                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng, tinv, pl, pw, K, alpha_q, beta_q, k0,
+                                                    k1, proc, dw, eh, &n_int, &n_blk);
+                }
             } else if constexpr (ADJ) {
                 const int K = gi_prepare(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, C.kbits);
                 pick = select_gi_planes(cand, m, vpos, rng, tinv, pl, pw, C.kbits, K, alpha_q, beta_q, k0, k1, proc,
