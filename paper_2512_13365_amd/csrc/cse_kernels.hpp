@@ -848,11 +848,21 @@ struct CoinStream {
         const int s = u & 3;
         return s == 0 ? a0 : s == 1 ? a1 : s == 2 ? a2 : a3;
     }
-    // Coins j .. j + 31 (bit i is coin j + i).
-    __device__ uint32_t bits32(int j) {
+    // Block 0 drawn now, by every lane at once (a stream's first block is
+    // nearly always needed; drawn lazily it would run once per lane group
+    // that reaches it).
+    __device__ void first_block() {
+        const U4 x = philox10(proc, dw, kp, eh, k0, k1);
+        a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
+        cb = 0;
+        has_nb = false;
+    }
+    // Coins j .. j + n - 1 in bits 0 .. n - 1 (1 <= n <= 32; higher bits
+    // unspecified).  A block is drawn only if one of these coins is in it.
+    __device__ uint32_t bits(int j, int n) {
         const int u = j >> 5, sh = j & 31;
         const uint32_t w0 = word(u);
-        if (sh == 0) return w0;
+        if (sh + n <= 32) return w0 >> sh;
         uint32_t w1;
         if ((u & 3) != 3) {
             const int s = (u & 3) + 1;
@@ -874,7 +884,7 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, 
         const int sh = pos & 31;
         const int n = min(32 - sh, end - pos);
         const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
-        const uint32_t cw = co.bits32(j) << sh;
+        const uint32_t cw = co.bits(j, n) << sh;
         const int wi = pos >> 5;
         for (int k = 0; k < K; ++k) {
             const uint32_t x = pl[k * pw + wi] & msk;
@@ -1023,8 +1033,9 @@ __device__ __forceinline__ void mask_walk(const uint32_t* Ma, const uint32_t* Mb
         uint32_t u = Ma[w] & (w == self_w ? ~self_bit : 0xFFFFFFFFu);
         if (Mb) u = Mb[w] & ~Ma[w];
         if (u == 0) continue;
-        uint32_t cw = co.bits32(j);
-        j += __popc(u);
+        const int nm = __popc(u);
+        uint32_t cw = co.bits(j, nm);
+        j += nm;
         const uint16_t* wrow = wt + (w << 5);
         do {
             const int bit = __builtin_ctz(u);
@@ -1635,10 +1646,12 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m,
         int I = 0, X = 0, ja = 0, jb = 0;
         CoinStream co;
         co.init(proc, dw, kp, eh, k0, k1);
+        co.first_block();
         plane_window(plt, pw, K, ra.z, ra.w, ja, co, I, X);
         plane_window(plc, pw, K, ra.x, p, ja, co, I, X);
         plane_window(plc, pw, K, p + 1, ra.y, ja, co, I, X);
         co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
+        co.first_block();
         plane_window(plt, pw, K, rb.z, t_ab, jb, co, I, X);
         plane_window(plt, pw, K, t_ab + n_ab, rb.w, jb, co, I, X);
         plane_window(plc, pw, K, rb.x, rb.y, jb, co, I, X);
