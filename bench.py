@@ -190,9 +190,9 @@ def run_plain44(args, cse, workloads, torch, ctx, stream):
         pcie_inclusive={"readback_ms": readback_s * 1e3,
                         "steps_per_s": subs / (per_step + readback_s),
                         "note": "job plus host copy of all unit results and programs"},
-        roofline={"kernel": "step_kernel<1, false, false, false>", "bound": "alu", "achieved": achieved / 1e12,
+        roofline={"kernel": "step_kernel<1, false, false, false, 1>", "bound": "alu", "achieved": achieved / 1e12,
                   "peak": PEAK_ALU_OPS / 1e12, "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS,
-                  "traffic": measured_traffic("step_kernel<1, false, false, false>", "plain_4x4x4"),
+                  "traffic": measured_traffic("step_kernel<1, false, false, false, 1>", "plain_4x4x4"),
                   "traffic_unit": "HBM bytes per launch",
                   "algorithmic_ops_per_launch": ops / launches,
                   "avg_launch_ms": avg_launch * 1e3})
@@ -218,8 +218,9 @@ BATCH_NAME = ("batch-32-uneven: 32 schemes, (n,m,p) uniform in {2..7}^3, r = rou
 
 def kernel_name(W, layout):
     gs, adj, tl = bool(layout & 1), bool(layout & 2), bool(layout & 4)
+    nw = 1 << ((layout >> 3) & 3)
     b = lambda x: "true" if x else "false"
-    return f"step_kernel<{W}, {b(gs)}, {b(adj)}, {b(tl)}>"
+    return f"step_kernel<{W}, {b(gs)}, {b(adj)}, {b(tl)}, {nw}>"
 
 
 def scheme_pass(cse, ctx, stream, dev, cfgs, batched):
@@ -421,7 +422,7 @@ def run_6x6x6(args, cse, workloads, torch, ctx, stream):
     return base_line(
         args, value=subs * args.steps / gpu_s, unit="substitution steps/s",
         ms_per_step=per_job * 1e3,
-        roofline={"kernel": "step_kernel<3, true, true, false> (U, V) and step_kernel<1, false, false, false> (W^T); "
+        roofline={"kernel": "step_kernel<3, true, true, false, 4> (U, V) and step_kernel<1, false, false, false, 1> (W^T); "
                             "achieved over the whole job, sharing rounds included",
                   "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,
                   "unit": "T int32 lane-op/s", "frac": achieved / PEAK_ALU_OPS, "traffic": None,

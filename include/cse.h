@@ -70,6 +70,13 @@ extern "C" {
 #define CSE_LAYOUT_RANGE   2   /* gi over per-variable ranges instead of masks */
 #define CSE_LAYOUT_LDS_TABLES 4 /* with HBM | RANGE only: gi's per-step range tables in LDS
                                  * (chosen explicitly; loading and cse_autotune never pick it) */
+/* Waves per unit (threads per process), bits 3-4 of a layout: one wave
+ * (neither bit), two or four; more than one only with CSE_LAYOUT_RANGE.
+ * Loading gives HBM | RANGE components four waves and the others one;
+ * cse_autotune times one, two and four for the range form. */
+#define CSE_LAYOUT_WAVES_SHIFT 3
+#define CSE_LAYOUT_WAVES2  8
+#define CSE_LAYOUT_WAVES4  16
 
 /* States of a job submitted to a server. */
 #define CSE_JOB_QUEUED  0   /* waiting for admission */
@@ -145,16 +152,19 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
  * `comp`; *current (may be NULL) receives the layout in effect before the
  * call.  Loading picks a layout from the system's size: the range form of gi
  * for large candidate sets, and state in HBM with the range form when the
- * state would leave room in a CU's 160 KB of LDS for fewer than four units.
- * Valid layouts: 0..3 and HBM | RANGE | LDS_TABLES; CSE_EINVAL otherwise.
- * CSE_EBUSY while a job of the scheme exists; CSE_ENOMEM if the state does not
- * fit in LDS for an LDS layout.  Unit results are the same in every layout. */
+ * state would leave room in a CU's 160 KB of LDS for fewer than four units
+ * (those run on four waves).  Valid layouts: 0..3 and HBM | RANGE |
+ * LDS_TABLES, each range layout with or without CSE_LAYOUT_WAVES2 or
+ * CSE_LAYOUT_WAVES4; CSE_EINVAL otherwise.  CSE_EBUSY while a job of the
+ * scheme exists; CSE_ENOMEM if the unit's LDS share does not fit a
+ * workgroup.  Unit results are the same in every layout. */
 int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t layout, int32_t* current);
 
 /* Pick each component's fastest layout by timing bounded probe runs of
  * `cfg` (at most 1024 processes, 32 steps each, no sharing) on `stream`, for
  * every layout 0..3 that fits (the mask form of gi only where the input's masks
- * fit their capacity); layouts[c] (may be NULL) receives the choice.
+ * fit their capacity), the range layouts on one, two and four waves per
+ * unit; layouts[c] (may be NULL) receives the choice.
  * Blocking.  CSE_EBUSY while a job of the scheme exists. */
 int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, void* stream, int32_t layouts[3]);
 

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcse.so")
 STRATEGIES = ("g", "ga", "wr", "gr", "gi", "mix", "gp")
 CSE_COUNT_AUTO, CSE_COUNT_POPCOUNT, CSE_COUNT_MFMA = 0, 1, 2
 CSE_LAYOUT_HBM, CSE_LAYOUT_RANGE, CSE_LAYOUT_LDS_TABLES = 1, 2, 4
+CSE_LAYOUT_WAVES_SHIFT, CSE_LAYOUT_WAVES2, CSE_LAYOUT_WAVES4 = 3, 8, 16
 
 STATUS = {0: "CSE_OK", -1: "CSE_EINVAL", -2: "CSE_ENOMEM", -3: "CSE_ERANGE", -4: "CSE_EHIP",
           -5: "CSE_EBUSY", -6: "CSE_ENOENT", -7: "CSE_ECANCELED"}

@@ -30,6 +30,7 @@
 #include "cse_input.hpp"
 #include "cse_kernels.hpp"
 #include "cse_share.hpp"
+#include "cse_step.hpp"
 
 // Working memory of cse_reduce_static, for callers that cannot allocate:
 // a file-scope device array, one copy per GPU, kept until the process ends.
@@ -66,6 +67,7 @@ struct DevComp {
     bool gs = false;   // bulk state in HBM
     bool adj = false;  // gi over per-variable ranges (large candidate sets)
     bool tl = false;   // with gs and adj: the range tables in LDS
+    int nw = 1;        // waves per unit (1, 2 or 4; more than one with adj)
     int kbits = 1;     // weight bit-planes per ordering
     long long occ0 = 0;
     int8_t* d_A = nullptr;        // the input, rows x cols row-major
@@ -123,6 +125,7 @@ struct LaunchGroup {
     bool gs = false;
     bool adj = false;
     bool tl = false;
+    int nw = 1;                     // waves per unit
     bool gp = false;                // some job gives Greedy-Potential a weight
     uint32_t n_grid = 0;
     size_t lds = 0;
@@ -250,10 +253,10 @@ size_t bulk_bytes(const DevComp& c) {
 size_t lds_bytes(const DevComp& c) {
     const int n_vmax = c.n_x + c.n_fmax;
     if (c.gs && c.tl) return csek::table_layout(n_vmax, c.m_cap, c.kbits).bytes;
-    // HBM state with ranges (units of several waves): lists, new-pair table
-    // and the LDS budget for gi's per-step tables.
-    if (c.gs && c.adj) return csek::list_bytes(n_vmax) + csek::newpair_table_bytes(n_vmax) + csek::kGsTableBudget;
-    return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(n_vmax);
+    // Units of several waves keep the new-pair table after the lists, and
+    // with HBM state the LDS budget for gi's per-step tables.
+    const size_t multi = c.nw > 1 ? csek::newpair_table_bytes(n_vmax) + (c.gs ? csek::kGsTableBudget : 0) : 0;
+    return (c.gs ? 0 : bulk_bytes(c)) + csek::list_bytes(n_vmax) + multi;
 }
 
 void free_component(DevComp& c) {
@@ -348,23 +351,29 @@ int ensure_gram_lists(cse_ctx* ctx, DevComp& c) {
 }
 
 // Layout of a component (CSE_LAYOUT_*): bulk state in HBM slots instead of
-// LDS, and gi over per-variable ranges instead of masks.  Results do not
-// depend on it.
-// Layouts: LDS or HBM state, masks or ranges, and for HBM state with ranges
-// the range tables in LDS.
-constexpr int kLayoutMax = CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE | CSE_LAYOUT_LDS_TABLES;
+// LDS, gi over per-variable ranges instead of masks, for HBM state with
+// ranges the range tables in LDS, and the waves per unit (1, 2 or 4; more
+// than one only with ranges).  Results do not depend on it.
+constexpr int kLayoutMax = CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE | CSE_LAYOUT_LDS_TABLES | CSE_LAYOUT_WAVES4;
+// Waves per unit that loading gives HBM-state range-form components.
+constexpr int kDefaultHbmRangeWaves = 4;
 bool layout_valid(int layout) {
     if (layout < 0 || layout > kLayoutMax) return false;
+    const int wb = (layout >> CSE_LAYOUT_WAVES_SHIFT) & 3;
+    if (wb == 3 || (wb && !(layout & CSE_LAYOUT_RANGE))) return false;
     return !(layout & CSE_LAYOUT_LDS_TABLES) || (layout & (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE)) ==
                                                       (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE);
 }
+int waves_bits(int nw) { return nw == 4 ? CSE_LAYOUT_WAVES4 : nw == 2 ? CSE_LAYOUT_WAVES2 : 0; }
 int layout_code(const DevComp& c) {
-    return (c.gs ? CSE_LAYOUT_HBM : 0) | (c.adj ? CSE_LAYOUT_RANGE : 0) | (c.tl ? CSE_LAYOUT_LDS_TABLES : 0);
+    return (c.gs ? CSE_LAYOUT_HBM : 0) | (c.adj ? CSE_LAYOUT_RANGE : 0) | (c.tl ? CSE_LAYOUT_LDS_TABLES : 0) |
+           waves_bits(c.nw);
 }
 void set_layout(DevComp& c, int layout) {
     c.gs = (layout & CSE_LAYOUT_HBM) != 0;
     c.adj = (layout & CSE_LAYOUT_RANGE) != 0;
     c.tl = (layout & CSE_LAYOUT_LDS_TABLES) != 0;
+    c.nw = 1 << ((layout >> CSE_LAYOUT_WAVES_SHIFT) & 3);
 }
 
 // Sizes of a component from its nonzeros, pair occurrences and naive count
@@ -403,6 +412,8 @@ int pick_layout(cse_ctx* ctx, DevComp& c) {
     // Too large for four units per CU: state in HBM, and gi over ranges, which
     // touches far less of that state per step than building masks does.
     if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
+    // Those units wait on memory; they run on several waves.
+    c.nw = c.gs && c.adj ? kDefaultHbmRangeWaves : 1;
     // Every layout keeps the variable lists in LDS.
     if (lds_bytes(c) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax,
@@ -705,36 +716,34 @@ void free_batch_device(BatchRec& B) {
     B.segs_cap = B.counts_cap = B.order_cap = 0;
 }
 
-// Dynamic LDS above 64 KB must be allowed per kernel before launches (and
-// before a launch is captured into a graph).
-template <int W, bool GS, bool ADJ, bool TL>
-int set_lds_limit_w(cse_ctx* ctx, size_t lds) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)csek::step_kernel<W, GS, ADJ, TL>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    return CSE_OK;
-}
-template <bool GS, bool ADJ, bool TL>
-int set_lds_limit_gs(cse_ctx* ctx, int W, size_t lds) {
-    switch (W) {
-    case 1: return set_lds_limit_w<1, GS, ADJ, TL>(ctx, lds);
-    case 2: return set_lds_limit_w<2, GS, ADJ, TL>(ctx, lds);
-    case 3: return set_lds_limit_w<3, GS, ADJ, TL>(ctx, lds);
-    case 4: return set_lds_limit_w<4, GS, ADJ, TL>(ctx, lds);
-    case 5: return set_lds_limit_w<5, GS, ADJ, TL>(ctx, lds);
-    case 6: return set_lds_limit_w<6, GS, ADJ, TL>(ctx, lds);
-    case 7: return set_lds_limit_w<7, GS, ADJ, TL>(ctx, lds);
-    case 8: return set_lds_limit_w<8, GS, ADJ, TL>(ctx, lds);
-    default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", W);
+// The step kernel of a class (row words W, layout, waves per unit); the
+// kernels of each W are compiled in their own translation unit.
+const void* step_kernel_ptr(const LaunchGroup& G) {
+    switch (G.W) {
+    case 1: return csek_step_kernel_w1(G.gs, G.adj, G.tl, G.nw);
+    case 2: return csek_step_kernel_w2(G.gs, G.adj, G.tl, G.nw);
+    case 3: return csek_step_kernel_w3(G.gs, G.adj, G.tl, G.nw);
+    case 4: return csek_step_kernel_w4(G.gs, G.adj, G.tl, G.nw);
+    case 5: return csek_step_kernel_w5(G.gs, G.adj, G.tl, G.nw);
+    case 6: return csek_step_kernel_w6(G.gs, G.adj, G.tl, G.nw);
+    case 7: return csek_step_kernel_w7(G.gs, G.adj, G.tl, G.nw);
+    case 8: return csek_step_kernel_w8(G.gs, G.adj, G.tl, G.nw);
+    default: return nullptr;
     }
 }
+int group_layout(const LaunchGroup& G) {
+    return (G.gs ? CSE_LAYOUT_HBM : 0) | (G.adj ? CSE_LAYOUT_RANGE : 0) | (G.tl ? CSE_LAYOUT_LDS_TABLES : 0) |
+           waves_bits(G.nw);
+}
+
+// Dynamic LDS above 64 KB must be allowed per kernel before launches (and
+// before a launch is captured into a graph).
 int set_lds_limit(cse_ctx* ctx, const LaunchGroup& G) {
     if (G.lds <= 65536) return CSE_OK;
-    if (G.gs && G.adj)
-        return G.tl ? set_lds_limit_gs<true, true, true>(ctx, G.W, G.lds)
-                    : set_lds_limit_gs<true, true, false>(ctx, G.W, G.lds);
-    if (G.gs) return set_lds_limit_gs<true, false, false>(ctx, G.W, G.lds);
-    return G.adj ? set_lds_limit_gs<false, true, false>(ctx, G.W, G.lds)
-                 : set_lds_limit_gs<false, false, false>(ctx, G.W, G.lds);
+    const void* k = step_kernel_ptr(G);
+    if (!k) return fail(ctx, CSE_EINVAL, "no step kernel for row words %d, layout %d", G.W, group_layout(G));
+    HIP_TRY(ctx, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds));
+    return CSE_OK;
 }
 
 // Segment table, launch groups and pools of the batch's unfinished jobs:
@@ -754,15 +763,18 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
     B.seg_job.clear();
     B.groups.clear();
     B.pools.clear();
-    // Classes (W, placement, gi form, tables): the kernel is specialised on each.
-    for (int cls = 0; cls < 40; ++cls) {
-        const int W = 1 + cls / 5, k = cls % 5;
+    // Classes (W, placement, gi form, tables, waves per unit): the kernel is
+    // specialised on each.
+    for (int cls = 0; cls < 120; ++cls) {
+        const int W = 1 + cls / 15, k = cls % 15 / 3, nw = 1 << (cls % 3);
         const bool gs = k == 1 || k >= 3, adj = k >= 2, tl = k == 4;
+        if (nw > 1 && !adj) continue;
         LaunchGroup G;
         G.W = W;
         G.gs = gs;
         G.adj = adj;
         G.tl = tl;
+        G.nw = nw;
         G.seg_begin = (int)B.segs.size();
         uint32_t unit = 0;
         for (int jid : B.jobs) {
@@ -771,7 +783,7 @@ int build_segments(cse_ctx* ctx, BatchRec& B) {
             const SchemeRec& sc = ctx->schemes[J.scheme];
             for (int c = 0; c < J.n_comp; ++c) {
                 const DevComp& dc = sc.comp[c];
-                if (dc.W != W || dc.gs != gs || dc.adj != adj || dc.tl != tl) continue;
+                if (dc.W != W || dc.gs != gs || dc.adj != adj || dc.tl != tl || dc.nw != nw) continue;
                 csek::Segment s{};
                 s.C = comp_args(dc, c, J.cfg.count_path == CSE_COUNT_MFMA);
                 s.R = run_args(ctx, J);
@@ -942,32 +954,21 @@ int set_iteration(cse_ctx* ctx, BatchRec& B, uint32_t it) {
     return CSE_OK;
 }
 
-template <int W, bool GS, bool ADJ, bool TL>
-int launch_group_w(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
-                   int* d_err, hipStream_t s) {
+// One group's step-kernel launch: a workgroup of 64 nw lanes per grid unit.
+int launch_group(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
+                 int* d_err, hipStream_t s) {
     if (G.lds > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "unit state needs %zu B of LDS (max %zu)", G.lds, ctx->lds_max);
-    hipLaunchKernelGGL((csek::step_kernel<W, GS, ADJ, TL>), dim3(G.n_grid),
-                       dim3(csek::kWave * csek::UnitWaves<GS, ADJ>::value), G.lds, s,
-                       d_segs + G.seg_begin, G.n_segs, d_order + G.order_begin, G.n_grid, d_err, G.gp ? 1 : 0);
-    HIP_TRY(ctx, hipGetLastError());
+    const void* k = step_kernel_ptr(G);
+    if (!k) return fail(ctx, CSE_EINVAL, "no step kernel for row words %d, layout %d", G.W, group_layout(G));
+    const csek::Segment* segs = d_segs + G.seg_begin;
+    int n_segs = G.n_segs;
+    const uint32_t* order = d_order ? d_order + G.order_begin : nullptr;
+    uint32_t n_grid = G.n_grid;
+    int any_gp = G.gp ? 1 : 0;
+    void* args[] = {(void*)&segs, (void*)&n_segs, (void*)&order, (void*)&n_grid, (void*)&d_err, (void*)&any_gp};
+    HIP_TRY(ctx, hipLaunchKernel(k, dim3(G.n_grid), dim3(csek::kWave * G.nw), args, G.lds, s));
     return CSE_OK;
-}
-
-template <bool GS, bool ADJ, bool TL>
-int launch_group_gs(cse_ctx* ctx, const LaunchGroup& G, const csek::Segment* d_segs, const uint32_t* d_order,
-                    int* d_err, hipStream_t s) {
-    switch (G.W) {
-    case 1: return launch_group_w<1, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 2: return launch_group_w<2, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 3: return launch_group_w<3, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 4: return launch_group_w<4, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 5: return launch_group_w<5, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 6: return launch_group_w<6, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 7: return launch_group_w<7, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    case 8: return launch_group_w<8, GS, ADJ, TL>(ctx, G, d_segs, d_order, d_err, s);
-    default: return fail(ctx, CSE_EINVAL, "row words %d unsupported", G.W);
-    }
 }
 
 // Device time of the timed launches queued since the last call, added to
@@ -977,8 +978,7 @@ int collect_times(cse_ctx* ctx, BatchRec& B) {
         float ms = 0.f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, B.tev[2 * g], B.tev[2 * g + 1]));
         const LaunchGroup& G = B.groups[g];
-        const int layout = (G.gs ? CSE_LAYOUT_HBM : 0) | (G.adj ? CSE_LAYOUT_RANGE : 0) | (G.tl ? CSE_LAYOUT_LDS_TABLES : 0);
-        auto& slot = B.t_class[std::make_pair(G.W, layout)];
+        auto& slot = B.t_class[std::make_pair(G.W, group_layout(G))];
         slot.first += 1;
         slot.second += (uint64_t)((double)ms * 1e6 + 0.5);
     }
@@ -1021,15 +1021,7 @@ int launch_groups(cse_ctx* ctx, BatchRec& B, hipStream_t s, bool timed = false) 
         const LaunchGroup& G = B.groups[gi];
         const hipStream_t gs = gi == 0 ? s : B.side[gi - 1];
         if (timed) HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi], gs));
-        int rc;
-        if (G.gs && G.adj)
-            rc = G.tl ? launch_group_gs<true, true, true>(ctx, G, B.d_segs, B.d_order, B.d_err, gs)
-                      : launch_group_gs<true, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
-        else if (G.gs)
-            rc = launch_group_gs<true, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
-        else
-            rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs)
-                       : launch_group_gs<false, false, false>(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
+        int rc = launch_group(ctx, G, B.d_segs, B.d_order, B.d_err, gs);
         if (rc) return rc;
         if (timed) {
             HIP_TRY(ctx, hipEventRecord(B.tev[2 * gi + 1], gs));
@@ -1477,7 +1469,12 @@ int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, vo
         // Range tables in LDS are not probed: a one-component probe cannot
         // show what their LDS footprint costs when the components of a job
         // share the CUs (on 6x6x6 it would pick them and lose 3%).
-        for (int lay = 0; lay <= (CSE_LAYOUT_HBM | CSE_LAYOUT_RANGE); ++lay) {
+        // Waves per unit (threads per process) are tuned with the range form:
+        // one, two or four.
+        for (int code = 0; code < 12; ++code) {
+            const int base = code & 3, wb = code >> 2;
+            if (wb && !(base & CSE_LAYOUT_RANGE)) continue;
+            const int lay = base | (wb << CSE_LAYOUT_WAVES_SHIFT);
             DevComp probe = dc;
             set_layout(probe, lay);
             if (lds_bytes(probe) > ctx->lds_max) continue;
@@ -2692,6 +2689,7 @@ int32_t cse_reduce_static(cse_ctx* ctx, const int8_t* A, int32_t rows, int32_t c
     G.gs = c.gs;
     G.adj = c.adj;
     G.tl = false;
+    G.nw = c.nw;
     G.gp = cfg->weights[CSE_STRAT_GP] != 0;
     G.n_grid = n;
     G.lds = lds_bytes(c);
@@ -2704,13 +2702,7 @@ int32_t cse_reduce_static(cse_ctx* ctx, const int8_t* A, int32_t rows, int32_t c
     hipLaunchKernelGGL(csek::fill_i32_kernel, dim3(1), dim3(64), 0, s, d_err, 1, 0);
     hipLaunchKernelGGL(csek::init_units_kernel, dim3((n + 255) / 256), dim3(256), 0, s, S, n, 1);
     HIP_TRY(ctx, hipGetLastError());
-    if (G.gs && G.adj)
-        rc = launch_group_gs<true, true, false>(ctx, G, d_seg, nullptr, d_err, s);
-    else if (G.gs)
-        rc = launch_group_gs<true, false, false>(ctx, G, d_seg, nullptr, d_err, s);
-    else
-        rc = G.adj ? launch_group_gs<false, true, false>(ctx, G, d_seg, nullptr, d_err, s)
-                   : launch_group_gs<false, false, false>(ctx, G, d_seg, nullptr, d_err, s);
+    rc = launch_group(ctx, G, d_seg, nullptr, d_err, s);
     if (rc) return rc;
     int herr = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s));

@@ -250,7 +250,7 @@ __host__ __device__ inline size_t newpair_table_bytes(int n_vmax) {
 // After that table they keep a fixed LDS budget for gi's per-step tables
 // (ranges and weight planes), used at every step whose tables fit it; steps
 // whose tables do not fit use the copies in the HBM slot.
-constexpr int kGsTableBudget = 12 * 1024;
+constexpr int kGsTableBudget = 11 * 1024;
 
 // Units with state in HBM slots may keep the per-step tables of the range
 // form of gi (ranges, places in the second ordering, weight bit-planes) in
@@ -1811,12 +1811,14 @@ __device__ __forceinline__ ProcDraw process_draw(const RunArgs& R, uint32_t proc
     return d;
 }
 
+#ifndef CSE_STEP_TU
 // Strategy of every process of a run (the host orders the dispatch of units
 // by expected work with it).
 __global__ void proc_strategy_kernel(RunArgs R, uint32_t n, int32_t* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = process_draw(R, i).strat;
 }
+#endif  // CSE_STEP_TU
 
 __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uint32_t g) {
     int lo = 0, hi = n_segs - 1;
@@ -1838,22 +1840,15 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 // W: row words; GS: bulk state in HBM slots; ADJ: gi over per-variable
 // ranges (large candidate sets) instead of masks; TL (with GS and ADJ): the
 // range tables in LDS; GP: the body of the Greedy-Potential units (every
-// other unit runs in the body without it).  Each (W, GS, ADJ, TL) is its own
-// kernel, so a launch carries only the code its units run and every
-// pointer's memory is known.
-// Waves per unit: units whose state lives in HBM slots and whose gi walks
-// ranges (the large systems) run on kGsWaves waves, the others on one.
-constexpr int kGsWaves = 4;
-template <bool GS, bool ADJ>
-struct UnitWaves {
-    static constexpr int value = (GS && ADJ) ? kGsWaves : 1;
-};
-
-template <int W, bool GS, bool ADJ, bool TL, bool GP>
+// other unit runs in the body without it); NW: waves per unit (one
+// workgroup of 64 NW lanes; more than one only with ADJ).  Each
+// (W, GS, ADJ, TL, NW) is its own kernel, so a launch carries only the code
+// its units run and every pointer's memory is known.
+template <int W, bool GS, bool ADJ, bool TL, bool GP, int NW>
 __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int n_segs,
                                           const uint32_t* __restrict__ order, uint32_t n_grid, int* err) {
     extern __shared__ uint64_t smem[];
-    constexpr int NW = UnitWaves<GS, ADJ>::value;
+    static_assert(NW == 1 || ADJ, "units of several waves walk ranges in gi");
     constexpr int NT = kWave * NW;  // lanes of the unit
     const int l = (int)threadIdx.x;
     if (blockIdx.x >= n_grid) return;
@@ -2070,7 +2065,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
                 // The ranges and planes go to the unit's LDS budget when they
                 // fit it (the range tables of TL units are in LDS anyway).
                 const int pw_m = plane_words(m);
-                if (!TL && 16 * n_live + 8 * K * pw_m <= kGsTableBudget) {
+                if (GS && !TL && 16 * n_live + 8 * K * pw_m <= kGsTableBudget) {
                     int32_t* rng_l = (int32_t*)gtab;
                     uint32_t* pl_l = (uint32_t*)(gtab + 16 * (size_t)n_live);
                     gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng_l, tinv, pl_l, pw_m, K);
@@ -2159,14 +2154,18 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 // the process draw.  gp units (any_gp: some job of the launch weights gp)
 // thus share the launch with the others, while each body is compiled on its
 // own.
-template <int W, bool GS, bool ADJ, bool TL>
-__global__ __launch_bounds__((kWave * UnitWaves<GS, ADJ>::value)) void step_kernel(const Segment* __restrict__ segs, int n_segs,
-                                                     const uint32_t* __restrict__ order, uint32_t n_grid,
-                                                     int* err, int any_gp) {
-    step_body<W, GS, ADJ, TL, false>(segs, n_segs, order, n_grid, err);
-    if (any_gp) step_body<W, GS, ADJ, TL, true>(segs, n_segs, order, n_grid, err);
+// Units of several waves are held to 64 registers (eight waves per SIMD):
+// they wait on memory, and 8 rather than 7 resident waves per SIMD hide more
+// of it (batch pass 2.17 -> 2.10 s).
+template <int W, bool GS, bool ADJ, bool TL, int NW>
+__global__ __launch_bounds__((kWave * NW), (NW > 1 ? 8 : 1)) void step_kernel(
+    const Segment* __restrict__ segs, int n_segs, const uint32_t* __restrict__ order, uint32_t n_grid, int* err,
+    int any_gp) {
+    step_body<W, GS, ADJ, TL, false, NW>(segs, n_segs, order, n_grid, err);
+    if (any_gp) step_body<W, GS, ADJ, TL, true, NW>(segs, n_segs, order, n_grid, err);
 }
 
+#ifndef CSE_STEP_TU
 // Lowest cost over a component's units (out starts at INT_MAX).
 __global__ void best_cost_kernel(const int32_t* cost, uint32_t n, int32_t* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2192,5 +2191,6 @@ __global__ void init_units_kernel(UnitState S, uint32_t n_units, int stamp) {
     S.finish[i] = 0;
     if (S.gs_base) *(int4*)(S.gs_base + (size_t)i * S.gs_stride + S.gs_stride - 16) = make_int4(-1, 0, 0, 0);
 }
+#endif  // CSE_STEP_TU
 
 }  // namespace csek

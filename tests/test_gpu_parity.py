@@ -524,14 +524,16 @@ def run_loaded(gpu, sid, kw):
 @pytest.mark.parametrize("rows,cols,p,cap", [(60, 18, 0.3, 0), (160, 36, 0.15, 40), (42, 197, 0.2, 30)])
 def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
     """Every layout (unit state in LDS or in HBM slots, gi over masks or over
-    ranges) and the autotuner's choice reproduce the oracle's runs."""
+    ranges, one, two or four waves per unit) and the autotuner's choice
+    reproduce the oracle's runs."""
     cse, ctx, torch = gpu
     A = workloads.random_system(rows * 31 + cols, rows, cols, p)
     kw = dict(seed=rows + 5, n_proc=64, weights=dict(ALL_W), proc0_greedy=True, step_cap=cap)
     ref = compare(oracle, [A], kw, "layouts")[0]
     sid = cse.cse_system_load(ctx, A)
     tried = 0
-    for lay in (0, 1, 2, 3, 7):
+    W2, W4 = cse.CSE_LAYOUT_WAVES2, cse.CSE_LAYOUT_WAVES4
+    for lay in (0, 1, 2, 3, 7, 2 | W2, 2 | W4, 3 | W2, 3 | W4, 7 | W2, 7 | W4):
         try:
             cse.cse_scheme_layout(ctx, sid, 0, lay)
         except cse.CseError as e:
@@ -546,7 +548,7 @@ def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
         assert_same(got, ref, f"layout {lay} {rows}x{cols}")
         tried += 1
     assert tried >= 3
-    for bad in (4, 5, 6, 8):
+    for bad in (4, 5, 6, 8, 1 | W4, 24, 2 | 24, 32, -2 & 0xFF):
         with pytest.raises(cse.CseError, match="CSE_EINVAL"):
             cse.cse_scheme_layout(ctx, sid, 0, bad)
     say(f"[gpu] autotune: system {rows}x{cols}")
@@ -626,6 +628,8 @@ def test_randomized_configurations(gpu, oracle):
         lay = int(rng.integers(0, 4))
         if lay == 3 and case % 2:
             lay = 7
+        if lay & cse.CSE_LAYOUT_RANGE:
+            lay |= int(rng.choice([0, cse.CSE_LAYOUT_WAVES2, cse.CSE_LAYOUT_WAVES4]))
         try:
             cse.cse_scheme_layout(ctx, sid, 0, lay)
         except cse.CseError as e:
@@ -688,7 +692,8 @@ def test_driver_with_sharing_rounds_and_layouts(gpu, oracle):
     kw = dict(seed=7, n_proc=64, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True,
               share_every=4, share_src_pm=50, share_dst_pm=300, share_max_rounds=64)
     check_driver(gpu, oracle, S, kw, "4x4x4 sharing", patience=2, max_iterations=5)
-    check_driver(gpu, oracle, S, kw, "4x4x4 sharing hbm+range", layouts=[3, 1, 2], patience=2, max_iterations=5)
+    check_driver(gpu, oracle, S, kw, "4x4x4 sharing hbm+range", layouts=[3 | 16, 1, 2 | 8], patience=2,
+                 max_iterations=5)
 
 
 def test_driver_epochs_past_ten_bits(gpu, oracle):
@@ -808,7 +813,9 @@ def test_hbm_units_resume_across_rounds(gpu, oracle, rows, cols, p, every):
     ref = compare(oracle, [A], kw, "resume")[0]
     assert ref["epoch"].max() > 1
     for lay in (cse.CSE_LAYOUT_HBM, cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE,
-                cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_LDS_TABLES):
+                cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_WAVES4,
+                cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_LDS_TABLES,
+                cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_LDS_TABLES | cse.CSE_LAYOUT_WAVES2):
         sid = cse.cse_system_load(ctx, A)
         cse.cse_scheme_layout(ctx, sid, 0, lay)
         say(f"[gpu] resume: system {rows}x{cols} every {every} layout {lay}")
@@ -957,7 +964,7 @@ def test_greedy_potential_layouts_sharing_driver(gpu, oracle):
                   share_every=3, share_src_pm=150, share_dst_pm=500, share_max_rounds=6)
         ref = compare(oracle, [A], kw, "gp layouts")[0]
         sid = cse.cse_system_load(ctx, A)
-        for lay in (0, 1, 2, 3, 7):
+        for lay in (0, 1, 2, 3, 7, 3 | cse.CSE_LAYOUT_WAVES4, 2 | cse.CSE_LAYOUT_WAVES2):
             try:
                 cse.cse_scheme_layout(ctx, sid, 0, lay)
             except cse.CseError as e:
