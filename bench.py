@@ -51,7 +51,7 @@ def measured_traffic(kernel, workload):
     if fields.get("kernel", "").strip() != kernel:
         return None
     h = hashlib.sha256()
-    for name in ("cse_kernels.hpp", "cse_api.hip"):
+    for name in ("cse_kernels.hpp", "cse_step.hip", "cse_api.hip"):
         with open(os.path.join(ROOT, "paper_2512_13365_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     if fields.get("kernel_sources_sha256_16", "").strip() != h.hexdigest()[:16]:
