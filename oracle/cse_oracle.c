@@ -243,15 +243,15 @@ int oc_select_wr(const oc_cand* C, int m, uint32_t u)
  * Coins: every intersecting q of p = (a, b) gets one fair coin of its own.
  * The intersecting candidates are split by the variable they share with p:
  * A_p = the candidates holding a (p's twin of the other sign included),
- * B_p = those holding b but not a; each list is numbered i = 0, 1, ... in
- * canonical order, and the i-th member of A_p (of B_p) takes bit i mod 128
- * of the Philox block counter (process, COIN|comp|epoch|step, key(p),
- * i div 128 | side | high epoch bits), side = 0 for A_p and 2^15 for B_p,
- * as word (i mod 128) div 32, bit i mod 32.
+ * B_p = those holding b but not a, each in canonical order.  The i-th member
+ * of the sequence A_p then B_p (i = 0 .. |A_p| + |B_p| - 1) takes bit
+ * i mod 128 of the Philox block counter (process, COIN|comp|epoch|step,
+ * key(p), i div 128 | high epoch bits), as word (i mod 128) div 32, bit
+ * i mod 32.
  *
  * n_int and n_blk (optional) receive sum_p (|A_p| + |B_p|) and the Philox
- * blocks drawn, sum_p (ceil(|A_p| / 128) + ceil(|B_p| / 128)), for the
- * algorithmic work tally. */
+ * blocks a candidate's coins span, sum_p ceil((|A_p| + |B_p|) / 128), for
+ * the algorithmic work tally. */
 int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
                  uint64_t seed, uint32_t proc, uint32_t comp, uint32_t epoch, uint32_t step,
                  int64_t* n_int, int64_t* n_blk)
@@ -262,35 +262,42 @@ int oc_select_gi(const oc_cand* C, int m, uint32_t alpha_q, uint32_t beta_q,
     const uint32_t eh = oc_epoch_high(epoch);
     for (int p = 0; p < m; p++) {
         const int pa = key_a(C[p].key), pb = key_b(C[p].key);
+        /* |A_p| first: B_p's coins follow A_p's. */
+        int64_t na = 0;
+        for (int q = 0; q < m; q++)
+            if (q != p && (key_a(C[q].key) == pa || key_b(C[q].key) == pa)) na++;
         int64_t D = 0, X = 0;
         int64_t ia = 0, ib = 0;             /* members of A_p and B_p so far */
+        /* The block of A_p's current coin and of B_p's (-1: none drawn). */
+        int64_t cur_a = -1, cur_b = -1;
         uint32_t blk_a[4] = { 0, 0, 0, 0 }, blk_b[4] = { 0, 0, 0, 0 };
         for (int q = 0; q < m; q++) {
             if (q == p) continue;
             const int64_t wq = C[q].c - 1;
             const int qa = key_a(C[q].key), qb = key_b(C[q].key);
-            int coin;
+            int64_t i;
+            uint32_t* blk;
+            int64_t* cur;
             if (qa == pa || qb == pa) {
-                if (ia % 128 == 0) {
-                    draw(seed, proc, dw, C[p].key, (uint32_t)(ia / 128) | eh, blk_a);
-                    tot_blk++;
-                }
-                coin = (int)((blk_a[(ia % 128) / 32] >> (ia % 32)) & 1u);
-                ia++;
+                i = ia++;
+                blk = blk_a;
+                cur = &cur_a;
             } else if (qa == pb || qb == pb) {
-                if (ib % 128 == 0) {
-                    draw(seed, proc, dw, C[p].key, (uint32_t)(ib / 128) | 0x8000u | eh, blk_b);
-                    tot_blk++;
-                }
-                coin = (int)((blk_b[(ib % 128) / 32] >> (ib % 32)) & 1u);
-                ib++;
+                i = na + ib++;
+                blk = blk_b;
+                cur = &cur_b;
             } else {
                 D += wq;
                 continue;
             }
-            if (coin) X += wq;
+            if (*cur != i / 128) {
+                draw(seed, proc, dw, C[p].key, (uint32_t)(i / 128) | eh, blk);
+                *cur = i / 128;
+            }
+            if ((blk[(i % 128) / 32] >> (i % 32)) & 1u) X += wq;
         }
         tot_int += ia + ib;
+        tot_blk += (ia + ib + 127) / 128;
         int64_t h = ((int64_t)(C[p].c - 1) << 32) + (int64_t)alpha_q * ((D << 16) + (int64_t)beta_q * X);
         if (best < 0 || h > best_h) { best = p; best_h = h; }
     }

@@ -83,7 +83,7 @@ __device__ __forceinline__ uint32_t domain(uint32_t tag, uint32_t comp, uint32_t
 // A unit's epoch may pass the 10 bits of word 1 (restarts from sharing
 // events and outer iterations add up): its higher bits go to the upper half
 // of counter word 3 of the step and coin draws, whose lower half is 0 or a
-// coin stream's block index (< 2^15) and side bit (2^15), so no key is
+// coin stream's block index (< 2^11: at most 4 x 32767 coins), so no key is
 // reused.
 __device__ __forceinline__ uint32_t epoch_high(uint32_t epoch) { return (epoch >> 10) << 16; }
 
@@ -805,10 +805,10 @@ __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const
     return K;
 }
 
-// One coin stream of candidate p: bit j is coin j, taken from Philox block
+// The coin stream of candidate p: bit j is coin j, taken from Philox block
 // (proc, dw, key(p), j div 128 | eh), bit j mod 32 of its word
-// (j mod 128) / 32, eh the stream's side bit and the high epoch bits.  Holds
-// the current block and, once needed, the next.
+// (j mod 128) / 32, eh the high epoch bits.  Holds the current block and,
+// once needed, the next.
 struct CoinStream {
     uint32_t proc, dw, kp, eh, k0, k1;
     int cb;
@@ -897,14 +897,15 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, 
 }
 
 // Greedy-Intersections over per-variable ranges (any number of candidates).
-// The intersecting candidates of p = (a, b), a < b, and their coin streams:
-//   A_p (stream 0): the candidates holding a, in canonical order: the pairs
-//       (x, a), x < a (a's range of the second ordering), then the pairs
-//       (a, y) (a's canonical range, which holds p and its twin; p skipped);
-//   B_p (stream 1): the candidates holding b but not a: the pairs (x, b),
-//       x < b, without (a, b, +-) (b's range of the second ordering, where
-//       those entries sit together at tinv of the first), then the pairs
-//       (b, y) (b's canonical range).
+// The intersecting candidates of p = (a, b), a < b, in coin order:
+//   A_p (coins 0 .. |A_p| - 1): the candidates holding a, in canonical
+//       order: the pairs (x, a), x < a (a's range of the second ordering),
+//       then the pairs (a, y) (a's canonical range, which holds p and its
+//       twin; p skipped);
+//   B_p (the next |B_p| coins): the candidates holding b but not a: the
+//       pairs (x, b), x < b, without (a, b, +-) (b's range of the second
+//       ordering, where those entries sit together at tinv of the first),
+//       then the pairs (b, y) (b's canonical range).
 // Every part is a contiguous range whose members take consecutive coins, so
 // lane p sums them 32 candidates at a time through the weight bit-planes.
 __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
@@ -932,22 +933,23 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             const int q_lo = tprev ? p - 1 : p;
             const int n_ab = (tprev || tnext) ? 2 : 1;
             const int t_ab = tinv[q_lo];
-            int I = 0, X = 0, ja = 0, jb = 0;
+            int I = 0, X = 0, j = 0;
             CoinStream co;
             co.init(proc, dw, kp, eh, k0, k1);
-            plane_window(plt, pw, K, ra.z, ra.w, ja, co, I, X);
-            plane_window(plc, pw, K, ra.x, p, ja, co, I, X);
-            plane_window(plc, pw, K, p + 1, ra.y, ja, co, I, X);
-            co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
-            plane_window(plt, pw, K, rb.z, t_ab, jb, co, I, X);
-            plane_window(plt, pw, K, t_ab + n_ab, rb.w, jb, co, I, X);
-            plane_window(plc, pw, K, rb.x, rb.y, jb, co, I, X);
+            co.first_block();
+            if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
+            plane_window(plt, pw, K, ra.z, ra.w, j, co, I, X);
+            plane_window(plc, pw, K, ra.x, p, j, co, I, X);
+            plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
+            plane_window(plt, pw, K, rb.z, t_ab, j, co, I, X);
+            plane_window(plt, pw, K, t_ab + n_ab, rb.w, j, co, I, X);
+            plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
             if (hsc > best_h) { best_h = hsc; best_p = p; }
-            my_int += ja + jb;
-            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
+            my_int += j;
+            my_blk += (j + 127) >> 7;
         }
     }
     *n_int = wave_sum(my_int);
@@ -959,12 +961,12 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
 //   2^32 H = (c_p - 1) 2^32 + alpha_q (D_p 2^16 + beta_q X_p)
 // with D_p the profit of the disjoint candidates and X_p that of the
 // intersecting candidates whose coin is 1.  The intersecting candidates of
-// p = (a, b) form two lists in canonical order, those holding a (p's twin
-// included) and those holding b but not a; the i-th member of a list uses
-// bit i mod 128 of Philox block (proc, COIN|comp|epoch|step, key(p),
-// i div 128 | side | eh), side 0 or 2^15 for the list, eh the high epoch
-// bits.  This form visits every q (the O(m^2) scan); it serves when the
-// masks of the sparse form do not fit.
+// p = (a, b) form two lists in canonical order, A_p holding a (p's twin
+// included) and B_p holding b but not a; the i-th member of A_p then B_p
+// (i = 0 .. |A_p| + |B_p| - 1) uses bit i mod 128 of Philox block
+// (proc, COIN|comp|epoch|step, key(p), i div 128 | eh), eh the high epoch
+// bits.  This form visits every q (the O(m^2) scan, after a count of A_p);
+// it serves when the masks of the sparse form do not fit.
 __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_t bq, uint32_t k0, uint32_t k1,
                                uint32_t proc, uint32_t dw, uint32_t eh, long long* n_int, long long* n_blk) {
     const int l = lane_id();
@@ -977,7 +979,14 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
         const uint64_t ep = valid ? cand[p] : 0ull;
         const uint32_t kp = (uint32_t)ep;
         const int ap = key_a(kp), bp = key_b(kp);
+        // |A_p| first: B_p's coins follow A_p's in the one stream.
+        int na = 0;
+        for (int q = 0; q < m; ++q) {
+            const uint32_t kq = (uint32_t)cand[q];
+            na += q != p && (key_a(kq) == ap || key_b(kq) == ap);
+        }
         U4 ba = {0u, 0u, 0u, 0u}, bb = {0u, 0u, 0u, 0u};
+        int cur_a = -1, cur_b = -1;  // blocks held for A_p's and B_p's coins
         int D = 0, X = 0, ja = 0, jb = 0;
         for (int q = 0; q < m; ++q) {
             const uint64_t eq = cand[q];
@@ -992,12 +1001,18 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
                 int j;
                 U4 blk;
                 if (sa) {
-                    if ((ja & 127) == 0) ba = philox10(proc, dw, kp, (uint32_t)(ja >> 7) | eh, k0, k1);
                     j = ja++;
+                    if ((j >> 7) != cur_a) {
+                        ba = philox10(proc, dw, kp, (uint32_t)(j >> 7) | eh, k0, k1);
+                        cur_a = j >> 7;
+                    }
                     blk = ba;
                 } else {
-                    if ((jb & 127) == 0) bb = philox10(proc, dw, kp, (uint32_t)(jb >> 7) | 0x8000u | eh, k0, k1);
-                    j = jb++;
+                    j = na + jb++;
+                    if ((j >> 7) != cur_b) {
+                        bb = philox10(proc, dw, kp, (uint32_t)(j >> 7) | eh, k0, k1);
+                        cur_b = j >> 7;
+                    }
                     blk = bb;
                 }
                 const int r = j & 127;
@@ -1010,7 +1025,7 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
             const long long h = (wp << 32) + (long long)aq * (((long long)D << 16) + (long long)bq * X);
             if (h > best_h) { best_h = h; best_p = p; }
             my_int += ja + jb;
-            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
+            my_blk += (ja + jb + 127) >> 7;
         }
     }
     *n_int = wave_sum64(my_int);
@@ -1021,9 +1036,10 @@ __device__ int select_gi_dense(const uint64_t* cand, int m, uint32_t aq, uint32_
 // Greedy-Intersections, sparse form: M[v] marks (bit i of 32-bit word w)
 // the candidates 32 w + i that contain the live variable at position v.
 // Lane p walks the set bits of M[a] (minus p itself), then those of
-// M[b] & ~M[a], in increasing index: the two coin lists of the other forms
-// (candidates holding a, twin included; those holding b only), each taking
-// its own stream, the members of a word the next 32-coin window.
+// M[b] & ~M[a], in increasing index: the two lists of the other forms
+// (candidates holding a, twin included; those holding b only), A_p's
+// members taking coins 0 .. |A_p| - 1 and B_p's the next ones, the members
+// of a word the next window of coins.
 // D_p = T - (c_p - 1) - I_p with I_p the profit of all intersecting
 // candidates.  wt[q] = c_q - 1 is filled on the way.
 __device__ __forceinline__ void mask_walk(const uint32_t* Ma, const uint32_t* Mb, int nw, int self_w,
@@ -1085,18 +1101,19 @@ __device__ int select_gi_sparse(const uint64_t* cand, int m, const int32_t* vpos
             const uint32_t* Mb = M + vpos[key_b(kp) - 1] * nw;
             const int self_w = p >> 5;
             const uint32_t self_bit = 1u << (p & 31);
-            int I = 0, X = 0, ja = 0, jb = 0;
+            // One coin stream: A_p's members take coins 0 .. |A_p| - 1, B_p's the next ones.
+            int I = 0, X = 0, j = 0;
             CoinStream co;
             co.init(proc, dw, kp, eh, k0, k1);
-            mask_walk(Ma, nullptr, nw, self_w, self_bit, wt, co, I, X, ja);
-            co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
-            mask_walk(Ma, Mb, nw, self_w, self_bit, wt, co, I, X, jb);
+            co.first_block();
+            mask_walk(Ma, nullptr, nw, self_w, self_bit, wt, co, I, X, j);
+            mask_walk(Ma, Mb, nw, self_w, self_bit, wt, co, I, X, j);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
             if (hsc > best_h) { best_h = hsc; best_p = p; }
-            my_int += ja + jb;
-            my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
+            my_int += j;
+            my_blk += (j + 127) >> 7;
         }
     }
     *n_int = wave_sum(my_int);
@@ -1643,24 +1660,26 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m,
         const int q_lo = tprev ? p - 1 : p;
         const int n_ab = (tprev || tnext) ? 2 : 1;
         const int t_ab = tinv[q_lo];
-        int I = 0, X = 0, ja = 0, jb = 0;
+        int I = 0, X = 0, j = 0;
         CoinStream co;
         co.init(proc, dw, kp, eh, k0, k1);
+        // The blocks of the first 256 coins are drawn by all lanes at once
+        // (lazily, lanes reaching a block at different points would each
+        // draw it in their own pass of the loop).
         co.first_block();
-        plane_window(plt, pw, K, ra.z, ra.w, ja, co, I, X);
-        plane_window(plc, pw, K, ra.x, p, ja, co, I, X);
-        plane_window(plc, pw, K, p + 1, ra.y, ja, co, I, X);
-        co.init(proc, dw, kp, eh | 0x8000u, k0, k1);
-        co.first_block();
-        plane_window(plt, pw, K, rb.z, t_ab, jb, co, I, X);
-        plane_window(plt, pw, K, t_ab + n_ab, rb.w, jb, co, I, X);
-        plane_window(plc, pw, K, rb.x, rb.y, jb, co, I, X);
+        if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
+        plane_window(plt, pw, K, ra.z, ra.w, j, co, I, X);
+        plane_window(plc, pw, K, ra.x, p, j, co, I, X);
+        plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
+        plane_window(plt, pw, K, rb.z, t_ab, j, co, I, X);
+        plane_window(plt, pw, K, t_ab + n_ab, rb.w, j, co, I, X);
+        plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
         const long long wp = (long long)entry_c(ep) - 1;
         const long long D = (long long)T - wp - I;
         const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
         if (hsc > best_h) { best_h = hsc; best_p = p; }
-        my_int += ja + jb;
-        my_blk += ((ja + 127) >> 7) + ((jb + 127) >> 7);
+        my_int += j;
+        my_blk += (j + 127) >> 7;
     }
     *n_int = grp_sum<NW>(my_int);
     *n_blk = grp_sum<NW>(my_blk);

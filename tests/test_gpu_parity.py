@@ -679,7 +679,7 @@ def test_driver_converges_like_oracle(gpu, oracle):
     """Outer iterations (Sec. 3.5.1-3.5.2, Sec. 4 rule): improvements after
     the first iteration, restarts from best prefixes, the same stop."""
     S = [workloads.random_system(61 + i, 49, 16, 0.3, 1, 8) for i in range(3)]
-    kw = dict(seed=3, n_proc=16, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True)
+    kw = dict(seed=9, n_proc=16, weights={"gi": 8, "ga": 4, "gr": 2, "wr": 1, "mix": 1}, proc0_greedy=True)
     got = check_driver(gpu, oracle, S, kw, "49x16 x3", patience=3, max_iterations=40)
     assert got["iterations"] > 4 and got["totals"][-1] < got["totals"][0]
 

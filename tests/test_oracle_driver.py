@@ -22,7 +22,8 @@ def test_driver_convergence_rule(oracle):
     processes on 49 x 16 systems keep improving after the first iteration."""
     S = [random_system(61 + i, 49, 16, 0.3, 1, 8) for i in range(3)]
     patience, cap = 3, 40
-    d = oracle.run_driver(S, oracle.make_cfg(**dict(KW, n_proc=16)), patience=patience, max_iterations=cap)
+    # seed 9: a run whose best total still falls at iteration 6
+    d = oracle.run_driver(S, oracle.make_cfg(**dict(KW, n_proc=16, seed=9)), patience=patience, max_iterations=cap)
     t = d["totals"]
     assert len(t) == d["iterations"] < cap
     assert all(b <= a for a, b in zip(t, t[1:]))

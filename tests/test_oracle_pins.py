@@ -224,10 +224,12 @@ def test_gi_score_against_float_formula(oracle):
         dw = oracle.domain_word(3, 1, 2, step)
         H = []
         for p, (pa, pb, ps, pc) in enumerate(cands):
-            # coins: the i-th candidate holding pa (twin included), and the
-            # i-th holding pb but not pa, in canonical order, each list with
-            # its own Philox stream (counter word 3: i div 128, + 2^15 for pb)
-            idx = {pa: 0, pb: 0}
+            # coins: the candidates holding pa (twin included), then those
+            # holding pb but not pa, each list in canonical order, numbered
+            # i = 0, 1, ... across both; coin i is bit i mod 128 of the Philox
+            # block with counter word 3 = i div 128
+            n_a = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and pa in (qa, qb))
+            idx = {pa: 0, pb: n_a}
             tot = 0.0
             for q, (qa, qb, qs, qc) in enumerate(cands):
                 if q == p:
@@ -239,7 +241,7 @@ def test_gi_score_against_float_formula(oracle):
                 i = idx[shared]
                 idx[shared] += 1
                 key = (pa << 16) | (pb << 1) | (ps < 0)
-                c3 = i // 128 + (0x8000 if shared == pb else 0)
+                c3 = i // 128
                 blk = oracle.philox4x32_10((proc, dw, key, c3), (seed & 0xFFFFFFFF, seed >> 32))
                 coin = (blk[(i % 128) // 32] >> (i % 32)) & 1
                 tot += (bq / 65536.0) * (qc - 1) if coin else 0.0
@@ -367,9 +369,9 @@ def test_gr_exploit_rate(oracle):
 
 def test_gi_work_tally_independent_count(oracle):
     """The gi work tally (n_int = sum over p of the candidates intersecting p;
-    n_blk = the coin blocks, ceil(|A_p| / 128) + ceil(|B_p| / 128) per p with
-    A_p the candidates holding p's first variable and B_p those holding only
-    its second) against a count written here from the intersection rule
+    n_blk = the coin blocks, ceil((|A_p| + |B_p|) / 128) per p with A_p the
+    candidates holding p's first variable and B_p those holding only its
+    second, whose coins follow A_p's) against a count written here from the intersection rule
     (shared variable index, p itself excluded), on candidate sets large
     enough that some lists exceed 128."""
     rng = np.random.default_rng(15)
@@ -391,7 +393,7 @@ def test_gi_work_tally_independent_count(oracle):
             ka = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and pa in (qa, qb))
             kb = sum(1 for q, (qa, qb, _, _) in enumerate(cands) if q != p and pa not in (qa, qb) and pb in (qa, qb))
             n_int += ka + kb
-            n_blk += -(-ka // 128) - (-kb // 128)
+            n_blk += -(-(ka + kb) // 128)
             big += max(ka, kb) > 128
         _, got_int, got_blk = oracle.select_gi(cands, int(rng.integers(0, 32768)), 40000, seed=trial)
         assert (got_int, got_blk) == (n_int, n_blk)
