@@ -155,7 +155,8 @@ int32_t cse_scheme_free(cse_ctx* ctx, int32_t scheme_id);
  * state would leave room in a CU's 160 KB of LDS for fewer than four units
  * (those run on four waves).  Valid layouts: 0..3 and HBM | RANGE |
  * LDS_TABLES, each range layout with or without CSE_LAYOUT_WAVES2 or
- * CSE_LAYOUT_WAVES4; CSE_EINVAL otherwise.  CSE_EBUSY while a job of the
+ * CSE_LAYOUT_WAVES4 (several waves only for systems of at most 2047
+ * variables, n_x + floor((nnz - rows) / 2)); CSE_EINVAL otherwise.  CSE_EBUSY while a job of the
  * scheme exists; CSE_ENOMEM if the unit's LDS share does not fit a
  * workgroup.  Unit results are the same in every layout. */
 int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t layout, int32_t* current);

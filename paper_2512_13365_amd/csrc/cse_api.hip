@@ -248,7 +248,10 @@ int fail(cse_ctx* ctx, int code, const char* fmt, ...) {
     } while (0)
 
 size_t bulk_bytes(const DevComp& c) {
-    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0, c.kbits).bytes;
+    // Units of several waves keep 32-bit candidate entries.
+    return csek::bulk_layout(c.n_x + c.n_fmax, c.W, c.m_cap, c.newc_cap, c.m_words, c.adj ? 1 : 0, c.kbits,
+                             c.nw > 1 ? 4 : 8)
+        .bytes;
 }
 size_t lds_bytes(const DevComp& c) {
     const int n_vmax = c.n_x + c.n_fmax;
@@ -412,8 +415,9 @@ int pick_layout(cse_ctx* ctx, DevComp& c) {
     // Too large for four units per CU: state in HBM, and gi over ranges, which
     // touches far less of that state per step than building masks does.
     if (kMinUnitsPerCu * (bulk_bytes(c) + csek::list_bytes(n_vmax)) > kLdsPerCu) c.gs = c.adj = true;
-    // Those units wait on memory; they run on several waves.
-    c.nw = c.gs && c.adj ? kDefaultHbmRangeWaves : 1;
+    // Those units wait on memory; they run on several waves (whose 32-bit
+    // candidate entries hold variable ids below 2048).
+    c.nw = c.gs && c.adj && n_vmax <= csek::kCompactMaxVars ? kDefaultHbmRangeWaves : 1;
     // Every layout keeps the variable lists in LDS.
     if (lds_bytes(c) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "%d variables need %zu B of LDS for their lists (max %zu)", n_vmax,
@@ -1438,6 +1442,9 @@ int32_t cse_scheme_layout(cse_ctx* ctx, int32_t scheme_id, int32_t comp, int32_t
     if (scheme_busy(ctx, scheme_id)) return fail(ctx, CSE_EBUSY, "scheme %d has jobs; release them first", scheme_id);
     DevComp probe = dc;
     set_layout(probe, layout);
+    if (probe.nw > 1 && dc.n_x + dc.n_fmax > csek::kCompactMaxVars)
+        return fail(ctx, CSE_EINVAL, "layout %d: several waves per unit need at most %d variables (%d)", layout,
+                    csek::kCompactMaxVars, dc.n_x + dc.n_fmax);
     if (lds_bytes(probe) > ctx->lds_max)
         return fail(ctx, CSE_ENOMEM, "layout %d needs %zu B of LDS per unit (max %zu)", layout, lds_bytes(probe),
                     ctx->lds_max);
@@ -1478,6 +1485,7 @@ int32_t cse_autotune(cse_ctx* ctx, int32_t scheme_id, const cse_run_cfg* cfg, vo
             DevComp probe = dc;
             set_layout(probe, lay);
             if (lds_bytes(probe) > ctx->lds_max) continue;
+            if (probe.nw > 1 && dc.n_x + dc.n_fmax > csek::kCompactMaxVars) continue;
             if (!probe.adj && !masks_fit) continue;
             float ms = 0.f;
             rc = probe_layout(ctx, probe, pc, (hipStream_t)stream, best_ms, &ms);

@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 // Wavefront reductions and scans of the ROCm device library (DPP based).
 extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
 extern "C" __device__ __attribute__((const)) long long __ockl_wfred_add_i64(long long);
@@ -205,13 +207,14 @@ __host__ __device__ inline int weight_bits(int n_e) {
     while (k < 31 && (1 << k) <= n_e - 1) ++k;
     return k;
 }
+// esz: bytes per candidate entry (8, or 4 for units of several waves).
 __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, int newc_cap, int m_words,
-                                                  int adj, int kbits) {
+                                                  int adj, int kbits, int esz = 8) {
     BulkLayout L;
     size_t o = 0;
     L.colP = o;  o += (size_t)n_vmax * W * 8;
     L.colN = o;  o += (size_t)n_vmax * W * 8;
-    L.cand = o;  o += (size_t)m_cap * 8;
+    L.cand = o;  o += (((size_t)m_cap * esz + 7) & ~size_t(7));
     if (!adj) {
         // The fresh-variable pairs (update) and the gi masks and weights
         // (selection) are never live at the same time: one region.
@@ -226,7 +229,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
         return L;
     }
     L.M = L.wt = o;
-    L.cand2 = o; o += (size_t)m_cap * 8;
+    L.cand2 = o; o += (((size_t)m_cap * esz + 7) & ~size_t(7));
     L.newc = o;  o += (size_t)newc_cap * 8;
     L.tl = o;    o += (size_t)m_cap * 4;
     L.remap = o; o += (size_t)m_cap * 4;
@@ -1189,6 +1192,28 @@ __device__ int select_gp(const uint64_t* cand, int m, const uint64_t* colP, cons
 // same in every wave, so the waves take the same branches and barriers.
 // The single-wave kernels keep the functions above.
 // ---------------------------------------------------------------------------
+// Candidates of units of several waves are 32-bit entries: first variable
+// (11 bits), second variable (11), sign (1) and c - 1 (9), so the canonical
+// order is the order of the entries' upper 23 bits.  Their systems have at
+// most 2047 variables (c <= 512 rows always fits).
+constexpr int kCompactMaxVars = 2047;
+__device__ __forceinline__ uint32_t ce_make(int a, int b, int neg, int c) {
+    return (uint32_t)a << 21 | (uint32_t)b << 10 | (uint32_t)neg << 9 | (uint32_t)(c - 1);
+}
+__device__ __forceinline__ int ce_a(uint32_t e) { return (int)(e >> 21); }
+__device__ __forceinline__ int ce_b(uint32_t e) { return (int)((e >> 10) & 0x7FFu); }
+__device__ __forceinline__ int ce_neg(uint32_t e) { return (int)((e >> 9) & 1u); }
+__device__ __forceinline__ int ce_w(uint32_t e) { return (int)(e & 0x1FFu); }  // c - 1
+__device__ __forceinline__ int ce_c(uint32_t e) { return ce_w(e) + 1; }
+__device__ __forceinline__ uint32_t ce_pair(uint32_t e) { return e >> 10; }   // (a, b) without the sign
+__device__ __forceinline__ uint32_t ce_order(uint32_t e) { return e >> 9; }   // a << 12 | b << 1 | sign
+// The canonical 32-bit key (programs, random draws).
+__device__ __forceinline__ uint32_t ce_key(uint32_t e) { return pair_key(ce_a(e), ce_b(e), ce_neg(e)); }
+__device__ __forceinline__ uint32_t ce_from64(uint64_t e) {
+    const uint32_t k = (uint32_t)e;
+    return ce_make(key_a(k), key_b(k), (int)(k & 1u), entry_c(e));
+}
+
 __device__ __forceinline__ int grp_tid() { return (int)threadIdx.x; }
 __device__ __forceinline__ int grp_lane() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int grp_wave() { return (int)(threadIdx.x >> 6); }
@@ -1369,7 +1394,7 @@ __device__ __forceinline__ int build_live_grp(const uint64_t* colP, const uint64
 
 template <int W, int NW>
 __device__ int analyse_full_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
-                                uint64_t* cand, int m_cap, int* err_flags) {
+                                uint32_t* cand, int m_cap, int* err_flags) {
     const int t = grp_tid();
     int m = 0;
     for (int i = 0; i + 1 < n_live; ++i) {
@@ -1385,12 +1410,12 @@ __device__ int analyse_full_grp(const uint64_t* colP, const uint64_t* colN, cons
             const int off = grp_offset<NW>(popc64(bp) + popc64(bm), &tot);
             const int pos = m + off + lanes_below(bp) + lanes_below(bm);
             if (hp) {
-                if (pos < m_cap) cand[pos] = pair_key(a, b, 0) | ((uint64_t)c.x << 32);
+                if (pos < m_cap) cand[pos] = ce_make(a, b, 0, c.x);
                 else *err_flags |= ERR_CAND_OVERFLOW;
             }
             if (hm) {
                 const int q = pos + (hp ? 1 : 0);
-                if (q < m_cap) cand[q] = pair_key(a, b, 1) | ((uint64_t)c.y << 32);
+                if (q < m_cap) cand[q] = ce_make(a, b, 1, c.y);
                 else *err_flags |= ERR_CAND_OVERFLOW;
             }
             m += tot;
@@ -1402,7 +1427,7 @@ __device__ int analyse_full_grp(const uint64_t* colP, const uint64_t* colN, cons
 
 template <int W, int NW>
 __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
-                                        const uint64_t* src, int m, uint64_t* dst, uint64_t* newc, int newc_cap,
+                                        const uint32_t* src, int m, uint32_t* dst, uint64_t* newc, int newc_cap,
                                         int m_cap, int32_t* remap, int32_t* kpre, const int32_t* vpos,
                                         uint64_t* npm, int32_t* npb, int a, int b, int k, int* n_new_out,
                                         int* err_flags) {
@@ -1443,14 +1468,13 @@ __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* co
     for (int base = 0; base < m; base += kWave * NW) {
         const int i = base + t;
         const bool valid = i < m;
-        uint64_t e = valid ? src[i] : 0ull;
-        const uint32_t key = (uint32_t)e;
-        const int qa = key_a(key), qb = key_b(key);
-        int c = entry_c(e);
+        uint32_t e = valid ? src[i] : 0u;
+        const int qa = ce_a(e), qb = ce_b(e);
+        int c = valid ? ce_c(e) : 0;
         if (valid && (qa == a || qa == b || qb == a || qb == b)) {
             const int2 cc = pair_counts<W>(colP, colN, qa - 1, qb - 1);
-            c = (key & 1u) ? cc.y : cc.x;
-            e = (uint64_t)key | ((uint64_t)c << 32);
+            c = ce_neg(e) ? cc.y : cc.x;
+            if (c >= 2) e = ce_make(qa, qb, ce_neg(e), c);
         }
         const bool keep = valid && c >= 2;
         const uint64_t bk = ballot(keep);
@@ -1488,10 +1512,10 @@ __device__ int update_candidates_db_grp(const uint64_t* colP, const uint64_t* co
             int lo = 0, hi = m;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (key_a((uint32_t)src[mid]) <= x) lo = mid + 1; else hi = mid;
+                if (ce_a(src[mid]) <= x) lo = mid + 1; else hi = mid;
             }
             const int dest = e + kpre[lo];
-            dst[dest] = v;
+            dst[dest] = ce_from64(v);
             newc[e] = v | ((uint64_t)dest << 42);
         }
     }
@@ -1524,7 +1548,7 @@ __device__ void update_tl_grp(uint32_t* tl, int m_old, const int32_t* remap, con
 
 template <int W, int NW>
 __device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
-                             const uint64_t* cand, int m, uint32_t* tl) {
+                             const uint32_t* cand, int m, uint32_t* tl) {
     const int t = grp_tid();
     int mt = 0;
     for (int j = 1; j < n_live; ++j) {
@@ -1542,11 +1566,11 @@ __device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const u
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const bool has = sgn ? hm : hp;
                 if (!has) continue;
-                const uint32_t key = pair_key(a, b, sgn);
+                const uint32_t key = (uint32_t)a << 12 | (uint32_t)b << 1 | (uint32_t)sgn;
                 int lo = 0, hi = m;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if ((uint32_t)cand[mid] < key) lo = mid + 1; else hi = mid;
+                    if (ce_order(cand[mid]) < key) lo = mid + 1; else hi = mid;
                 }
                 const int q = pos + (sgn && hp ? 1 : 0);
                 if (q < m) tl[q] = (uint32_t)lo;
@@ -1560,10 +1584,10 @@ __device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const u
 // Total profit T = sum (c - 1) over the candidates and the number K of
 // weight bit-planes (bit length of the largest c - 1, at most kbits).
 template <int NW>
-__device__ __forceinline__ void gi_totals_grp(const uint64_t* cand, int m, int kbits, int* T, int* K) {
+__device__ __forceinline__ void gi_totals_grp(const uint32_t* cand, int m, int kbits, int* T, int* K) {
     int tot = 0, wmax = 0;
     for (int q = grp_tid(); q < m; q += kWave * NW) {
-        const int w = entry_c(cand[q]) - 1;
+        const int w = ce_w(cand[q]);
         tot += w;
         wmax = w > wmax ? w : wmax;
     }
@@ -1577,7 +1601,7 @@ __device__ __forceinline__ void gi_totals_grp(const uint64_t* cand, int m, int k
 // As gi_prepare, with the K planes of each ordering (the canonical
 // ordering's at pl, the second ordering's at pl + K pw).
 template <int NW>
-__device__ __forceinline__ void gi_prepare_grp(const uint64_t* cand, const uint32_t* tl, int m,
+__device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint32_t* tl, int m,
                                                const int32_t* vpos, int n_live, int32_t* rng, int32_t* tinv,
                                                uint32_t* pl, int pw, int K) {
     const int l = grp_lane();
@@ -1588,21 +1612,21 @@ __device__ __forceinline__ void gi_prepare_grp(const uint64_t* cand, const uint3
         if (cb >= m) continue;
         const int i = cb + l;
         const bool valid = i < m;
-        const uint64_t e = valid ? cand[i] : 0ull;
+        const uint32_t e = valid ? cand[i] : 0u;
         const uint32_t q = valid ? tl[i] : 0u;
-        const uint64_t eq = valid ? cand[q] : 0ull;
-        const int w = valid ? entry_c(e) - 1 : 0;
-        const int wq = valid ? entry_c(eq) - 1 : 0;
-        const int a = key_a((uint32_t)e), b = key_b((uint32_t)eq);
+        const uint32_t eq = valid ? cand[q] : 0u;
+        const int w = valid ? ce_w(e) : 0;
+        const int wq = valid ? ce_w(eq) : 0;
+        const int a = ce_a(e), b = ce_b(eq);
         int pa = __shfl_up(a, 1), na = __shfl_down(a, 1);
         int pb = __shfl_up(b, 1), nb = __shfl_down(b, 1);
         if (l == 0) {
-            pa = i > 0 && valid ? key_a((uint32_t)cand[i - 1]) : -1;
-            pb = i > 0 && valid ? key_b((uint32_t)cand[tl[i - 1]]) : -1;
+            pa = i > 0 && valid ? ce_a(cand[i - 1]) : -1;
+            pb = i > 0 && valid ? ce_b(cand[tl[i - 1]]) : -1;
         }
         if (l == kWave - 1 || i + 1 >= m) {
-            na = i + 1 < m ? key_a((uint32_t)cand[i + 1]) : -1;
-            nb = i + 1 < m ? key_b((uint32_t)cand[tl[i + 1]]) : -1;
+            na = i + 1 < m ? ce_a(cand[i + 1]) : -1;
+            nb = i + 1 < m ? ce_b(cand[tl[i + 1]]) : -1;
         }
         if (valid) {
             const int va = vpos[a - 1], vb = vpos[b - 1];
@@ -1625,9 +1649,9 @@ __device__ __forceinline__ void gi_prepare_grp(const uint64_t* cand, const uint3
 }
 
 template <int NW>
-__device__ __forceinline__ int total_profit_grp(const uint64_t* cand, int m) {
+__device__ __forceinline__ int total_profit_grp(const uint32_t* cand, int m) {
     int tot = 0;
-    for (int q = grp_tid(); q < m; q += kWave * NW) tot += entry_c(cand[q]) - 1;
+    for (int q = grp_tid(); q < m; q += kWave * NW) tot += ce_w(cand[q]);
     return grp_sum<NW>(tot);
 }
 
@@ -1639,7 +1663,7 @@ __device__ __forceinline__ int gi_argmax_grp(long long best_h, int best_p) {
 
 // As select_gi_planes over the tables of gi_prepare_grp.
 template <int NW>
-__device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m, int T, const int32_t* vpos,
+__device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m, int T, const int32_t* vpos,
                                                     const int32_t* rng, const int32_t* tinv, const uint32_t* pl,
                                                     int pw, int K, uint32_t aq, uint32_t bq, uint32_t k0,
                                                     uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
@@ -1650,13 +1674,13 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m,
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
     for (int p = grp_tid(); p < m; p += kWave * NW) {
-        const uint64_t ep = cand[p];
-        const uint32_t kp = (uint32_t)ep;
-        const int va = vpos[key_a(kp) - 1], vb = vpos[key_b(kp) - 1];
+        const uint32_t ep = cand[p];
+        const uint32_t kp = ce_key(ep);
+        const int va = vpos[ce_a(ep) - 1], vb = vpos[ce_b(ep) - 1];
         const int4 ra = *(const int4*)(rng + 4 * va);
         const int4 rb = *(const int4*)(rng + 4 * vb);
-        const bool tprev = p > 0 && ((uint32_t)cand[p - 1] >> 1) == (kp >> 1);
-        const bool tnext = p + 1 < m && ((uint32_t)cand[p + 1] >> 1) == (kp >> 1);
+        const bool tprev = p > 0 && ce_pair(cand[p - 1]) == ce_pair(ep);
+        const bool tnext = p + 1 < m && ce_pair(cand[p + 1]) == ce_pair(ep);
         const int q_lo = tprev ? p - 1 : p;
         const int n_ab = (tprev || tnext) ? 2 : 1;
         const int t_ab = tinv[q_lo];
@@ -1674,7 +1698,7 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m,
         plane_window(plt, pw, K, rb.z, t_ab, j, co, I, X);
         plane_window(plt, pw, K, t_ab + n_ab, rb.w, j, co, I, X);
         plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
-        const long long wp = (long long)entry_c(ep) - 1;
+        const long long wp = (long long)ce_w(ep);
         const long long D = (long long)T - wp - I;
         const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
         if (hsc > best_h) { best_h = hsc; best_p = p; }
@@ -1687,10 +1711,10 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint64_t* cand, int m,
 }
 
 template <int NW>
-__device__ __forceinline__ int select_g_grp(const uint64_t* cand, int m) {
+__device__ __forceinline__ int select_g_grp(const uint32_t* cand, int m) {
     unsigned long long best = 0;
     for (int q = grp_tid(); q < m; q += kWave * NW) {
-        const unsigned long long key = ((unsigned long long)entry_c(cand[q]) << 32) | (0xFFFFFFFFull - (unsigned)q);
+        const unsigned long long key = ((unsigned long long)ce_c(cand[q]) << 32) | (0xFFFFFFFFull - (unsigned)q);
         best = key > best ? key : best;
     }
     best = grp_max_u64<NW>(best);
@@ -1698,21 +1722,21 @@ __device__ __forceinline__ int select_g_grp(const uint64_t* cand, int m) {
 }
 
 template <int NW>
-__device__ __forceinline__ int select_ga_grp(const uint64_t* cand, int m, uint32_t u) {
+__device__ __forceinline__ int select_ga_grp(const uint32_t* cand, int m, uint32_t u) {
     const int t = grp_tid();
     int cmax = 0;
     for (int q = t; q < m; q += kWave * NW) {
-        const int c = entry_c(cand[q]);
+        const int c = ce_c(cand[q]);
         cmax = c > cmax ? c : cmax;
     }
     cmax = grp_max<NW>(cmax);
     int mine = 0;
-    for (int q = t; q < m; q += kWave * NW) mine += entry_c(cand[q]) == cmax;
+    for (int q = t; q < m; q += kWave * NW) mine += ce_c(cand[q]) == cmax;
     const int ties = grp_sum<NW>(mine);
     uint32_t want = scale_u32(u, (uint32_t)ties);
     for (int base = 0; base < m; base += kWave * NW) {
         const int q = base + t;
-        const bool tie = q < m && entry_c(cand[q]) == cmax;
+        const bool tie = q < m && ce_c(cand[q]) == cmax;
         const uint64_t bt = ballot(tie);
         const int cnt = popc64(bt);
         int tot;
@@ -1732,14 +1756,14 @@ __device__ __forceinline__ int select_ga_grp(const uint64_t* cand, int m, uint32
 }
 
 template <int NW>
-__device__ __forceinline__ int select_wr_grp(const uint64_t* cand, int m, uint32_t u) {
+__device__ __forceinline__ int select_wr_grp(const uint32_t* cand, int m, uint32_t u) {
     const int t = grp_tid();
     const int tot = total_profit_grp<NW>(cand, m);
     const uint32_t x = scale_u32(u, (uint32_t)tot);
     uint32_t run = 0;
     for (int base = 0; base < m; base += kWave * NW) {
         const int q = base + t;
-        const int w = q < m ? entry_c(cand[q]) - 1 : 0;
+        const int w = q < m ? ce_w(cand[q]) : 0;
         const uint32_t incl = (uint32_t)wave_scan(w);
         const int wtot = __builtin_amdgcn_readlane((int)incl, kWave - 1);
         int gtot;
@@ -1753,16 +1777,15 @@ __device__ __forceinline__ int select_wr_grp(const uint64_t* cand, int m, uint32
 }
 
 template <int W, int NW>
-__device__ int select_gp_grp(const uint64_t* cand, int m, const uint64_t* colP, const uint64_t* colN,
+__device__ int select_gp_grp(const uint32_t* cand, int m, const uint64_t* colP, const uint64_t* colN,
                              const uint32_t* live, int n_live, uint32_t alpha_q, long long* n_cols) {
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     for (int base = 0; base < m; base += kWave * NW) {
         const int q = base + grp_tid();
-        const uint64_t e = cand[q < m ? q : 0];
-        const uint32_t key = (uint32_t)e;
-        const int a = key_a(key), b = key_b(key);
-        const bool neg = key & 1u;
+        const uint32_t e = cand[q < m ? q : 0];
+        const int a = ce_a(e), b = ce_b(e);
+        const bool neg = ce_neg(e);
         uint64_t Pk[W], Nk[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -1785,7 +1808,7 @@ __device__ int select_gp_grp(const uint64_t* cand, int m, const uint64_t* colP, 
             n_new += (x == a || x == b) ? 0 : (same >= 2) + (opp >= 2);
         }
         if (q < m) {
-            const long long h = ((long long)(entry_c(e) - 1) << 16) + (long long)alpha_q * n_new;
+            const long long h = ((long long)ce_w(e) << 16) + (long long)alpha_q * n_new;
             if (h > best_h) {
                 best_h = h;
                 best_p = q;
@@ -1881,7 +1904,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     if (proc >= R.n_units || S.active[proc] == 0) return;
 
     const int n_vmax = C.n_x + C.n_fmax;
-    const BulkLayout BL = bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, ADJ ? 1 : 0, C.kbits);
+    // Candidate entries: 64-bit, or 32-bit for units of several waves.
+    using Ent = typename std::conditional<(NW > 1), uint32_t, uint64_t>::type;
+    const BulkLayout BL =
+        bulk_layout(n_vmax, W, C.m_cap, C.newc_cap, C.m_words, ADJ ? 1 : 0, C.kbits, (int)sizeof(Ent));
     // HBM slots are addressed from a kernel argument (which the compiler
     // knows to be global memory) plus a byte offset, so every access to them
     // compiles to global rather than generic loads and stores.
@@ -1891,8 +1917,8 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     char* lists = GS ? (char*)smem : (char*)smem + BL.bytes;
     uint64_t* colP = (uint64_t*)(bulk + BL.colP);
     uint64_t* colN = (uint64_t*)(bulk + BL.colN);
-    uint64_t* cand = (uint64_t*)(bulk + BL.cand);
-    uint64_t* cand2 = (uint64_t*)(bulk + BL.cand2);
+    Ent* cand = (Ent*)(bulk + BL.cand);
+    Ent* cand2 = (Ent*)(bulk + BL.cand2);
     uint64_t* newc = (uint64_t*)(bulk + BL.newc);
     uint64_t* M = (uint64_t*)(bulk + BL.M);
     uint16_t* wt = (uint16_t*)(bulk + BL.wt);
@@ -1957,7 +1983,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             cost = S.cost[proc];
             if constexpr (ADJ) {
                 if (rs.w) {
-                    uint64_t* sw = cand;
+                    Ent* sw = cand;
                     cand = cand2;
                     cand2 = sw;
                 }
@@ -2015,7 +2041,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         // Every unit of a component starts from the same input: its
         // candidates (and second ordering) were counted once, on load.
         m = C.m0;
-        for (int i = l; i < m; i += NT) cand[i] = C.cand0[i];
+        if constexpr (NW > 1)
+            for (int i = l; i < m; i += NT) cand[i] = ce_from64(C.cand0[i]);
+        else
+            for (int i = l; i < m; i += NT) cand[i] = C.cand0[i];
         if (need_tl)
             for (int i = l; i < m; i += NT) tl[i] = C.tl0[i];
         __syncthreads();
@@ -2107,9 +2136,16 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
         }
         if (pick < 0 || pick >= m) { err_flags |= ERR_BAD_PICK; active = 0; break; }
 
-        const uint64_t e = cand[pick];
-        const uint32_t key = (uint32_t)e;
-        const int csel = entry_c(e);
+        uint32_t key;
+        int csel;
+        if constexpr (NW > 1) {
+            key = ce_key(cand[pick]);
+            csel = ce_c(cand[pick]);
+        } else {
+            const uint64_t e = cand[pick];
+            key = (uint32_t)e;
+            csel = entry_c(e);
+        }
         __syncthreads();
         int dead;
         const int k = C.n_x + t + 1;
@@ -2137,7 +2173,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             else
                 m = update_candidates_db<W>(colP, colN, live, n_live, cand, m, cand2, newc, C.newc_cap, C.m_cap,
                                             remap, kpre, key_a(key), key_b(key), k, &n_new, &err_flags);
-            uint64_t* sw = cand;
+            Ent* sw = cand;
             cand = cand2;
             cand2 = sw;
             if (need_tl) {
@@ -2156,7 +2192,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 
     if (l == 0) {
         if constexpr (GS) {
-            const int cur = (ADJ && cand != (uint64_t*)(bulk + BL.cand)) ? 1 : 0;
+            const int cur = (ADJ && cand != (Ent*)(bulk + BL.cand)) ? 1 : 0;
             *rec = make_int4(t, epoch, m, cur);
         }
         S.t[proc] = t;

@@ -291,6 +291,24 @@ def test_hbm_state_large_systems(gpu, oracle, rows, cols, p, cap):
     check_workload(gpu, oracle, [A], kw, f"hbm-state {rows}x{cols}")
 
 
+def test_many_variables_single_wave(gpu, oracle):
+    """A system with more than 2047 variables (n_x + its fresh-variable
+    bound) keeps one wave per unit: its candidates need 64-bit entries, so
+    loading gives it HBM | RANGE without waves and layouts with waves are
+    refused; its units equal the oracle's."""
+    cse, ctx, torch = gpu
+    A = workloads.random_system(4400, 40, 2200, 0.05)
+    sid = cse.cse_system_load(ctx, A)
+    info = cse.cse_scheme_info(ctx, sid)
+    assert info[0][1] + info[0][2] > 2047
+    assert cse.cse_scheme_layout(ctx, sid, 0) == cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE
+    with pytest.raises(cse.CseError, match="CSE_EINVAL"):
+        cse.cse_scheme_layout(ctx, sid, 0, cse.CSE_LAYOUT_HBM | cse.CSE_LAYOUT_RANGE | cse.CSE_LAYOUT_WAVES4)
+    cse.cse_scheme_free(ctx, sid)
+    kw = dict(seed=4, n_proc=6, weights={"gi": 3, "ga": 1, "wr": 1, "mix": 1}, step_cap=4)
+    check_workload(gpu, oracle, [A], kw, "many variables 40x2200")
+
+
 def test_sharing_6x6x6_full_size_sampled(gpu, oracle):
     """The 6x6x6 workload at full size (16384 processes, sharing every 32
     steps): every sampled unit equals the oracle continued from its last
