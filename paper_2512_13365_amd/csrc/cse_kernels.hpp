@@ -1547,7 +1547,7 @@ __device__ void update_tl_grp(uint32_t* tl, int m_old, const int32_t* remap, con
 }
 
 template <int W, int NW>
-__device__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
+__device__ __forceinline__ void build_tl_grp(const uint64_t* colP, const uint64_t* colN, const uint32_t* live, int n_live,
                              const uint32_t* cand, int m, uint32_t* tl) {
     const int t = grp_tid();
     int mt = 0;
@@ -1862,6 +1862,22 @@ __global__ void proc_strategy_kernel(RunArgs R, uint32_t n, int32_t* out) {
 }
 #endif  // CSE_STEP_TU
 
+// A copy of a unit's segment with every word made wave-uniform.  The
+// segment is read with vector loads, whose results the compiler keeps in
+// vector registers and, with them, everything computed from them (the
+// Philox key schedule, every state pointer): about 50 registers per lane
+// held across the step loop.  Uniform copies live in scalar registers.
+__device__ __forceinline__ Segment uniform_segment(const Segment& src) {
+    constexpr int n = (int)(sizeof(Segment) / 4);
+    uint32_t w[n];
+    __builtin_memcpy(w, &src, sizeof(Segment));
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    Segment s;
+    __builtin_memcpy(&s, w, sizeof(Segment));
+    return s;
+}
+
 __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uint32_t g) {
     int lo = 0, hi = n_segs - 1;
     while (lo < hi) {
@@ -1896,7 +1912,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     if (blockIdx.x >= n_grid) return;
     // Dispatch order: the host lists grid units longest expected work first.
     const uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
-    const Segment& sg = segs[find_segment(segs, n_segs, g)];
+    const Segment sg = uniform_segment(segs[find_segment(segs, n_segs, g)]);
     const CompArgs& C = sg.C;
     const RunArgs& R = sg.R;
     const UnitState& S = sg.S;
