@@ -1214,9 +1214,24 @@ __device__ __forceinline__ uint32_t ce_from64(uint64_t e) {
     return ce_make(key_a(k), key_b(k), (int)(k & 1u), entry_c(e));
 }
 
+// A value every lane of the wave holds, marked so for the compiler (kept in
+// a scalar register; loop bounds and branches on it stay scalar).
+template <class T>
+__device__ __forceinline__ T wave_uniform(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    } else {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
 __device__ __forceinline__ int grp_tid() { return (int)threadIdx.x; }
 __device__ __forceinline__ int grp_lane() { return (int)(threadIdx.x & 63u); }
-__device__ __forceinline__ int grp_wave() { return (int)(threadIdx.x >> 6); }
+__device__ __forceinline__ int grp_wave() { return wave_uniform((int)(threadIdx.x >> 6)); }
 
 // Every wave passes one wave-uniform value; all receive the NW values.
 template <int NW, class T>
@@ -1225,7 +1240,7 @@ __device__ __forceinline__ void grp_exchange(T v, T (&all)[NW]) {
     if (grp_lane() == 0) slot[grp_wave()] = v;
     __syncthreads();
 #pragma unroll
-    for (int w = 0; w < NW; ++w) all[w] = slot[w];
+    for (int w = 0; w < NW; ++w) all[w] = wave_uniform(slot[w]);
     __syncthreads();
 }
 // Offset of this wave's wave-uniform count among the waves (lower waves
