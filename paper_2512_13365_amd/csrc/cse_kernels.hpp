@@ -98,7 +98,16 @@ __device__ __forceinline__ uint32_t scale_u32(uint32_t u, uint32_t n) {
 // Wavefront helpers (64 lanes, one wave per workgroup).  Reductions and scans
 // use the device library's DPP sequences; call them in uniform control flow.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+// The lane index, opaque to the compiler: otherwise it computes every
+// lane-dependent constant of the step loop (masks, loop bounds, addresses)
+// once before the loop and holds them all in vector registers (about 15
+// per lane, which cost the one-wave kernels a wave per SIMD); recomputed
+// where used, they cost an instruction or two each.
+__device__ __forceinline__ int lane_id() {
+    int l = (int)threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
+}
 // c + a * b on 24-bit operands in one instruction (the compiler turns a
 // multiply by a 0/1 value into a compare and a select).
 __device__ __forceinline__ int mad_u24(uint32_t a, uint32_t b, int c) {
@@ -1229,8 +1238,8 @@ __device__ __forceinline__ T wave_uniform(T v) {
     }
 }
 
-__device__ __forceinline__ int grp_tid() { return (int)threadIdx.x; }
-__device__ __forceinline__ int grp_lane() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int grp_tid() { return lane_id(); }
+__device__ __forceinline__ int grp_lane() { return lane_id() & 63; }
 __device__ __forceinline__ int grp_wave() { return wave_uniform((int)(threadIdx.x >> 6)); }
 
 // Every wave passes one wave-uniform value; all receive the NW values.
@@ -1923,7 +1932,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     extern __shared__ uint64_t smem[];
     static_assert(NW == 1 || ADJ, "units of several waves walk ranges in gi");
     constexpr int NT = kWave * NW;  // lanes of the unit
-    const int l = (int)threadIdx.x;
+    const int l = lane_id();
     if (blockIdx.x >= n_grid) return;
     // Dispatch order: the host lists grid units longest expected work first.
     const uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
