@@ -2249,10 +2249,10 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 // the process draw.  gp units (any_gp: some job of the launch weights gp)
 // thus share the launch with the others, while each body is compiled on its
 // own.
-// Units of several waves are held to 80 registers (six waves per SIMD).
-// Their natural need is about 100; at 64 (eight waves) the spills cost more
-// than the two extra waves hide (batch pass 1.70 s at eight, 1.60 s at six
-// or seven, 1.71 s at five; the 6x6x6 job 93, 81, 77 and 81 ms at eight,
+// Units of several waves are held to 80 registers (six waves per SIMD),
+// about their natural need; at 64 (eight waves) the spills cost more than
+// the two extra waves hide (batch pass 1.70 s at eight, 1.60 s at six or
+// seven, 1.71 s at five; the 6x6x6 job 93, 81, 77 and 81 ms at eight,
 // seven, six and five).
 template <int W, bool GS, bool ADJ, bool TL, int NW>
 __global__ __launch_bounds__((kWave * NW), (NW > 1 ? 6 : 1)) void step_kernel(
