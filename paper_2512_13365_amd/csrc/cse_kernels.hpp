@@ -210,6 +210,11 @@ struct BulkLayout {
 };
 // Words of one bit-plane (one bit per candidate, 64-candidate granules).
 __host__ __device__ inline int plane_words(int m_cap) { return 2 * ((m_cap + 63) / 64); }
+// The weight bit-planes of one ordering are stored word-interleaved: the k
+// planes' words for candidates 32 w .. 32 w + 31 sit together at
+// pl[w * ks .. w * ks + ks - 1], ks = plane_stride(k) a multiple of four
+// (the planes beyond k zero), so one 16-byte load fetches four planes.
+__host__ __device__ inline int plane_stride(int k) { return (k + 3) & ~3; }
 // Bit-planes needed for the weights c - 1 <= n_e - 1.
 __host__ __device__ inline int weight_bits(int n_e) {
     int k = 1;
@@ -246,7 +251,8 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     o = (o + 15) & ~size_t(15);
     L.rng = o;   o += (size_t)n_vmax * 16;
     L.tinv = o;  o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
-    L.pl = o;    o += (size_t)2 * kbits * plane_words(m_cap) * 4;
+    o = (o + 15) & ~size_t(15);
+    L.pl = o;    o += (size_t)2 * plane_stride(kbits) * plane_words(m_cap) * 4;
     L.bytes = (o + 255) & ~size_t(255);
     return L;
 }
@@ -276,7 +282,8 @@ __host__ __device__ inline TableLayout table_layout(int n_vmax, int m_cap, int k
     size_t o = list_bytes(n_vmax) + newpair_table_bytes(n_vmax);  // HBM state with ranges: several waves
     T.rng = o;  o += (size_t)n_vmax * 16;
     T.tinv = o; o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
-    T.pl = o;   o += (size_t)2 * kbits * plane_words(m_cap) * 4;
+    o = (o + 15) & ~size_t(15);
+    T.pl = o;   o += (size_t)2 * plane_stride(kbits) * plane_words(m_cap) * 4;
     T.bytes = (o + 15) & ~size_t(15);
     return T;
 }
@@ -762,10 +769,11 @@ __device__ void build_tl(const uint64_t* colP, const uint64_t* colN, const uint3
 // rng[v] = (first, end) of the canonical-list range of the pairs whose first
 // variable is v, then (first, end) of the range of the second ordering
 // holding the pairs whose second variable is v.  tinv[q] is the place of
-// candidate q in the second ordering.  pl holds kbits bit-planes of the
-// weights c - 1 in canonical order, then kbits in the second ordering (bit
-// i of word w is candidate 32 w + i).  Returns the number of planes in use:
-// the bit length of the largest weight.
+// candidate q in the second ordering.  pl holds the kbits bit-planes of the
+// weights c - 1 in canonical order, then those of the second ordering at
+// pl + plane_stride(kbits) pw, each word-interleaved (bit i of plane k's
+// word w, pl[w ks + k], is candidate 32 w + i).  Returns the number of
+// planes in use: the bit length of the largest weight.
 __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const int32_t* vpos, int n_live,
                           int32_t* rng, int32_t* tinv, uint32_t* pl, int pw, int kbits) {
     const int l = lane_id();
@@ -802,11 +810,12 @@ __device__ int gi_prepare(const uint64_t* cand, const uint32_t* tl, int m, const
         }
         wmax = w > wmax ? w : wmax;
         const int word = 2 * (base / kWave);
-        for (int k = 0; k < kbits; ++k) {
+        const int ks = plane_stride(kbits);
+        for (int k = 0; k < ks; ++k) {
             const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
             if (l < 2) {
-                pl[k * pw + word + l] = (uint32_t)(l ? bc >> 32 : bc);
-                pl[(kbits + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
+                pl[(word + l) * ks + k] = (uint32_t)(l ? bc >> 32 : bc);
+                pl[ks * pw + (word + l) * ks + k] = (uint32_t)(l ? bt >> 32 : bt);
             }
         }
     }
@@ -889,19 +898,22 @@ struct CoinStream {
 
 // Weighted coin sum over a contiguous range [pos, end) of one ordering whose
 // candidates take the consecutive coins j, j + 1, ...: I += sum of c - 1,
-// X += sum of c - 1 over coin 1, 32 candidates per plane word.
-__device__ __forceinline__ void plane_window(const uint32_t* pl, int pw, int K, int pos, int end, int& j,
+// X += sum of c - 1 over coin 1, 32 candidates per plane word; the planes
+// are word-interleaved with stride ks, and the first ku (a multiple of
+// four) are summed, four per 16-byte load.
+__device__ __forceinline__ void plane_window(const uint32_t* pl, int ks, int ku, int pos, int end, int& j,
                                              CoinStream& co, int& I, int& X) {
     while (pos < end) {
         const int sh = pos & 31;
         const int n = min(32 - sh, end - pos);
         const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
         const uint32_t cw = co.bits(j, n) << sh;
-        const int wi = pos >> 5;
-        for (int k = 0; k < K; ++k) {
-            const uint32_t x = pl[k * pw + wi] & msk;
-            I += __popc(x) << k;
-            X += __popc(x & cw) << k;
+        const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
+        for (int g = 0; g < ku; g += 4) {
+            const uint4 v = q[g >> 2];
+            const uint32_t x0 = v.x & msk, x1 = v.y & msk, x2 = v.z & msk, x3 = v.w & msk;
+            I += (__popc(x0) + (__popc(x1) << 1) + (__popc(x2) << 2) + (__popc(x3) << 3)) << g;
+            X += (__popc(x0 & cw) + (__popc(x1 & cw) << 1) + (__popc(x2 & cw) << 2) + (__popc(x3 & cw) << 3)) << g;
         }
         pos += n;
         j += n;
@@ -926,8 +938,9 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
                                 long long* n_int, long long* n_blk) {
     const int l = lane_id();
     const int T = total_profit(cand, m);
-    const uint32_t* plc = pl;               // canonical order
-    const uint32_t* plt = pl + kbits * pw;  // second ordering
+    const int ks = plane_stride(kbits), ku = plane_stride(K);
+    const uint32_t* plc = pl;            // canonical order
+    const uint32_t* plt = pl + ks * pw;  // second ordering
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
@@ -950,12 +963,12 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             co.init(proc, dw, kp, eh, k0, k1);
             co.first_block();
             if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
-            plane_window(plt, pw, K, ra.z, ra.w, j, co, I, X);
-            plane_window(plc, pw, K, ra.x, p, j, co, I, X);
-            plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
-            plane_window(plt, pw, K, rb.z, t_ab, j, co, I, X);
-            plane_window(plt, pw, K, t_ab + n_ab, rb.w, j, co, I, X);
-            plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
+            plane_window(plt, ks, ku, ra.z, ra.w, j, co, I, X);
+            plane_window(plc, ks, ku, ra.x, p, j, co, I, X);
+            plane_window(plc, ks, ku, p + 1, ra.y, j, co, I, X);
+            plane_window(plt, ks, ku, rb.z, t_ab, j, co, I, X);
+            plane_window(plt, ks, ku, t_ab + n_ab, rb.w, j, co, I, X);
+            plane_window(plc, ks, ku, rb.x, rb.y, j, co, I, X);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
             const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
@@ -1622,8 +1635,9 @@ __device__ __forceinline__ void gi_totals_grp(const uint32_t* cand, int m, int k
     *K = k;
 }
 
-// As gi_prepare, with the K planes of each ordering (the canonical
-// ordering's at pl, the second ordering's at pl + K pw).
+// As gi_prepare, with the K planes of each ordering, word-interleaved with
+// stride plane_stride(K) (the canonical ordering's at pl, the second
+// ordering's at pl + plane_stride(K) pw).
 template <int NW>
 __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint32_t* tl, int m,
                                                const int32_t* vpos, int n_live, int32_t* rng, int32_t* tinv,
@@ -1661,11 +1675,12 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
             tinv[q] = i;
         }
         const int word = 2 * (cb / kWave);
-        for (int k = 0; k < K; ++k) {
+        const int ks = plane_stride(K);
+        for (int k = 0; k < ks; ++k) {
             const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
             if (l < 2) {
-                pl[k * pw + word + l] = (uint32_t)(l ? bc >> 32 : bc);
-                pl[(K + k) * pw + word + l] = (uint32_t)(l ? bt >> 32 : bt);
+                pl[(word + l) * ks + k] = (uint32_t)(l ? bc >> 32 : bc);
+                pl[ks * pw + (word + l) * ks + k] = (uint32_t)(l ? bt >> 32 : bt);
             }
         }
     }
@@ -1692,8 +1707,9 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
                                                     int pw, int K, uint32_t aq, uint32_t bq, uint32_t k0,
                                                     uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
                                                     long long* n_int, long long* n_blk) {
+    const int ks = plane_stride(K), ku = ks;
     const uint32_t* plc = pl;
-    const uint32_t* plt = pl + K * pw;
+    const uint32_t* plt = pl + ks * pw;
     long long best_h = -1;
     int best_p = 0x7FFFFFFF;
     int my_int = 0, my_blk = 0;
@@ -1716,12 +1732,12 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
         // draw it in their own pass of the loop).
         co.first_block();
         if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
-        plane_window(plt, pw, K, ra.z, ra.w, j, co, I, X);
-        plane_window(plc, pw, K, ra.x, p, j, co, I, X);
-        plane_window(plc, pw, K, p + 1, ra.y, j, co, I, X);
-        plane_window(plt, pw, K, rb.z, t_ab, j, co, I, X);
-        plane_window(plt, pw, K, t_ab + n_ab, rb.w, j, co, I, X);
-        plane_window(plc, pw, K, rb.x, rb.y, j, co, I, X);
+        plane_window(plt, ks, ku, ra.z, ra.w, j, co, I, X);
+        plane_window(plc, ks, ku, ra.x, p, j, co, I, X);
+        plane_window(plc, ks, ku, p + 1, ra.y, j, co, I, X);
+        plane_window(plt, ks, ku, rb.z, t_ab, j, co, I, X);
+        plane_window(plt, ks, ku, t_ab + n_ab, rb.w, j, co, I, X);
+        plane_window(plc, ks, ku, rb.x, rb.y, j, co, I, X);
         const long long wp = (long long)ce_w(ep);
         const long long D = (long long)T - wp - I;
         const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
@@ -1929,7 +1945,7 @@ __device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, uin
 template <int W, bool GS, bool ADJ, bool TL, bool GP, int NW>
 __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int n_segs,
                                           const uint32_t* __restrict__ order, uint32_t n_grid, int* err) {
-    extern __shared__ uint64_t smem[];
+    extern __shared__ __attribute__((aligned(16))) uint64_t smem[];
     static_assert(NW == 1 || ADJ, "units of several waves walk ranges in gi");
     constexpr int NT = kWave * NW;  // lanes of the unit
     const int l = lane_id();
@@ -2153,7 +2169,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
                 // The ranges and planes go to the unit's LDS budget when they
                 // fit it (the range tables of TL units are in LDS anyway).
                 const int pw_m = plane_words(m);
-                if (GS && !TL && 16 * n_live + 8 * K * pw_m <= kGsTableBudget) {
+                if (GS && !TL && 16 * n_live + 8 * plane_stride(K) * pw_m <= kGsTableBudget) {
                     int32_t* rng_l = (int32_t*)gtab;
                     uint32_t* pl_l = (uint32_t*)(gtab + 16 * (size_t)n_live);
                     gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng_l, tinv, pl_l, pw_m, K);
