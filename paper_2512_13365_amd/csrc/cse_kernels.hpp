@@ -1637,7 +1637,10 @@ __device__ __forceinline__ void gi_totals_grp(const uint32_t* cand, int m, int k
 
 // As gi_prepare, with the K planes of each ordering, word-interleaved with
 // stride plane_stride(K) (the canonical ordering's at pl, the second
-// ordering's at pl + plane_stride(K) pw).
+// ordering's at pl + plane_stride(K) pw), and tinv[q] the place in the
+// second ordering of the first entry of q's pair (a, b), bit 31 set when
+// the pair is there with both signs: all the twin test of the scoring
+// loop needs.
 template <int NW>
 __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint32_t* tl, int m,
                                                const int32_t* vpos, int n_live, int32_t* rng, int32_t* tinv,
@@ -1656,23 +1659,31 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
         const int w = valid ? ce_w(e) : 0;
         const int wq = valid ? ce_w(eq) : 0;
         const int a = ce_a(e), b = ce_b(eq);
+        // Neighbours in each ordering (other lanes of the chunk, or memory
+        // at its edges): first variables of the canonical list, pairs of
+        // the second ordering (for b's range and the twin test).
+        const uint32_t pq = valid ? ce_pair(eq) : 0u;
         int pa = __shfl_up(a, 1), na = __shfl_down(a, 1);
-        int pb = __shfl_up(b, 1), nb = __shfl_down(b, 1);
+        uint32_t pp = __shfl_up(pq, 1), pn = __shfl_down(pq, 1);
         if (l == 0) {
             pa = i > 0 && valid ? ce_a(cand[i - 1]) : -1;
-            pb = i > 0 && valid ? ce_b(cand[tl[i - 1]]) : -1;
+            pp = i > 0 && valid ? ce_pair(cand[tl[i - 1]]) : 0u;
         }
         if (l == kWave - 1 || i + 1 >= m) {
             na = i + 1 < m ? ce_a(cand[i + 1]) : -1;
-            nb = i + 1 < m ? ce_b(cand[tl[i + 1]]) : -1;
+            pn = i + 1 < m ? ce_pair(cand[tl[i + 1]]) : 0u;
         }
         if (valid) {
             const int va = vpos[a - 1], vb = vpos[b - 1];
             if (a != pa) rng[4 * va + 0] = i;
             if (a != na) rng[4 * va + 1] = i + 1;
-            if (b != pb) rng[4 * vb + 2] = i;
-            if (b != nb) rng[4 * vb + 3] = i + 1;
-            tinv[q] = i;
+            if ((pp & 0x7FFu) != (uint32_t)b) rng[4 * vb + 2] = i;
+            if ((pn & 0x7FFu) != (uint32_t)b) rng[4 * vb + 3] = i + 1;
+            // The place of q's pair in the second ordering: the first of
+            // its entries (the twins of the two signs sit together there),
+            // and bit 31 set when there are two.
+            const bool twin_prev = pp == pq, twin_next = pn == pq;
+            tinv[q] = (twin_prev ? i - 1 : i) | (twin_prev || twin_next ? (int)0x80000000u : 0);
         }
         const int word = 2 * (cb / kWave);
         const int ks = plane_stride(K);
@@ -1719,11 +1730,9 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
         const int va = vpos[ce_a(ep) - 1], vb = vpos[ce_b(ep) - 1];
         const int4 ra = *(const int4*)(rng + 4 * va);
         const int4 rb = *(const int4*)(rng + 4 * vb);
-        const bool tprev = p > 0 && ce_pair(cand[p - 1]) == ce_pair(ep);
-        const bool tnext = p + 1 < m && ce_pair(cand[p + 1]) == ce_pair(ep);
-        const int q_lo = tprev ? p - 1 : p;
-        const int n_ab = (tprev || tnext) ? 2 : 1;
-        const int t_ab = tinv[q_lo];
+        const int tv = tinv[p];
+        const int n_ab = tv < 0 ? 2 : 1;
+        const int t_ab = tv & 0x7FFFFFFF;
         int I = 0, X = 0, j = 0;
         CoinStream co;
         co.init(proc, dw, kp, eh, k0, k1);
