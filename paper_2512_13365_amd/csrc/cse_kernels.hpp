@@ -206,7 +206,7 @@ struct Segment {
 // weight bit-planes of both orderings instead of the gi masks.  m_words is
 // the mask capacity in 64-bit words.
 struct BulkLayout {
-    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, tinv, pl, bytes;
+    size_t colP, colN, cand, cand2, newc, M, wt, tl, remap, kpre, rng, ssum, tinv, pl, bytes;
 };
 // Words of one bit-plane (one bit per candidate, 64-candidate granules).
 __host__ __device__ inline int plane_words(int m_cap) { return 2 * ((m_cap + 63) / 64); }
@@ -238,7 +238,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
         L.M = o;
         L.wt = o + (size_t)m_words * 8;
         o += gi > up ? gi : up;
-        L.cand2 = L.tl = L.remap = L.kpre = L.rng = L.tinv = L.pl = o;
+        L.cand2 = L.tl = L.remap = L.kpre = L.rng = L.ssum = L.tinv = L.pl = o;
         L.bytes = (o + 255) & ~size_t(255);
         return L;
     }
@@ -250,6 +250,7 @@ __host__ __device__ inline BulkLayout bulk_layout(int n_vmax, int W, int m_cap, 
     L.kpre = o;  o += ((size_t)m_cap * 4 + 8) & ~size_t(7);
     o = (o + 15) & ~size_t(15);
     L.rng = o;   o += (size_t)n_vmax * 16;
+    L.ssum = o;  o += ((size_t)n_vmax * 4 + 15) & ~size_t(15);
     L.tinv = o;  o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
     o = (o + 15) & ~size_t(15);
     L.pl = o;    o += (size_t)2 * plane_stride(kbits) * plane_words(m_cap) * 4;
@@ -266,8 +267,9 @@ __host__ __device__ inline size_t newpair_table_bytes(int n_vmax) {
     return ((size_t)((n_vmax + 63) / 64) * 24 + 15) & ~size_t(15);
 }
 // After that table they keep a fixed LDS budget for gi's per-step tables
-// (ranges and weight planes), used at every step whose tables fit it; steps
-// whose tables do not fit use the copies in the HBM slot.
+// (ranges, per-variable profit sums and weight planes), used at every step
+// whose tables fit it; steps whose tables do not fit use the copies in the
+// HBM slot.
 constexpr int kGsTableBudget = 11 * 1024;
 
 // Units with state in HBM slots may keep the per-step tables of the range
@@ -275,12 +277,13 @@ constexpr int kGsTableBudget = 11 * 1024;
 // LDS after their lists instead of in the slot: offsets in LDS, and bytes
 // of LDS in all.
 struct TableLayout {
-    size_t rng, tinv, pl, bytes;
+    size_t rng, ssum, tinv, pl, bytes;
 };
 __host__ __device__ inline TableLayout table_layout(int n_vmax, int m_cap, int kbits) {
     TableLayout T;
     size_t o = list_bytes(n_vmax) + newpair_table_bytes(n_vmax);  // HBM state with ranges: several waves
     T.rng = o;  o += (size_t)n_vmax * 16;
+    T.ssum = o; o += ((size_t)n_vmax * 4 + 15) & ~size_t(15);
     T.tinv = o; o += ((size_t)m_cap * 4 + 7) & ~size_t(7);
     o = (o + 15) & ~size_t(15);
     T.pl = o;   o += (size_t)2 * plane_stride(kbits) * plane_words(m_cap) * 4;
@@ -918,6 +921,43 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int ks, int ku,
         pos += n;
         j += n;
     }
+}
+
+// As plane_window, the coin-weighted sum X only.
+__device__ __forceinline__ void plane_window_x(const uint32_t* pl, int ks, int pos, int end, int& j,
+                                               CoinStream& co, int& X) {
+    while (pos < end) {
+        const int sh = pos & 31;
+        const int n = min(32 - sh, end - pos);
+        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint32_t mc = (co.bits(j, n) << sh) & msk;
+        const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
+        for (int g = 0; g < ks; g += 4) {
+            const uint4 v = q[g >> 2];
+            X += (__popc(v.x & mc) + (__popc(v.y & mc) << 1) + (__popc(v.z & mc) << 2) + (__popc(v.w & mc) << 3))
+                 << g;
+        }
+        pos += n;
+        j += n;
+    }
+}
+// Sum of c - 1 over the candidates [pos, end) of one ordering, from its planes.
+__device__ __forceinline__ int plane_sum(const uint32_t* pl, int ks, int pos, int end) {
+    int I = 0;
+    while (pos < end) {
+        const int sh = pos & 31;
+        const int n = min(32 - sh, end - pos);
+        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
+        for (int g = 0; g < ks; g += 4) {
+            const uint4 v = q[g >> 2];
+            I += (__popc(v.x & msk) + (__popc(v.y & msk) << 1) + (__popc(v.z & msk) << 2) +
+                  (__popc(v.w & msk) << 3))
+                 << g;
+        }
+        pos += n;
+    }
+    return I;
 }
 
 // Greedy-Intersections over per-variable ranges (any number of candidates).
@@ -1643,8 +1683,8 @@ __device__ __forceinline__ void gi_totals_grp(const uint32_t* cand, int m, int k
 // loop needs.
 template <int NW>
 __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint32_t* tl, int m,
-                                               const int32_t* vpos, int n_live, int32_t* rng, int32_t* tinv,
-                                               uint32_t* pl, int pw, int K) {
+                                               const int32_t* vpos, int n_live, int32_t* rng, int32_t* ssum,
+                                               int32_t* tinv, uint32_t* pl, int pw, int K) {
     const int l = grp_lane();
     for (int i = grp_tid(); i < 4 * n_live; i += kWave * NW) rng[i] = 0;
     __syncthreads();
@@ -1696,6 +1736,14 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
         }
     }
     __syncthreads();
+    // S_v: the profit of the candidates holding live variable v, its pairs
+    // (v, y) (canonical range) and (x, v) (range of the second ordering).
+    const int ks = plane_stride(K);
+    for (int v = grp_tid(); v < n_live; v += kWave * NW) {
+        const int4 r = *(const int4*)(rng + 4 * v);
+        ssum[v] = plane_sum(pl, ks, r.x, r.y) + plane_sum(pl + ks * pw, ks, r.z, r.w);
+    }
+    __syncthreads();
 }
 
 template <int NW>
@@ -1714,11 +1762,12 @@ __device__ __forceinline__ int gi_argmax_grp(long long best_h, int best_p) {
 // As select_gi_planes over the tables of gi_prepare_grp.
 template <int NW>
 __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m, int T, const int32_t* vpos,
-                                                    const int32_t* rng, const int32_t* tinv, const uint32_t* pl,
+                                                    const int32_t* rng, const int32_t* ssum,
+                                                    const int32_t* tinv, const uint32_t* pl,
                                                     int pw, int K, uint32_t aq, uint32_t bq, uint32_t k0,
                                                     uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
                                                     long long* n_int, long long* n_blk) {
-    const int ks = plane_stride(K), ku = ks;
+    const int ks = plane_stride(K);
     const uint32_t* plc = pl;
     const uint32_t* plt = pl + ks * pw;
     long long best_h = -1;
@@ -1733,7 +1782,12 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
         const int tv = tinv[p];
         const int n_ab = tv < 0 ? 2 : 1;
         const int t_ab = tv & 0x7FFFFFFF;
-        int I = 0, X = 0, j = 0;
+        // I_p: the candidates holding a or b, less p (counted in both) and
+        // its twin of the other sign (in both; next to p in canonical order).
+        const int wp = ce_w(ep);
+        const int w_twin = tv < 0 ? ce_w(cand[ce_neg(ep) ? p - 1 : p + 1]) : 0;
+        const int I = ssum[va] + ssum[vb] - 2 * wp - w_twin;
+        int X = 0, j = 0;
         CoinStream co;
         co.init(proc, dw, kp, eh, k0, k1);
         // The blocks of the first 256 coins are drawn by all lanes at once
@@ -1741,15 +1795,14 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
         // draw it in their own pass of the loop).
         co.first_block();
         if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
-        plane_window(plt, ks, ku, ra.z, ra.w, j, co, I, X);
-        plane_window(plc, ks, ku, ra.x, p, j, co, I, X);
-        plane_window(plc, ks, ku, p + 1, ra.y, j, co, I, X);
-        plane_window(plt, ks, ku, rb.z, t_ab, j, co, I, X);
-        plane_window(plt, ks, ku, t_ab + n_ab, rb.w, j, co, I, X);
-        plane_window(plc, ks, ku, rb.x, rb.y, j, co, I, X);
-        const long long wp = (long long)ce_w(ep);
+        plane_window_x(plt, ks, ra.z, ra.w, j, co, X);
+        plane_window_x(plc, ks, ra.x, p, j, co, X);
+        plane_window_x(plc, ks, p + 1, ra.y, j, co, X);
+        plane_window_x(plt, ks, rb.z, t_ab, j, co, X);
+        plane_window_x(plt, ks, t_ab + n_ab, rb.w, j, co, X);
+        plane_window_x(plc, ks, rb.x, rb.y, j, co, X);
         const long long D = (long long)T - wp - I;
-        const long long hsc = (wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
+        const long long hsc = ((long long)wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
         if (hsc > best_h) { best_h = hsc; best_p = p; }
         my_int += j;
         my_blk += (j + 127) >> 7;
@@ -1992,6 +2045,7 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
     int32_t* kpre = (int32_t*)(bulk + BL.kpre);
     const TableLayout TB = table_layout(n_vmax, C.m_cap, C.kbits);
     int32_t* rng = TL ? (int32_t*)((char*)smem + TB.rng) : (int32_t*)(bulk + BL.rng);
+    int32_t* ssum = TL ? (int32_t*)((char*)smem + TB.ssum) : (int32_t*)(bulk + BL.ssum);
     int32_t* tinv = TL ? (int32_t*)((char*)smem + TB.tinv) : (int32_t*)(bulk + BL.tinv);
     uint32_t* pl = TL ? (uint32_t*)((char*)smem + TB.pl) : (uint32_t*)(bulk + BL.pl);
     const int pw = plane_words(C.m_cap);
@@ -2175,18 +2229,21 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
             if constexpr (ADJ && NW > 1) {
                 int T, K;
                 gi_totals_grp<NW>(cand, m, C.kbits, &T, &K);
-                // The ranges and planes go to the unit's LDS budget when they
-                // fit it (the range tables of TL units are in LDS anyway).
+                // The ranges, profit sums and planes go to the unit's LDS
+                // budget when they fit it (the range tables of TL units are in
+                // LDS anyway).
                 const int pw_m = plane_words(m);
-                if (GS && !TL && 16 * n_live + 8 * plane_stride(K) * pw_m <= kGsTableBudget) {
+                const int ss_b = (4 * n_live + 15) & ~15;
+                if (GS && !TL && 16 * n_live + ss_b + 8 * plane_stride(K) * pw_m <= kGsTableBudget) {
                     int32_t* rng_l = (int32_t*)gtab;
-                    uint32_t* pl_l = (uint32_t*)(gtab + 16 * (size_t)n_live);
-                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng_l, tinv, pl_l, pw_m, K);
-                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng_l, tinv, pl_l, pw_m, K, alpha_q, beta_q,
-                                                    k0, k1, proc, dw, eh, &n_int, &n_blk);
+                    int32_t* ssum_l = (int32_t*)(gtab + 16 * (size_t)n_live);
+                    uint32_t* pl_l = (uint32_t*)(gtab + 16 * (size_t)n_live + ss_b);
+                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng_l, ssum_l, tinv, pl_l, pw_m, K);
+                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng_l, ssum_l, tinv, pl_l, pw_m, K, alpha_q,
+                                                    beta_q, k0, k1, proc, dw, eh, &n_int, &n_blk);
                 } else {
-                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, tinv, pl, pw, K);
-                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng, tinv, pl, pw, K, alpha_q, beta_q, k0,
+                    gi_prepare_grp<NW>(cand, tl, m, vpos, n_live, rng, ssum, tinv, pl, pw, K);
+                    pick = select_gi_planes_grp<NW>(cand, m, T, vpos, rng, ssum, tinv, pl, pw, K, alpha_q, beta_q, k0,
                                                     k1, proc, dw, eh, &n_int, &n_blk);
                 }
             } else if constexpr (ADJ) {
