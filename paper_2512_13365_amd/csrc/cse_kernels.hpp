@@ -1727,11 +1727,19 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
         }
         const int word = 2 * (cb / kWave);
         const int ks = plane_stride(K);
-        for (int k = 0; k < ks; ++k) {
-            const uint64_t bc = ballot((w >> k) & 1), bt = ballot((wq >> k) & 1);
+        // Lanes 0 and 1 store the low and high halves of four planes' ballots
+        // at a time (one 16-byte store per ordering).
+        for (int k = 0; k < ks; k += 4) {
+            uint32_t c4[4], t4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t bc = ballot((w >> (k + u)) & 1), bt = ballot((wq >> (k + u)) & 1);
+                c4[u] = (uint32_t)(l ? bc >> 32 : bc);
+                t4[u] = (uint32_t)(l ? bt >> 32 : bt);
+            }
             if (l < 2) {
-                pl[(word + l) * ks + k] = (uint32_t)(l ? bc >> 32 : bc);
-                pl[ks * pw + (word + l) * ks + k] = (uint32_t)(l ? bt >> 32 : bt);
+                *(uint4*)(pl + (word + l) * ks + k) = make_uint4(c4[0], c4[1], c4[2], c4[3]);
+                *(uint4*)(pl + ks * pw + (word + l) * ks + k) = make_uint4(t4[0], t4[1], t4[2], t4[3]);
             }
         }
     }
