@@ -578,6 +578,28 @@ def test_layouts_and_autotune_same_results(gpu, oracle, rows, cols, p, cap):
     cse.cse_scheme_free(ctx, sid)
 
 
+def test_range_form_wide_weights(gpu, oracle):
+    """A pair held by 300 of 320 rows gives weights c - 1 of nine bits, so the
+    range form's weight planes take three 16-byte groups per word; every
+    range layout (one and four waves, tables in the slot, in LDS or in the
+    LDS budget) reproduces the oracle's runs."""
+    cse, ctx, torch = gpu
+    A = workloads.random_system(9321, 320, 14, 0.25)
+    A[:300, 0] = 1
+    A[:300, 1] = 1
+    kw = dict(seed=77, n_proc=64, weights=dict(ALL_W), proc0_greedy=True, step_cap=24)
+    ref = compare(oracle, [A], kw, "wide weights")[0]
+    sid = cse.cse_system_load(ctx, A)
+    W4 = cse.CSE_LAYOUT_WAVES4
+    for lay in (2, 3, 2 | W4, 3 | W4, 7 | W4):
+        cse.cse_scheme_layout(ctx, sid, 0, lay)
+        say(f"[gpu] wide weights: layout {lay}")
+        job, got = run_loaded(gpu, sid, kw)
+        cse.cse_job_release(ctx, job)
+        assert_same(got, ref, f"wide weights, layout {lay}")
+    cse.cse_scheme_free(ctx, sid)
+
+
 def test_server_cancel_queued_and_running(gpu, oracle):
     """A queued server job cancelled before admission never runs; a running
     one stops at the end of its round and keeps prefixes of the oracle's runs;
