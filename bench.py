@@ -223,10 +223,11 @@ def kernel_name(W, layout):
     return f"step_kernel<{W}, {b(gs)}, {b(adj)}, {b(tl)}, {nw}>"
 
 
-def scheme_pass(cse, ctx, stream, dev, cfgs, batched):
-    """One pass over the batch: load every scheme from its device tensors,
-    run the jobs (one batched launch, or one plain launch after another),
-    read every unit's results, release.  Returns per-pass figures."""
+def scheme_pass(cse, ctx, stream, dev, cfgs, batched, layouts=None):
+    """One pass over the batch: load every scheme from its device tensors
+    (and give its components the layouts chosen before timing, if any), run
+    the jobs (one batched launch, or one plain launch after another), read
+    every unit's results, release.  Returns per-pass figures."""
     import numpy as np
     t0 = time.perf_counter()
     out = {"subs": 0, "best": [], "ttb_s": [], "per_class_ops": {}, "classes": {}}
@@ -247,8 +248,15 @@ def scheme_pass(cse, ctx, stream, dev, cfgs, batched):
         out["best"].append(best_total)
         out["ttb_s"].append(t_start + ttb)
 
+    def load(i, d):
+        sid = cse.cse_scheme_load_device(ctx, *d, stream=stream)
+        if layouts is not None:
+            for c, lay in enumerate(layouts[i]):
+                cse.cse_scheme_layout(ctx, sid, c, lay)
+        return sid
+
     if batched:
-        sids = [cse.cse_scheme_load_device(ctx, *d, stream=stream) for d in dev]
+        sids = [load(i, d) for i, d in enumerate(dev)]
         t_launch = time.perf_counter() - t0
         jobs = cse.cse_launch_batch(ctx, sids, cfgs, stream)
         for j in jobs:
@@ -261,9 +269,9 @@ def scheme_pass(cse, ctx, stream, dev, cfgs, batched):
         for sid in sids:
             cse.cse_scheme_free(ctx, sid)
     else:
-        for d, cfg in zip(dev, cfgs):
+        for i, (d, cfg) in enumerate(zip(dev, cfgs)):
             t_start = time.perf_counter() - t0
-            sid = cse.cse_scheme_load_device(ctx, *d, stream=stream)
+            sid = load(i, d)
             j = cse.cse_launch(ctx, sid, cfg, stream)
             cse.cse_wait(ctx, j)
             collect(j, sid, cfg.n_proc, t_start)
@@ -324,22 +332,39 @@ def run_batch(args, cse, workloads, torch, ctx, stream):
     cfgs = [cse.cse_run_cfg(**rs.as_kwargs()) for rs in wl.runs]
     torch.cuda.synchronize()
     log(f"[bench] workload batch-32: {len(wl.schemes)} schemes, {sum(rs.n_proc for rs in wl.runs)} processes")
+    # Component layouts (state placement, gi form, waves per unit) chosen
+    # once by the autotuner, before any timed pass; every pass loads the
+    # schemes afresh and gives them these layouts.
+    layouts, tuning = None, {"mode": "default"}
+    if args.layouts == "autotune":
+        t_tune = time.perf_counter()
+        sids = [cse.cse_scheme_load_device(ctx, *d, stream=stream) for d in dev]
+        default = [[cse.cse_scheme_layout(ctx, sid, c) for c in range(3)] for sid in sids]
+        layouts = [cse.cse_autotune(ctx, sid, cfg, stream) for sid, cfg in zip(sids, cfgs)]
+        for sid in sids:
+            cse.cse_scheme_free(ctx, sid)
+        torch.cuda.synchronize()
+        changed = sum(a != b for d, t in zip(default, layouts) for a, b in zip(d, t))
+        tuning = {"mode": "cse_autotune once per scheme before the timed passes",
+                  "seconds": time.perf_counter() - t_tune, "components_changed": changed,
+                  "components": 3 * len(sids)}
+        log(f"[bench] autotune: {changed} of {3 * len(sids)} component layouts changed in {tuning['seconds']:.1f} s")
     cse.cse_ctx_set_timing(ctx, True)
     for w in range(args.warmup):
-        p = scheme_pass(cse, ctx, stream, dev, cfgs, True)
+        p = scheme_pass(cse, ctx, stream, dev, cfgs, True, layouts)
         log(f"[bench] warmup {w}: {p['seconds'] * 1e3:.1f} ms")
     torch.cuda.synchronize()
     passes = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        passes.append(scheme_pass(cse, ctx, stream, dev, cfgs, True))
+        passes.append(scheme_pass(cse, ctx, stream, dev, cfgs, True, layouts))
         log(f"[bench] batched pass {k}: {passes[-1]['seconds'] * 1e3:.1f} ms")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     cse.cse_ctx_set_timing(ctx, False)
     plain = []
     for k in range(args.plain_passes):
-        plain.append(scheme_pass(cse, ctx, stream, dev, cfgs, False))
+        plain.append(scheme_pass(cse, ctx, stream, dev, cfgs, False, layouts))
         log(f"[bench] plain pass {k}: {plain[-1]['seconds'] * 1e3:.1f} ms")
     subs = sum(p["subs"] for p in passes)
     sec = [p["seconds"] for p in passes]
@@ -360,7 +385,8 @@ def run_batch(args, cse, workloads, torch, ctx, stream):
     out = base_line(
         args, value=subs / total, unit="substitution steps/s", ms_per_step=total / args.steps * 1e3,
         config={"workload": BATCH_NAME, "schemes": len(wl.schemes), "n_proc_total": sum(rs.n_proc for rs in wl.runs),
-                "substitutions_per_step": first["subs"], "inputs_sha256": workloads.workload_digest(wl)},
+                "substitutions_per_step": first["subs"], "inputs_sha256": workloads.workload_digest(wl),
+                "layouts": tuning},
         ms_per_step_median=float(np.median(sec)) * 1e3,
         time_to_best_ms={"mean_over_schemes": float(np.mean(first["ttb_s"])) * 1e3,
                          "max_over_schemes": float(np.max(first["ttb_s"])) * 1e3},
@@ -571,6 +597,8 @@ def main():
     ap.add_argument("--strategy", default=None, choices=["g", "ga", "wr", "gr", "gi", "mix", "gp"],
                     help="4x4x4 only: every process uses this strategy (per-strategy cost)")
     ap.add_argument("--autotune", action="store_true", help="6x6x6: pick component layouts with cse_autotune first")
+    ap.add_argument("--layouts", default="default", choices=["default", "autotune"],
+                    help="batch: the loader's component layouts, or those cse_autotune picks once before timing")
     ap.add_argument("--count-path", default="auto", choices=list(COUNT_PATHS),
                     help="4x4x4 / 6x6x6: how the input's pair counts are computed (same results)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: number of jobs of the stream")
