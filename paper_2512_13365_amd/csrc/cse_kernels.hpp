@@ -1118,14 +1118,23 @@ __device__ __forceinline__ void mask_walk(const uint32_t* Ma, const uint32_t* Mb
         uint32_t cw = co.bits(j, nm);
         j += nm;
         const uint16_t* wrow = wt + (w << 5);
-        do {
-            const int bit = __builtin_ctz(u);
+        // The next member's weight is read before this one is summed, so the
+        // LDS latency overlaps the arithmetic (the last read repeats a
+        // member's own weight and is unused).
+        int bit = __builtin_ctz(u);
+        u &= u - 1u;
+        uint32_t wq = wrow[bit];
+        while (true) {
+            const bool more = u != 0u;
+            bit = more ? __builtin_ctz(u) : bit;
+            const uint32_t wn = wrow[bit];
             u &= u - 1u;
-            const uint32_t wq = wrow[bit];
             I += (int)wq;
             X = mad_u24(cw & 1u, wq, X);
             cw >>= 1;
-        } while (u);
+            if (!more) break;
+            wq = wn;
+        }
     }
 }
 
