@@ -1,13 +1,14 @@
 // cse_kernels.hpp -- gfx950 device code for randomized CSE processes
 // (Perminov, arXiv 2512.13365, Algorithm 1 and Sec. 3.4-3.5).
 //
-// Execution model: one 64-lane wavefront (one workgroup) per unit, i.e. one
-// component reduced by one process.  A launch covers a table of segments;
+// Execution model: one workgroup per unit, i.e. one component reduced by one
+// process: one 64-lane wavefront, or two or four for units whose gi walks
+// ranges (the *_grp functions).  A launch covers a table of segments;
 // a segment is a contiguous range of units that share one system and one run
 // configuration, so one launch can hold the three components of a scheme or
 // the components of many schemes.  The step kernel is specialised on the row
-// words W, on where the unit's state lives and on the form of gi.  A unit's
-// state:
+// words W, on where the unit's state lives, on the form of gi and on the
+// waves per unit.  A unit's state:
 //   colP[v][w], colN[v][w]  pos / neg bitsets of variable v over the rows,
 //                           W 64-bit words per column (rows <= 64 W);
 //   live[], vpos[]          ids of the variables with a nonzero column,
@@ -15,19 +16,21 @@
 //                           the position of each live variable in that list;
 //   cand[]                  the pairs occurring at least twice, in canonical
 //                           order, one 64-bit entry each: key | c << 32 with
-//                           key = a << 16 | b << 1 | (s < 0);
+//                           key = a << 16 | b << 1 | (s < 0); units of
+//                           several waves keep 32-bit entries
+//                           a << 21 | b << 10 | (s < 0) << 9 | (c - 1);
 //   newc[]                  the pairs of the fresh variable (update scratch);
 //   M[], wt[]               per-variable candidate masks and weights (the
 //                           mask form of gi; they share newc's region);
-//   cand2[], tl[], tinv[], pl[], rng[], remap[], kpre[]
+//   cand2[], tl[], tinv[], pl[], rng[], ssum[], remap[], kpre[]
 //                           for large candidate sets (the range form of gi):
 //                           a second candidate buffer, the second ordering
 //                           (by second variable) and each candidate's place
 //                           in it, weight bit-planes, per-variable ranges
-//                           and the index map of the update.
+//                           and profit sums, and the index map of the update.
 // The lists live in LDS; the rest lives in LDS too, or, for systems whose
 // state would leave fewer than four units per CU, in a per-unit slot in HBM
-// (optionally with tinv, pl and rng in LDS).  A slot also records which state
+// (optionally with tinv, pl, rng and ssum in LDS).  A slot also records which state
 // it holds, so a unit that was not restarted resumes from it at its next
 // launch instead of replaying its program.
 // The pair count of (a, b, +) is popc(Pa & Pb) + popc(Na & Nb) and of
@@ -941,6 +944,7 @@ __device__ __forceinline__ void plane_window_x(const uint32_t* pl, int ks, int p
         j += n;
     }
 }
+
 // Sum of c - 1 over the candidates [pos, end) of one ordering, from its planes.
 __device__ __forceinline__ int plane_sum(const uint32_t* pl, int ks, int pos, int end) {
     int I = 0;
