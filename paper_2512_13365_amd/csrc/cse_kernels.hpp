@@ -945,6 +945,69 @@ __device__ __forceinline__ void plane_window_x(const uint32_t* pl, int ks, int p
     }
 }
 
+// Bits 0 .. k - 1 of a word (0 <= k <= 32).
+__device__ __forceinline__ uint32_t low_bits(int k) { return k >= 32 ? 0xFFFFFFFFu : (1u << k) - 1u; }
+
+// The window [pos, end) of one ordering less the gap [s0, s0 + ns) inside it
+// (the scored candidate, or the pair's one or two entries): the coins run on
+// over the gap, so the plane word that holds it is read once, its coin word
+// spread around the gap (coins after it move up by the gap's width in that
+// word), rather than as two windows with a partial word each.  Per word:
+// the window's bits less the gap (msk) and its coin mask (mc).
+struct GapWord {
+    uint32_t msk, mc;
+    int n;   // positions of the window in this word
+    int nc;  // coins taken: n less the gap's positions in this word
+};
+__device__ __forceinline__ GapWord gap_word(int pos, int end, int s0, int ns, int j, CoinStream& co) {
+    GapWord g;
+    const int sh = pos & 31;
+    g.n = min(32 - sh, end - pos);
+    const int wb = pos - sh;  // the position of the word's bit 0
+    const int gl = min(max(s0 - wb, sh), sh + g.n), gh = min(max(s0 + ns - wb, sh), sh + g.n);
+    const int e = gh - gl;
+    g.nc = g.n - e;
+    g.msk = ((g.n == 32 ? 0xFFFFFFFFu : ((1u << g.n) - 1u)) << sh) & ~(low_bits(gh) & ~low_bits(gl));
+    const uint32_t cc = (g.nc > 0 ? co.bits(j, g.nc) : 0u) << sh;
+    g.mc = ((cc & low_bits(gl)) | ((cc << e) & ~low_bits(gh))) & g.msk;
+    return g;
+}
+
+// plane_window over [pos, end) less the gap [s0, s0 + ns).
+__device__ __forceinline__ void plane_window_gap(const uint32_t* pl, int ks, int ku, int pos, int end, int s0,
+                                                 int ns, int& j, CoinStream& co, int& I, int& X) {
+    while (pos < end) {
+        const GapWord g = gap_word(pos, end, s0, ns, j, co);
+        const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
+        for (int k = 0; k < ku; k += 4) {
+            const uint4 v = q[k >> 2];
+            const uint32_t x0 = v.x & g.msk, x1 = v.y & g.msk, x2 = v.z & g.msk, x3 = v.w & g.msk;
+            I += (__popc(x0) + (__popc(x1) << 1) + (__popc(x2) << 2) + (__popc(x3) << 3)) << k;
+            X += (__popc(x0 & g.mc) + (__popc(x1 & g.mc) << 1) + (__popc(x2 & g.mc) << 2) + (__popc(x3 & g.mc) << 3))
+                 << k;
+        }
+        j += g.nc;
+        pos += g.n;
+    }
+}
+
+// plane_window_x over [pos, end) less the gap [s0, s0 + ns).
+__device__ __forceinline__ void plane_window_x_gap(const uint32_t* pl, int ks, int pos, int end, int s0, int ns,
+                                                   int& j, CoinStream& co, int& X) {
+    while (pos < end) {
+        const GapWord g = gap_word(pos, end, s0, ns, j, co);
+        const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
+        for (int k = 0; k < ks; k += 4) {
+            const uint4 v = q[k >> 2];
+            X += (__popc(v.x & g.mc) + (__popc(v.y & g.mc) << 1) + (__popc(v.z & g.mc) << 2) +
+                  (__popc(v.w & g.mc) << 3))
+                 << k;
+        }
+        j += g.nc;
+        pos += g.n;
+    }
+}
+
 // Sum of c - 1 over the candidates [pos, end) of one ordering, from its planes.
 __device__ __forceinline__ int plane_sum(const uint32_t* pl, int ks, int pos, int end) {
     int I = 0;
@@ -974,8 +1037,10 @@ __device__ __forceinline__ int plane_sum(const uint32_t* pl, int ks, int pos, in
 //       pairs (x, b), x < b, without (a, b, +-) (b's range of the second
 //       ordering, where those entries sit together at tinv of the first),
 //       then the pairs (b, y) (b's canonical range).
-// Every part is a contiguous range whose members take consecutive coins, so
-// lane p sums them 32 candidates at a time through the weight bit-planes.
+// Every part is a contiguous range (p's canonical range less p, b's range of
+// the second ordering less the pair's entries) whose members take
+// consecutive coins, so lane p sums them 32 candidates at a time through the
+// weight bit-planes.
 __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos, const int32_t* rng,
                                 const int32_t* tinv, const uint32_t* pl, int pw, int kbits, int K, uint32_t aq,
                                 uint32_t bq, uint32_t k0, uint32_t k1, uint32_t proc, uint32_t dw, uint32_t eh,
@@ -1008,10 +1073,8 @@ __device__ int select_gi_planes(const uint64_t* cand, int m, const int32_t* vpos
             co.first_block();
             if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
             plane_window(plt, ks, ku, ra.z, ra.w, j, co, I, X);
-            plane_window(plc, ks, ku, ra.x, p, j, co, I, X);
-            plane_window(plc, ks, ku, p + 1, ra.y, j, co, I, X);
-            plane_window(plt, ks, ku, rb.z, t_ab, j, co, I, X);
-            plane_window(plt, ks, ku, t_ab + n_ab, rb.w, j, co, I, X);
+            plane_window_gap(plc, ks, ku, ra.x, ra.y, p, 1, j, co, I, X);
+            plane_window_gap(plt, ks, ku, rb.z, rb.w, t_ab, n_ab, j, co, I, X);
             plane_window(plc, ks, ku, rb.x, rb.y, j, co, I, X);
             const long long wp = (long long)entry_c(ep) - 1;
             const long long D = (long long)T - wp - I;
@@ -1701,14 +1764,12 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
     const int l = grp_lane();
     for (int i = grp_tid(); i < 4 * n_live; i += kWave * NW) rng[i] = 0;
     __syncthreads();
-    for (int base = 0; base < m; base += kWave * NW) {
-        const int cb = base + kWave * grp_wave();  // this wave's chunk
-        if (cb >= m) continue;
+    const int ks = plane_stride(K);
+    // One chunk of 64 candidates of the canonical list (e) and the second
+    // ordering (q, its candidate eq) at positions cb + lane.
+    auto chunk = [&](const int cb, const uint32_t e, const uint32_t q, const uint32_t eq) {
         const int i = cb + l;
         const bool valid = i < m;
-        const uint32_t e = valid ? cand[i] : 0u;
-        const uint32_t q = valid ? tl[i] : 0u;
-        const uint32_t eq = valid ? cand[q] : 0u;
         const int w = valid ? ce_w(e) : 0;
         const int wq = valid ? ce_w(eq) : 0;
         const int a = ce_a(e), b = ce_b(eq);
@@ -1739,7 +1800,6 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
             tinv[q] = (twin_prev ? i - 1 : i) | (twin_prev || twin_next ? (int)0x80000000u : 0);
         }
         const int word = 2 * (cb / kWave);
-        const int ks = plane_stride(K);
         // Lanes 0 and 1 store the low and high halves of four planes' ballots
         // at a time (one 16-byte store per ordering).
         for (int k = 0; k < ks; k += 4) {
@@ -1755,11 +1815,23 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
                 *(uint4*)(pl + ks * pw + (word + l) * ks + k) = make_uint4(t4[0], t4[1], t4[2], t4[3]);
             }
         }
+    };
+    // Two chunks per wave and iteration: their loads (the candidates, the
+    // second ordering and its candidates, a dependent gather) are all in
+    // flight before either chunk is processed.
+    for (int base = 0; base < m; base += 2 * kWave * NW) {
+        const int cb0 = base + kWave * grp_wave(), cb1 = cb0 + kWave * NW;
+        const int i0 = cb0 + l, i1 = cb1 + l;
+        const bool v0 = i0 < m, v1 = i1 < m;
+        const uint32_t e0 = v0 ? cand[i0] : 0u, q0 = v0 ? tl[i0] : 0u;
+        const uint32_t e1 = v1 ? cand[i1] : 0u, q1 = v1 ? tl[i1] : 0u;
+        const uint32_t eq0 = v0 ? cand[q0] : 0u, eq1 = v1 ? cand[q1] : 0u;
+        if (cb0 < m) chunk(cb0, e0, q0, eq0);
+        if (cb1 < m) chunk(cb1, e1, q1, eq1);
     }
     __syncthreads();
     // S_v: the profit of the candidates holding live variable v, its pairs
     // (v, y) (canonical range) and (x, v) (range of the second ordering).
-    const int ks = plane_stride(K);
     for (int v = grp_tid(); v < n_live; v += kWave * NW) {
         const int4 r = *(const int4*)(rng + 4 * v);
         ssum[v] = plane_sum(pl, ks, r.x, r.y) + plane_sum(pl + ks * pw, ks, r.z, r.w);
@@ -1817,10 +1889,8 @@ __device__ __forceinline__ int select_gi_planes_grp(const uint32_t* cand, int m,
         co.first_block();
         if ((ra.w - ra.z) + (ra.y - ra.x - 1) + (rb.w - rb.z - n_ab) + (rb.y - rb.x) > 128) co.next_block();
         plane_window_x(plt, ks, ra.z, ra.w, j, co, X);
-        plane_window_x(plc, ks, ra.x, p, j, co, X);
-        plane_window_x(plc, ks, p + 1, ra.y, j, co, X);
-        plane_window_x(plt, ks, rb.z, t_ab, j, co, X);
-        plane_window_x(plt, ks, t_ab + n_ab, rb.w, j, co, X);
+        plane_window_x_gap(plc, ks, ra.x, ra.y, p, 1, j, co, X);
+        plane_window_x_gap(plt, ks, rb.z, rb.w, t_ab, n_ab, j, co, X);
         plane_window_x(plc, ks, rb.x, rb.y, j, co, X);
         const long long D = (long long)T - wp - I;
         const long long hsc = ((long long)wp << 32) + (long long)aq * ((D << 16) + (long long)bq * X);
