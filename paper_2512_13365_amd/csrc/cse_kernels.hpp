@@ -857,23 +857,17 @@ struct CoinStream {
             has_nb = true;
         }
     }
-    // Word u (coins 32u .. 32u + 31); u never decreases between calls by more
-    // than stays within the held blocks.
-    __device__ uint32_t word(int u) {
-        const int blk = u >> 2;
-        if (blk != cb) {
-            if (blk == cb + 1) {
-                next_block();
-                a0 = b0; a1 = b1; a2 = b2; a3 = b3;
-            } else {
-                const U4 x = philox10(proc, dw, kp, (uint32_t)blk | eh, k0, k1);
-                a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
-            }
-            cb = blk;
-            has_nb = false;
+    // Make block blk the held one (blk never below the held block).
+    __device__ __forceinline__ void hold(int blk) {
+        if (blk == cb + 1) {
+            next_block();
+            a0 = b0; a1 = b1; a2 = b2; a3 = b3;
+        } else {
+            const U4 x = philox10(proc, dw, kp, (uint32_t)blk | eh, k0, k1);
+            a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
         }
-        const int s = u & 3;
-        return s == 0 ? a0 : s == 1 ? a1 : s == 2 ? a2 : a3;
+        cb = blk;
+        has_nb = false;
     }
     // Block 0 drawn now, by every lane at once (a stream's first block is
     // nearly always needed; drawn lazily it would run once per lane group
@@ -886,18 +880,16 @@ struct CoinStream {
     }
     // Coins j .. j + n - 1 in bits 0 .. n - 1 (1 <= n <= 32; higher bits
     // unspecified).  A block is drawn only if one of these coins is in it.
+    // The words are picked by selects, not branches: only a block draw
+    // branches.
     __device__ uint32_t bits(int j, int n) {
-        const int u = j >> 5, sh = j & 31;
-        const uint32_t w0 = word(u);
-        if (sh + n <= 32) return w0 >> sh;
-        uint32_t w1;
-        if ((u & 3) != 3) {
-            const int s = (u & 3) + 1;
-            w1 = s == 1 ? a1 : s == 2 ? a2 : a3;
-        } else {
-            next_block();
-            w1 = b0;
-        }
+        const int u = j >> 5, sh = j & 31, s = u & 3;
+        if ((u >> 2) != cb) hold(u >> 2);
+        if (s == 3 && sh + n > 32) next_block();
+        const bool odd = (s & 1) != 0, high = (s & 2) != 0;
+        const uint32_t x0 = a0, x1 = a1, x2 = a2, x3 = a3, x4 = b0;
+        const uint32_t lo0 = odd ? x1 : x0, hi0 = odd ? x3 : x2, lo1 = odd ? x2 : x1, hi1 = odd ? x4 : x3;
+        const uint32_t w0 = high ? hi0 : lo0, w1 = high ? hi1 : lo1;
         return __builtin_amdgcn_alignbit(w1, w0, (uint32_t)sh);
     }
 };
