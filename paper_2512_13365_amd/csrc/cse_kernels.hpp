@@ -894,6 +894,11 @@ struct CoinStream {
     }
 };
 
+// Bits sh .. sh + n - 1 of a word (0 <= sh <= 31, 1 <= n <= 32 - sh).
+__device__ __forceinline__ uint32_t window_bits(int sh, int n) {
+    return (0xFFFFFFFFu << sh) & (0xFFFFFFFFu >> (32 - sh - n));
+}
+
 // Weighted coin sum over a contiguous range [pos, end) of one ordering whose
 // candidates take the consecutive coins j, j + 1, ...: I += sum of c - 1,
 // X += sum of c - 1 over coin 1, 32 candidates per plane word; the planes
@@ -904,7 +909,7 @@ __device__ __forceinline__ void plane_window(const uint32_t* pl, int ks, int ku,
     while (pos < end) {
         const int sh = pos & 31;
         const int n = min(32 - sh, end - pos);
-        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint32_t msk = window_bits(sh, n);
         const uint32_t cw = co.bits(j, n) << sh;
         const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
         for (int g = 0; g < ku; g += 4) {
@@ -924,7 +929,7 @@ __device__ __forceinline__ void plane_window_x(const uint32_t* pl, int ks, int p
     while (pos < end) {
         const int sh = pos & 31;
         const int n = min(32 - sh, end - pos);
-        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint32_t msk = window_bits(sh, n);
         const uint32_t mc = (co.bits(j, n) << sh) & msk;
         const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
         for (int g = 0; g < ks; g += 4) {
@@ -937,8 +942,6 @@ __device__ __forceinline__ void plane_window_x(const uint32_t* pl, int ks, int p
     }
 }
 
-// Bits 0 .. k - 1 of a word (0 <= k <= 32).
-__device__ __forceinline__ uint32_t low_bits(int k) { return k >= 32 ? 0xFFFFFFFFu : (1u << k) - 1u; }
 
 // The window [pos, end) of one ordering less the gap [s0, s0 + ns) inside it
 // (the scored candidate, or the pair's one or two entries): the coins run on
@@ -959,9 +962,13 @@ __device__ __forceinline__ GapWord gap_word(int pos, int end, int s0, int ns, in
     const int gl = min(max(s0 - wb, sh), sh + g.n), gh = min(max(s0 + ns - wb, sh), sh + g.n);
     const int e = gh - gl;
     g.nc = g.n - e;
-    g.msk = ((g.n == 32 ? 0xFFFFFFFFu : ((1u << g.n) - 1u)) << sh) & ~(low_bits(gh) & ~low_bits(gl));
+    // gl is 32 only with an empty gap (e = 0), where the shifts below (taken
+    // mod 32) give no gap bits and the same coin word on both sides.
+    const int gs = gl & 31;
+    g.msk = window_bits(sh, g.n) & ~(((1u << e) - 1u) << gs);
     const uint32_t cc = (g.nc > 0 ? co.bits(j, g.nc) : 0u) << sh;
-    g.mc = ((cc & low_bits(gl)) | ((cc << e) & ~low_bits(gh))) & g.msk;
+    const uint32_t below = (1u << gs) - 1u;
+    g.mc = ((cc & below) | ((cc << e) & ~below)) & g.msk;
     return g;
 }
 
@@ -1006,7 +1013,7 @@ __device__ __forceinline__ int plane_sum(const uint32_t* pl, int ks, int pos, in
     while (pos < end) {
         const int sh = pos & 31;
         const int n = min(32 - sh, end - pos);
-        const uint32_t msk = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+        const uint32_t msk = window_bits(sh, n);
         const uint4* q = (const uint4*)(pl + (pos >> 5) * ks);
         for (int g = 0; g < ks; g += 4) {
             const uint4 v = q[g >> 2];
@@ -1758,26 +1765,29 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
     __syncthreads();
     const int ks = plane_stride(K);
     // One chunk of 64 candidates of the canonical list (e) and the second
-    // ordering (q, its candidate eq) at positions cb + lane.
-    auto chunk = [&](const int cb, const uint32_t e, const uint32_t q, const uint32_t eq) {
+    // ordering (q, its candidate eq) at positions cb + lane; lanes 0 and 63
+    // also hold the entries just outside the chunk in both orderings (ex,
+    // exq), at x = cb - 1 and cb + 64 when those exist.
+    auto chunk = [&](const int cb, const uint32_t e, const uint32_t q, const uint32_t eq, const int x,
+                     const uint32_t ex, const uint32_t exq) {
         const int i = cb + l;
         const bool valid = i < m;
         const int w = valid ? ce_w(e) : 0;
         const int wq = valid ? ce_w(eq) : 0;
         const int a = ce_a(e), b = ce_b(eq);
-        // Neighbours in each ordering (other lanes of the chunk, or memory
-        // at its edges): first variables of the canonical list, pairs of
-        // the second ordering (for b's range and the twin test).
+        // Neighbours in each ordering (other lanes of the chunk, or the
+        // entries at its edges): first variables of the canonical list,
+        // pairs of the second ordering (for b's range and the twin test).
         const uint32_t pq = valid ? ce_pair(eq) : 0u;
         int pa = __shfl_up(a, 1), na = __shfl_down(a, 1);
         uint32_t pp = __shfl_up(pq, 1), pn = __shfl_down(pq, 1);
         if (l == 0) {
-            pa = i > 0 && valid ? ce_a(cand[i - 1]) : -1;
-            pp = i > 0 && valid ? ce_pair(cand[tl[i - 1]]) : 0u;
+            pa = x >= 0 && valid ? ce_a(ex) : -1;
+            pp = x >= 0 && valid ? ce_pair(exq) : 0u;
         }
         if (l == kWave - 1 || i + 1 >= m) {
-            na = i + 1 < m ? ce_a(cand[i + 1]) : -1;
-            pn = i + 1 < m ? ce_pair(cand[tl[i + 1]]) : 0u;
+            na = x >= 0 && l == kWave - 1 ? ce_a(ex) : -1;
+            pn = x >= 0 && l == kWave - 1 ? ce_pair(exq) : 0u;
         }
         if (valid) {
             const int va = vpos[a - 1], vb = vpos[b - 1];
@@ -1809,17 +1819,26 @@ __device__ __forceinline__ void gi_prepare_grp(const uint32_t* cand, const uint3
         }
     };
     // Two chunks per wave and iteration: their loads (the candidates, the
-    // second ordering and its candidates, a dependent gather) are all in
-    // flight before either chunk is processed.
+    // second ordering and its candidates, a dependent gather, the same for
+    // the entries at the chunks' edges) are all in flight before either
+    // chunk is processed.
+    auto edge = [&](const int i) {  // cb - 1 for lane 0, cb + 64 for lane 63
+        const int x = l == 0 ? i - 1 : l == kWave - 1 ? i + 1 : -1;
+        return x >= 0 && x < m ? x : -1;
+    };
     for (int base = 0; base < m; base += 2 * kWave * NW) {
         const int cb0 = base + kWave * grp_wave(), cb1 = cb0 + kWave * NW;
         const int i0 = cb0 + l, i1 = cb1 + l;
         const bool v0 = i0 < m, v1 = i1 < m;
+        const int x0 = edge(i0), x1 = edge(i1);
         const uint32_t e0 = v0 ? cand[i0] : 0u, q0 = v0 ? tl[i0] : 0u;
         const uint32_t e1 = v1 ? cand[i1] : 0u, q1 = v1 ? tl[i1] : 0u;
+        const uint32_t ex0 = x0 >= 0 ? cand[x0] : 0u, tx0 = x0 >= 0 ? tl[x0] : 0u;
+        const uint32_t ex1 = x1 >= 0 ? cand[x1] : 0u, tx1 = x1 >= 0 ? tl[x1] : 0u;
         const uint32_t eq0 = v0 ? cand[q0] : 0u, eq1 = v1 ? cand[q1] : 0u;
-        if (cb0 < m) chunk(cb0, e0, q0, eq0);
-        if (cb1 < m) chunk(cb1, e1, q1, eq1);
+        const uint32_t exq0 = x0 >= 0 ? cand[tx0] : 0u, exq1 = x1 >= 0 ? cand[tx1] : 0u;
+        if (cb0 < m) chunk(cb0, e0, q0, eq0, x0, ex0, exq0);
+        if (cb1 < m) chunk(cb1, e1, q1, eq1, x1, ex1, exq1);
     }
     __syncthreads();
     // S_v: the profit of the candidates holding live variable v, its pairs
