@@ -600,6 +600,45 @@ def test_range_form_wide_weights(gpu, oracle):
     cse.cse_scheme_free(ctx, sid)
 
 
+def test_range_form_gaps_at_word_edges(gpu, oracle):
+    """Greedy-Intersections (Sec. 3.4.2) in the range form reads p's canonical
+    range less p, and b's range of the second ordering less the pair's one or
+    two entries, as windows with a gap over 32-candidate plane words.  On a
+    45 x 150 system of the batch's W^T shape (4490 candidates at the first
+    step) twin pairs (a, b, +-) straddle a word boundary in both orderings, so
+    gaps of two entries split across two words and gaps at a word's first or
+    last bit all occur; every range layout reproduces the oracle's gi-only
+    runs."""
+    from cse_helpers import pair_counts
+    cse, ctx, torch = gpu
+    A = workloads.random_system(7000, 45, 150, 0.2)
+    pc = pair_counts(A)
+    canon = sorted(k for k, c in pc.items() if c >= 2)
+    second = sorted(canon, key=lambda t: (t[1], t[0], t[2]))
+    def straddling(lst):
+        return [i for i in range(31, len(lst) - 1, 32) if lst[i][:2] == lst[i + 1][:2]]
+    assert len(canon) == 4490
+    assert straddling(canon) and straddling(second), "the input no longer holds both word-edge cases"
+    kw = dict(seed=5, n_proc=32, weights={"gi": 1}, proc0_greedy=False, step_cap=8)
+    ref = compare(oracle, [A], kw, "gaps at word edges")[0]
+    sid = cse.cse_system_load(ctx, A)
+    W2, W4 = cse.CSE_LAYOUT_WAVES2, cse.CSE_LAYOUT_WAVES4
+    tried = []
+    for lay in (2, 3, 7, 2 | W4, 3 | W2, 3 | W4, 7 | W4):
+        try:
+            cse.cse_scheme_layout(ctx, sid, 0, lay)
+        except cse.CseError as e:  # unit state or full tables that do not fit LDS
+            assert "CSE_ENOMEM" in str(e) and (not lay & cse.CSE_LAYOUT_HBM or lay & cse.CSE_LAYOUT_LDS_TABLES)
+            continue
+        say(f"[gpu] gaps at word edges: layout {lay}")
+        job, got = run_loaded(gpu, sid, kw)
+        cse.cse_job_release(ctx, job)
+        assert_same(got, ref, f"gaps at word edges, layout {lay}")
+        tried.append(lay)
+    assert {3, 3 | W2, 3 | W4} <= set(tried)
+    cse.cse_scheme_free(ctx, sid)
+
+
 def test_server_cancel_queued_and_running(gpu, oracle):
     """A queued server job cancelled before admission never runs; a running
     one stops at the end of its round and keeps prefixes of the oracle's runs;
