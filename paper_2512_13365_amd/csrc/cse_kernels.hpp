@@ -2433,13 +2433,13 @@ __device__ __forceinline__ void step_body(const Segment* __restrict__ segs, int 
 // the process draw.  gp units (any_gp: some job of the launch weights gp)
 // thus share the launch with the others, while each body is compiled on its
 // own.
-// Units of several waves are held to 80 registers (six waves per SIMD),
-// about their natural need; at 64 (eight waves) the spills cost more than
-// the two extra waves hide (batch pass 1.70 s at eight, 1.60 s at six or
-// seven, 1.71 s at five; the 6x6x6 job 93, 81, 77 and 81 ms at eight,
-// seven, six and five).
+// Units of several waves are held to 72 registers (seven waves per SIMD), a
+// few spills below their natural need: the extra wave hides more memory
+// latency than the spills cost (batch pass 1.217 s at seven, 1.254 s at
+// six, 1.338 s at eight; the 6x6x6 job 66.0, 68.6 and 83.9 ms), while at 64
+// registers (eight) the spills dominate.
 template <int W, bool GS, bool ADJ, bool TL, int NW>
-__global__ __launch_bounds__((kWave * NW), (NW > 1 ? 6 : 1)) void step_kernel(
+__global__ __launch_bounds__((kWave * NW), (NW > 1 ? 7 : 1)) void step_kernel(
     const Segment* __restrict__ segs, int n_segs, const uint32_t* __restrict__ order, uint32_t n_grid, int* err,
     int any_gp) {
     step_body<W, GS, ADJ, TL, false, NW>(segs, n_segs, order, n_grid, err);
